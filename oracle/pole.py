@@ -1,0 +1,111 @@
+"""Pole-expansion route to G and N (test infrastructure only).
+
+Sec. 3.3 of the paper (eqs. pseudo_H_k and rho_LDA+DMFT_componet_final): when
+the local self-energy has the pole form of Sec. 3.2.4 eq. se_pole,
+
+    Sigma(i w) = Sigma_inf + sum_i V_i^dag (i w - p_i)^{-1} V_i ,
+
+the band-window resolvent is the physical block of the resolvent of an
+enlarged Hermitian "pseudo-Hamiltonian".  Written relative to the chemical
+potential (mu enters the physical block only, because Sigma(i w) does not move
+with mu):
+
+    Htil_k = [[ M1_k,        W_k^dag        ],
+              [ W_k,   diag(p_i) (poles)    ]],
+    M1_k   = diag(E_k) - mu + S_k^dag (Sigma_inf - diag(V_DC)) S_k,
+    W_k    = rows V_i S_k  (one row per pole),
+
+    G_k(i w) = [ (i w - Htil_k)^{-1} ]_phys = sum_l u_l u_l^dag / (i w - lam_l)
+    N_k      = sum_l u_l u_l^dag n_F(lam_l)                    (exact, no frequency sum)
+
+with Htil_k = U diag(lam) U^dag and u_l the physical (band-window) part of
+column l of U.  The eigen-decomposition is numpy's ``eigh`` (a library
+routine).  This route shares nothing with the Matsubara-sum oracle in
+``dmft_oracle.c``; the tests use it to pin that oracle.
+
+``truncated_fermi`` is the scalar that the positive-frequency sum with the
+analytic 1/(iw) and 1/(iw)^2 tails gives for one level at energy lam:
+
+    f_Nw(lam) = 1/2 - beta lam / 4 + (2/beta) sum_{n<Nw} lam^3 / (w_n^2 (w_n^2 + lam^2)),
+
+obtained by pairing 1/(i w_n - lam) with its n -> -n-1 partner
+(1/(iw - lam) + 1/(-iw - lam) = -2 lam / (w^2 + lam^2)) and adding
+2 lam / w_n^2; f_Nw -> n_F(lam) as Nw -> infinity (the classic identity
+n_F(lam) = 1/2 - (2/beta) sum_{n>=0} lam / (w_n^2 + lam^2) with
+sum_{n>=0} 1/w_n^2 = beta^2/8).  Because the first moment of the physical
+block is exactly M1_k, the truncated Matsubara density of the oracle equals
+sum_l u_l u_l^dag f_Nw(lam_l) identically, at any Nw.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def fermi(x, beta):
+    """n_F(x) = 1 / (exp(beta x) + 1), evaluated without overflow."""
+    x = np.asarray(x, dtype=np.float64) * beta
+    out = np.empty_like(x)
+    pos = x > 0
+    e = np.exp(-x[pos])
+    out[pos] = e / (1.0 + e)
+    out[~pos] = 1.0 / (1.0 + np.exp(x[~pos]))
+    return out
+
+
+def truncated_fermi(lam, beta, nw):
+    lam = np.asarray(lam, dtype=np.float64)
+    w = (2.0 * np.arange(nw) + 1.0) * np.pi / beta
+    l3 = lam[..., None] ** 3
+    s = (l3 / (w ** 2 * (w ** 2 + lam[..., None] ** 2))).sum(axis=-1)
+    return 0.5 - beta * lam / 4.0 + 2.0 * s / beta
+
+
+def pseudo_hamiltonian(eps_k, proj_k, sigma_inf, e_dc, poles, mu):
+    """Htil_k (see module docstring).  ``poles`` is a list of (p_i, V_i[nc])."""
+    nb = eps_k.shape[0]
+    nc = proj_k.shape[0]
+    sinf = np.zeros((nc, nc), np.complex128) if sigma_inf is None else np.asarray(sigma_inf)
+    m1 = np.diag(eps_k - mu).astype(np.complex128) + proj_k.conj().T @ (sinf - np.diag(e_dc)) @ proj_k
+    npl = len(poles)
+    h = np.zeros((nb + npl, nb + npl), np.complex128)
+    h[:nb, :nb] = m1
+    for i, (p, v) in enumerate(poles):
+        row = np.asarray(v, np.complex128) @ proj_k        # V_i S_k : 1 x nb
+        h[nb + i, :nb] = row
+        h[:nb, nb + i] = row.conj()
+        h[nb + i, nb + i] = p
+    return h
+
+
+def _phys_eig(eps_k, proj_k, sigma_inf, e_dc, poles, mu):
+    h = pseudo_hamiltonian(eps_k, proj_k, sigma_inf, e_dc, poles, mu)
+    lam, u = np.linalg.eigh(h)
+    return lam, u[:eps_k.shape[0], :]
+
+
+def exact_density(eps_k, proj_k, sigma_inf, e_dc, poles, mu, beta):
+    """N_k = sum_l u_l u_l^dag n_F(lam_l): the paper's exact pole-route density."""
+    lam, up = _phys_eig(eps_k, proj_k, sigma_inf, e_dc, poles, mu)
+    return (up * fermi(lam, beta)) @ up.conj().T
+
+
+def truncated_density(eps_k, proj_k, sigma_inf, e_dc, poles, mu, beta, nw):
+    """sum_l u_l u_l^dag f_Nw(lam_l): what the positive-frequency Matsubara sum
+    with the analytic tail must return at finite Nw."""
+    lam, up = _phys_eig(eps_k, proj_k, sigma_inf, e_dc, poles, mu)
+    return (up * truncated_fermi(lam, beta, nw)) @ up.conj().T
+
+
+def exact_green(eps_k, proj_k, sigma_inf, e_dc, poles, mu, iw):
+    """G_k(i w) = sum_l u_l u_l^dag / (i w - lam_l)."""
+    lam, up = _phys_eig(eps_k, proj_k, sigma_inf, e_dc, poles, mu)
+    return (up / (iw - lam)) @ up.conj().T
+
+
+def exact_ntot(lat, sig, mu):
+    """sum_k w_k tr N_k from the pole route (Sec. 3.3 eq. fix_mu)."""
+    tot = 0.0
+    for k in range(lat.nk):
+        n = exact_density(lat.eps_k(k), lat.proj_k(k), sig.sigma_inf, sig.e_dc, sig.poles, mu, sig.beta)
+        tot += lat.wk[k] * np.trace(n).real
+    return tot

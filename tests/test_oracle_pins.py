@@ -1,0 +1,457 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests trusts the oracle's own formulas: each compares it with an
+independent route (library inverse, the paper's pole-expansion /
+pseudo-Hamiltonian density, closed forms, brute-force two-sided sums, finite
+differences, algebraic identities, symmetries).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pole
+from paper_1111_2157_amd import synth
+
+RTOL = 1e-11
+
+
+def small_plain(nk=4, nb=7, nc=3, nw=48, beta=10.0, seed=1):
+    return synth.plain(seed=seed, nk=nk, nb=nb, nc=nc, nw=nw, beta=beta)
+
+
+def small_dshell(nk=3, nb=12, nc=10, nw=40, beta=8.0, seed=2):
+    return synth.d_shell(seed=seed, nk=nk, nb=nb, nc=nc, nw=nw, beta=beta, n_narrow=4)
+
+
+def small_fshell(nk=3, nb=16, nc=14, nw=40, beta=12.0, seed=3):
+    return synth.f_shell(seed=seed, nk=nk, nb=nb, nc=nc, nw=nw, beta=beta, n_narrow=5)
+
+
+def small_ragged(nk=5, nw=40, beta=9.0, seed=4):
+    wl = synth.batched(seed=seed, nk=nk, nb_lo=14, nb_hi=22, nw=nw, beta=beta, n_iter=2, n_narrow=4)
+    return wl
+
+
+def relnorm(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+def m1_of(lat, sig, k, mu):
+    p = lat.proj_k(k)
+    nc = lat.nc
+    sinf = np.zeros((nc, nc)) if sig.sigma_inf is None else sig.sigma_inf
+    return np.diag(lat.eps_k(k) - mu) + p.conj().T @ (sinf - np.diag(sig.e_dc)) @ p
+
+
+def wgrid(nw, beta):
+    return (2.0 * np.arange(nw) + 1.0) * np.pi / beta
+
+
+# ----------------------------------------------------------------------------- inverse
+
+@pytest.mark.parametrize("n", [1, 5, 12, 17])
+def test_invert_matches_library(n):
+    rng = np.random.default_rng(n)
+    h = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    a = h + 1j * (n + 1.0) * np.eye(n)
+    g = oracle.invert(a)
+    assert relnorm(g, np.linalg.inv(a)) < 1e-13
+
+
+def test_invert_needs_pivoting():
+    a = np.array([[0.0, 2.0, 1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 3.0j]], np.complex128)
+    assert relnorm(oracle.invert(a), np.linalg.inv(a)) < 1e-14
+
+
+def test_invert_singular_raises():
+    with pytest.raises(ZeroDivisionError):
+        oracle.invert(np.zeros((3, 3), np.complex128))
+
+
+# ------------------------------------------------------------------- Sigma = 0: Fermi sum
+
+def zero_sigma(sig):
+    return synth.SelfEnergy(sig.nw, sig.beta, np.zeros_like(sig.sigma), None, sig.e_dc.copy(), [])
+
+
+def test_truncated_fermi_converges_to_fermi():
+    beta = 20.0
+    lam = np.array([-3.0, -0.7, -0.05, 0.0, 0.2, 1.3, 4.0])
+    for nw in (256, 1024, 4096):
+        f = pole.truncated_fermi(lam, beta, nw)
+        bound = beta ** 3 * np.abs(lam) ** 3 / (24 * np.pi ** 4 * nw ** 3)
+        err = np.abs(f - pole.fermi(lam, beta))
+        assert np.all(err <= 1.05 * bound + 1e-15)
+    # the leading remainder has the predicted size: xi = 1.3, beta = 20, Nw = 256
+    f = pole.truncated_fermi(np.array([1.3]), 20.0, 256)
+    pred = -(20.0 ** 3) * 1.3 ** 3 / (24 * np.pi ** 4 * 256 ** 3)
+    assert abs((f - pole.fermi(np.array([1.3]), 20.0))[0] - pred) < 0.02 * abs(pred)
+
+
+@pytest.mark.parametrize("nw", [48, 600])
+def test_sigma_zero_gives_fermi_function(nw):
+    wl = small_plain(nw=nw)
+    lat, sig = wl.lattice, zero_sigma(wl.sigma)
+    sig.nw = nw
+    sig.sigma = np.zeros((nw, lat.nc, lat.nc), np.complex128)
+    mu = -0.4
+    mats, ntr = oracle.density(lat, sig, mu)
+    for k in range(lat.nk):
+        p = lat.proj_k(k)
+        h = np.diag(lat.eps_k(k)) - p.conj().T @ np.diag(sig.e_dc) @ p - mu * np.eye(lat.nb[k])
+        lam, u = np.linalg.eigh(h)
+        ref = (u * pole.truncated_fermi(lam, sig.beta, nw)) @ u.conj().T
+        assert relnorm(mats[k], ref) < RTOL
+        exact = (u * pole.fermi(lam, sig.beta)) @ u.conj().T
+        bound = sig.beta ** 3 * np.max(np.abs(lam)) ** 3 / (24 * np.pi ** 4 * nw ** 3)
+        assert np.max(np.abs(mats[k] - exact)) <= lat.nb[k] * bound + 1e-13
+        assert abs(ntr[k] - np.trace(mats[k]).real) < 1e-12
+
+
+def test_sigma_zero_large_nw_exact():
+    wl = small_plain(nk=2, nb=5, nc=2, beta=4.0)
+    lat = wl.lattice
+    nw = 65536
+    sig = synth.SelfEnergy(nw, 4.0, np.zeros((nw, 2, 2), np.complex128), None, wl.sigma.e_dc.copy(), [])
+    mats, _ = oracle.density(lat, sig, 0.3)
+    for k in range(lat.nk):
+        p = lat.proj_k(k)
+        h = np.diag(lat.eps_k(k)) - p.conj().T @ np.diag(sig.e_dc) @ p - 0.3 * np.eye(5)
+        lam, u = np.linalg.eigh(h)
+        exact = (u * pole.fermi(lam, 4.0)) @ u.conj().T
+        assert np.max(np.abs(mats[k] - exact)) < 1e-11
+
+
+# ------------------------------------------------------------ pole route (paper Sec. 3.3)
+
+@pytest.mark.parametrize("maker", [small_plain, small_dshell, small_fshell])
+def test_green_equals_pseudo_hamiltonian_resolvent(maker):
+    wl = maker()
+    lat, sig = wl.lattice, wl.sigma
+    mu = 0.37
+    w = wgrid(sig.nw, sig.beta)
+    for k in range(lat.nk):
+        for n in (0, 1, sig.nw // 2, sig.nw - 1):
+            g = oracle.green(lat, sig, mu, k, n)
+            ref = pole.exact_green(lat.eps_k(k), lat.proj_k(k), sig.sigma_inf, sig.e_dc, sig.poles,
+                                   mu, 1j * w[n])
+            assert relnorm(g, ref) < 1e-12
+
+
+@pytest.mark.parametrize("maker", [small_plain, small_dshell, small_fshell])
+def test_density_equals_pole_route_at_finite_nw(maker):
+    wl = maker()
+    lat, sig = wl.lattice, wl.sigma
+    mu = -0.6
+    mats, _ = oracle.density(lat, sig, mu)
+    for k in range(lat.nk):
+        ref = pole.truncated_density(lat.eps_k(k), lat.proj_k(k), sig.sigma_inf, sig.e_dc, sig.poles,
+                                     mu, sig.beta, sig.nw)
+        assert relnorm(mats[k], ref) < RTOL
+
+
+def test_density_ragged_equals_pole_route():
+    wl = small_ragged()
+    for lat, sig in zip(wl.lattices, wl.sigmas):
+        mats, _ = oracle.density(lat, sig, 0.1)
+        assert len(set(lat.nb.tolist())) > 1
+        for k in range(lat.nk):
+            ref = pole.truncated_density(lat.eps_k(k), lat.proj_k(k), sig.sigma_inf, sig.e_dc,
+                                         sig.poles, 0.1, sig.beta, sig.nw)
+            assert relnorm(mats[k], ref) < RTOL
+
+
+def test_density_converges_to_exact_as_nw_cubed():
+    errs = []
+    for nw in (64, 128, 256):
+        wl = small_plain(nk=2, nb=6, nc=2, nw=nw, beta=10.0)
+        lat, sig = wl.lattice, wl.sigma
+        mats, _ = oracle.density(lat, sig, 0.2)
+        e = 0.0
+        for k in range(lat.nk):
+            ex = pole.exact_density(lat.eps_k(k), lat.proj_k(k), sig.sigma_inf, sig.e_dc, sig.poles,
+                                    0.2, sig.beta)
+            e = max(e, np.max(np.abs(mats[k] - ex)))
+        errs.append(e)
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 6.5 < r1 < 9.5 and 6.5 < r2 < 9.5, errs
+
+
+def test_one_level_closed_form():
+    # one band, one orbital, S = [[1]], Sigma = a/(iw - p): the two poles of G
+    eps, mu, a, p, beta, nw = 0.8, 0.25, 2.0, -0.5, 7.0, 300
+    lat = synth.Lattice(1, 1, np.array([1], np.int32), np.array([eps]), np.array([1.0]),
+                        np.array([1.0 + 0j]))
+    w = wgrid(nw, beta)
+    sig = synth.SelfEnergy(nw, beta, (a / (1j * w - p)).reshape(nw, 1, 1).astype(np.complex128), None,
+                           np.zeros(1), [(p, np.array([np.sqrt(a)]))])
+    mats, _ = oracle.density(lat, sig, mu)
+    e = eps - mu
+    root = np.sqrt((e - p) ** 2 + 4 * a)
+    zp, zm = (e + p + root) / 2, (e + p - root) / 2
+    wp, wm = (zp - p) / (zp - zm), (zm - p) / (zm - zp)
+    trunc = wp * pole.truncated_fermi(np.array([zp]), beta, nw) + wm * pole.truncated_fermi(np.array([zm]), beta, nw)
+    assert abs(mats[0][0, 0].real - trunc[0]) < 1e-13
+    assert abs(mats[0][0, 0].imag) < 1e-15
+    exact = wp * pole.fermi(np.array([zp]), beta) + wm * pole.fermi(np.array([zm]), beta)
+    bound = beta ** 3 * max(abs(zp), abs(zm)) ** 3 / (24 * np.pi ** 4 * nw ** 3)
+    assert abs(mats[0][0, 0].real - exact[0]) <= bound
+
+
+# ------------------------------------------------------- brute force, both signs of n
+
+def two_sided_density(lat, sig, k, mu, dps=None):
+    """(1/beta) sum over n = -Nw..Nw-1 of [G(i w_n) + M1/w_n^2] + 1/2 - beta M1/4,
+    with G at negative frequencies from its own inverse (Sigma(-iw) = Sigma(iw)^dag)."""
+    nb, nc = int(lat.nb[k]), lat.nc
+    p = lat.proj_k(k)
+    m1 = m1_of(lat, sig, k, mu)
+    w = wgrid(sig.nw, sig.beta)
+    if dps is None:
+        acc = np.zeros((nb, nb), np.complex128)
+        for n in range(sig.nw):
+            for s in (+1, -1):
+                sn = sig.sigma[n] if s > 0 else sig.sigma[n].conj().T
+                a = (1j * s * w[n] + mu) * np.eye(nb) - np.diag(lat.eps_k(k)) - p.conj().T @ (sn - np.diag(sig.e_dc)) @ p
+                acc += np.linalg.inv(a) + m1 / w[n] ** 2
+        return 0.5 * np.eye(nb) - sig.beta * m1 / 4 + acc / sig.beta
+    import mpmath as mp
+    mp.mp.dps = dps
+    beta = mp.mpf(sig.beta)
+    P = mp.matrix([[mp.mpc(complex(x)) for x in row] for row in p])
+    Pd = P.H
+    M1 = mp.matrix([[mp.mpc(complex(x)) for x in row] for row in m1])
+    acc = mp.zeros(nb, nb)
+    for n in range(sig.nw):
+        wn = (2 * n + 1) * mp.pi / beta
+        for s in (+1, -1):
+            sn = sig.sigma[n] if s > 0 else sig.sigma[n].conj().T
+            S = mp.matrix([[mp.mpc(complex(x)) for x in row] for row in (sn - np.diag(sig.e_dc))])
+            A = (mp.mpc(0, s * wn) + mp.mpf(mu)) * mp.eye(nb) - mp.diag([mp.mpf(x) for x in lat.eps_k(k)]) - Pd * S * P
+            acc += A ** -1 + M1 / wn ** 2
+    res = mp.eye(nb) * mp.mpf("0.5") - M1 * (beta / 4) + acc / beta
+    return np.array([[complex(res[i, j]) for j in range(nb)] for i in range(nb)])
+
+
+@pytest.mark.parametrize("maker", [small_plain, small_dshell])
+def test_two_sided_brute_force(maker):
+    wl = maker()
+    lat, sig = wl.lattice, wl.sigma
+    mu = 0.15
+    mats, _ = oracle.density(lat, sig, mu)
+    for k in range(lat.nk):
+        assert relnorm(mats[k], two_sided_density(lat, sig, k, mu)) < 1e-12
+
+
+def test_two_sided_brute_force_mpmath():
+    wl = synth.plain(seed=5, nk=1, nb=3, nc=2, nw=24, beta=6.0)
+    lat, sig = wl.lattice, wl.sigma
+    mats, _ = oracle.density(lat, sig, -0.2)
+    ref = two_sided_density(lat, sig, 0, -0.2, dps=40)
+    assert relnorm(mats[0], ref) < 1e-13
+
+
+# ---------------------------------------------------------- consistency of G_loc and N_k
+
+@pytest.mark.parametrize("maker", [small_plain, small_fshell])
+def test_charge_consistency_between_gloc_and_nk(maker):
+    wl = maker()
+    lat, sig = wl.lattice, wl.sigma
+    mu = 0.05
+    mats, _ = oracle.density(lat, sig, mu)
+    gl = oracle.gloc(lat, sig, mu)
+    nc = lat.nc
+    lhs = np.zeros((nc, nc), np.complex128)
+    q = np.zeros((nc, nc), np.complex128)
+    for k in range(lat.nk):
+        p = lat.proj_k(k)
+        lhs += lat.wk[k] * p @ mats[k] @ p.conj().T
+        q += lat.wk[k] * p @ m1_of(lat, sig, k, mu) @ p.conj().T
+    w = wgrid(sig.nw, sig.beta)
+    s = sum(gl[n] + gl[n].conj().T + 2 * q / w[n] ** 2 for n in range(sig.nw))
+    rhs = 0.5 * np.eye(nc) - sig.beta * q / 4 + s / sig.beta
+    assert relnorm(lhs, rhs) < 1e-12
+
+
+def test_gloc_high_frequency_tail():
+    wl = small_plain(nk=3, nb=6, nc=3, nw=4096, beta=20.0)
+    lat, sig = wl.lattice, wl.sigma
+    mu = 0.4
+    w = wgrid(sig.nw, sig.beta)
+    ns = [1023, 4095]
+    gl = oracle.gloc(lat, sig, mu, ns)
+    q = sum(lat.wk[k] * lat.proj_k(k) @ m1_of(lat, sig, k, mu) @ lat.proj_k(k).conj().T
+            for k in range(lat.nk))
+    res = []
+    for i, n in enumerate(ns):
+        iw = 1j * w[n]
+        res.append(np.linalg.norm(iw * gl[i] - np.eye(3) - q / iw))
+        assert np.linalg.norm(iw * gl[i] - np.eye(3)) < 10.0 / w[n]
+    # the remainder after the 1/(iw) term falls as 1/w^2
+    ratio = res[0] / res[1]
+    expect = (w[ns[1]] / w[ns[0]]) ** 2
+    assert 0.8 * expect < ratio < 1.2 * expect
+
+
+def test_gloc_woodbury_route():
+    wl = small_dshell()
+    lat, sig = wl.lattice, wl.sigma
+    mu = -0.3
+    ns = [0, 7, sig.nw - 1]
+    gl = oracle.gloc(lat, sig, mu, ns)
+    w = wgrid(sig.nw, sig.beta)
+    for i, n in enumerate(ns):
+        ref = np.zeros((lat.nc, lat.nc), np.complex128)
+        for k in range(lat.nk):
+            p = lat.proj_k(k)
+            d = 1.0 / (1j * w[n] + mu - lat.eps_k(k))
+            x = (p * d) @ p.conj().T
+            sp = sig.sigma[n] - np.diag(sig.e_dc)
+            ref += lat.wk[k] * np.linalg.inv(np.linalg.inv(x) - sp)
+        assert relnorm(gl[i], ref) < 1e-12
+
+
+def test_nk_hermitian_and_pauli_bounds():
+    wl = small_fshell(nw=256)
+    lat, sig = wl.lattice, wl.sigma
+    mats, ntr = oracle.density(lat, sig, 0.0)
+    for k in range(lat.nk):
+        m = mats[k]
+        assert np.max(np.abs(m - m.conj().T)) < 1e-13
+        ev = np.linalg.eigvalsh(m)
+        assert ev.min() > -1e-3 and ev.max() < 1 + 1e-3
+        assert -1e-3 <= ntr[k] <= lat.nb[k] + 1e-3
+
+
+# ----------------------------------------------------------------------- symmetries
+
+def test_orbital_rotation_invariance():
+    wl = small_dshell()
+    lat, sig = wl.lattice, wl.sigma
+    rng = np.random.default_rng(11)
+    r, _ = np.linalg.qr(rng.standard_normal((lat.nc, lat.nc)) + 1j * rng.standard_normal((lat.nc, lat.nc)))
+    edc = np.full(lat.nc, 7.0)
+    sig0 = synth.SelfEnergy(sig.nw, sig.beta, sig.sigma, sig.sigma_inf, edc, [])
+    projr = np.concatenate([(r @ lat.proj_k(k)).ravel() for k in range(lat.nk)])
+    latr = synth.Lattice(lat.nk, lat.nc, lat.nb, lat.eps, lat.wk, projr)
+    sigr = synth.SelfEnergy(sig.nw, sig.beta, r @ sig.sigma @ r.conj().T, r @ sig.sigma_inf @ r.conj().T, edc, [])
+    mu = 0.2
+    m0, _ = oracle.density(lat, sig0, mu)
+    m1, _ = oracle.density(latr, sigr, mu)
+    for a, b in zip(m0, m1):
+        assert relnorm(b, a) < 1e-12
+    g0 = oracle.gloc(lat, sig0, mu, [0, 5])
+    g1 = oracle.gloc(latr, sigr, mu, [0, 5])
+    for a, b in zip(g0, g1):
+        assert relnorm(b, r @ a @ r.conj().T) < 1e-12
+
+
+def test_band_and_k_permutation():
+    wl = small_plain()
+    lat, sig = wl.lattice, wl.sigma
+    mu = 0.0
+    m0, _ = oracle.density(lat, sig, mu)
+    perm = np.random.default_rng(3).permutation(lat.nb[0])
+    eps = np.concatenate([lat.eps_k(k)[perm] for k in range(lat.nk)])
+    proj = np.concatenate([lat.proj_k(k)[:, perm].ravel() for k in range(lat.nk)])
+    m1, _ = oracle.density(synth.Lattice(lat.nk, lat.nc, lat.nb, eps, lat.wk, proj), sig, mu)
+    for a, b in zip(m0, m1):
+        assert relnorm(b, a[np.ix_(perm, perm)]) < 1e-12
+    kp = np.random.default_rng(4).permutation(lat.nk)
+    g0 = oracle.gloc(lat, sig, mu, [0, 3])
+    g1 = oracle.gloc(lat.subset(kp), sig, mu, [0, 3])
+    assert relnorm(g1, g0) < 1e-13
+
+
+# ----------------------------------------------------------------------- gradients
+
+def grad_case():
+    return synth.f_shell(seed=7, nk=3, nb=6, nc=3, nw=20, beta=6.0, n_narrow=2)
+
+
+def test_dn_dmu_finite_difference():
+    wl = grad_case()
+    lat, sig = wl.lattice, wl.sigma
+    mu, h = 0.3, 1e-6
+    n0, d = oracle.trace(lat, sig, mu)
+    np_, _ = oracle.trace(lat, sig, mu + h)
+    nm, _ = oracle.trace(lat, sig, mu - h)
+    fd = (np_ - nm) / (2 * h)
+    assert d > 0
+    assert abs(fd - d) <= 1e-6 * abs(d)
+    # trace pass agrees with the density pass
+    _, ntr = oracle.density(lat, sig, mu)
+    assert abs(float(np.dot(lat.wk, ntr)) - n0) < 1e-12
+
+
+def test_dn_dsigma_finite_difference():
+    wl = grad_case()
+    lat, sig = wl.lattice, wl.sigma
+    mu, h = 0.3, 1e-6
+    nbar = [lat.wk[k] * np.eye(lat.nb[k]) for k in range(lat.nk)]
+    sbar, mubar = oracle.vjp(lat, sig, mu, nbar=nbar)
+    _, d = oracle.trace(lat, sig, mu)
+    assert abs(mubar - d) < 1e-10 * abs(d)
+    gmax = np.max(np.abs(sbar))
+    for (n, a, b) in [(0, 0, 0), (0, 1, 2), (3, 2, 1), (sig.nw - 1, 1, 1)]:
+        fd = 0j
+        for part, unit in ((0, 1.0), (1, 1j)):
+            vals = []
+            for s in (+1, -1):
+                sg = sig.sigma.copy()
+                sg[n, a, b] += s * h * unit
+                s2 = synth.SelfEnergy(sig.nw, sig.beta, sg, sig.sigma_inf, sig.e_dc, [])
+                vals.append(oracle.trace(lat, s2, mu)[0])
+            fd += unit * (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - sbar[n, a, b]) <= 1e-6 * gmax
+    # closed form (2/beta) [sum_k w_k S G^2 S^dag]^dag
+    for n in (0, 5):
+        ref = np.zeros((lat.nc, lat.nc), np.complex128)
+        for k in range(lat.nk):
+            g = oracle.green(lat, sig, mu, k, n)
+            p = lat.proj_k(k)
+            ref += lat.wk[k] * p @ g @ g @ p.conj().T
+        assert relnorm(sbar[n], (2 / sig.beta) * ref.conj().T) < 1e-12
+
+
+def test_general_vjp_finite_difference():
+    wl = grad_case()
+    lat, sig = wl.lattice, wl.sigma
+    mu, h = -0.2, 1e-6
+    rng = np.random.default_rng(9)
+    nbar = [rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) for n in lat.nb]
+    gbar = rng.standard_normal(sig.sigma.shape) + 1j * rng.standard_normal(sig.sigma.shape)
+
+    def loss(s, m):
+        mats, _ = oracle.density(lat, s, m)
+        g = oracle.gloc(lat, s, m)
+        return sum(np.vdot(nb_, x).real for nb_, x in zip(nbar, mats)) + np.vdot(gbar, g).real
+
+    sbar, mubar = oracle.vjp(lat, sig, mu, nbar=nbar, gbar=gbar)
+    fdmu = (loss(sig, mu + h) - loss(sig, mu - h)) / (2 * h)
+    assert abs(fdmu - mubar) <= 1e-6 * max(1.0, abs(mubar))
+    gmax = np.max(np.abs(sbar))
+    for (n, a, b) in [(0, 0, 1), (2, 2, 2), (sig.nw - 1, 1, 0)]:
+        fd = 0j
+        for unit in (1.0, 1j):
+            vals = []
+            for s in (+1, -1):
+                sg = sig.sigma.copy()
+                sg[n, a, b] += s * h * unit
+                vals.append(loss(synth.SelfEnergy(sig.nw, sig.beta, sg, sig.sigma_inf, sig.e_dc, []), mu))
+            fd += unit * (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - sbar[n, a, b]) <= 1e-6 * gmax
+
+
+# ----------------------------------------------------------------------- mu search
+
+def test_bisection_hits_target():
+    wl = small_plain(nk=4, nb=7, nc=3, nw=64)
+    lat, sig = wl.lattice, wl.sigma
+    n0 = 3.0
+    mu, passes, n = oracle.find_mu_bisect(lat, sig, n0, 1e-8, -40.0, 40.0)
+    assert abs(n - n0) <= 1e-8
+    assert abs(oracle.trace(lat, sig, mu)[0] - n0) <= 1e-8
+    assert passes < 60
+    # the exact (pole-route) electron count at this mu differs only by the truncation
+    assert abs(pole.exact_ntot(lat, sig, mu) - n0) < 5e-3
