@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark of the lattice Dyson step on one MI355X.
+
+A step is one full pass of the hot path over the d-shell workload (Nk=512,
+Nb=32, Nc=10 in two 5-orbital sites, beta=40/eV, Nw=1024 positive Matsubara
+frequencies, complex128): build A(k, i w_n), invert it, project to G_loc,
+Matsubara-sum into N(k) with the analytic tail, and reduce N_tot, n_corr and
+<H_KS> -- i.e. one density_matrix call with every output.  Inputs are seeded
+synthetic arrays resident in HBM before the timed region starts.
+
+The JSON line also carries
+  * "roofline": achieved FP64 rate of the dominant kernel (the Dyson kernel)
+    from its average duration, measured with hipEvents on its own stream
+    inside the timed region, against the MI355X FP64 peak;
+  * "cpu_baseline": the FP64 CPU oracle timed on a bounded sample of the same
+    workload on this host's cores;
+  * "mu_search": Newton (dN/dmu from the adjoint trace pass) against
+    bisection, same kernels, bracket [-40, 40] eV, start at its midpoint,
+    stop at |N - N0| < 1e-8, on the differentiation workload (Nk=1024, Nb=40,
+    Nc=14, beta=50, Nw=2048, N0=20).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6
+
+
+def flops_per_eval(nb, nc):
+    """Algorithmic FP64 flops of one (k, i w_n) evaluation in the dense form:
+    embed S^dag Sigma' S (Nb^2 Nc + Nb Nc^2 complex MACs), invert (Nb^3), project
+    S G S^dag (Nb^2 Nc + Nb Nc^2); 8 real flops per complex multiply-add."""
+    return 8.0 * (nb ** 3 + 2.0 * nb * nb * nc + 2.0 * nb * nc * nc)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mu", action="store_true", help="skip the mu-search comparison")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
+    ap.add_argument("--extra", action="store_true", help="also time the other workloads")
+    return ap.parse_args()
+
+
+def time_density(ctx, lat, sig, mu, steps, warmup, tail=2):
+    import torch
+
+    for _ in range(warmup):
+        ctx.density_matrix(lat, sig, mu, tail)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.density_matrix(lat, sig, mu, tail)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, launches = ctx.timing(False)
+    ctx.sync_status()
+    return (t1 - t0) / steps, kms, launches
+
+
+def cpu_baseline(wl, mu, target_s):
+    import numpy as np
+
+    import oracle
+
+    lat, sig = wl.lattice, wl.sigma
+    cores = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    # calibrate on a few k-points, then size the sample to ~target_s
+    t0 = time.perf_counter()
+    oracle.density(lat, sig, mu, 2, klist=list(range(cores)), nthreads=cores)
+    t_cal = time.perf_counter() - t0
+    nsel = int(max(cores, min(lat.nk, cores * max(1, int(target_s / max(t_cal, 1e-3))))))
+    ks = list(range(nsel))
+    t0 = time.perf_counter()
+    oracle.density(lat, sig, mu, 2, klist=ks, nthreads=cores)
+    t = time.perf_counter() - t0
+    evals = nsel * sig.nw
+    return {"value": evals / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": "N(k) of the first %d of %d k-points over all %d frequencies (%d evals, %.1f s)"
+                      % (nsel, lat.nk, sig.nw, evals, t)}
+
+
+def mu_search(ctx):
+    import torch
+
+    from paper_1111_2157_amd import synth
+    from paper_1111_2157_amd.dyson import BISECT, NEWTON, Lattice, SelfEnergy
+
+    wl = synth.differentiation()
+    lat, sig = Lattice.from_host(wl.lattice), SelfEnergy.from_host(wl.sigma)
+    ctx.dmft_ntot(lat, sig, 0.0)  # warm-up
+    torch.cuda.synchronize()
+    out = {"workload": wl.name, "n_target": wl.n_target, "tol": 1e-8, "bracket": [-40.0, 40.0]}
+    for name, m in (("newton", NEWTON), ("bisect", BISECT)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mu, passes, n = ctx.find_mu(lat, sig, wl.n_target, 1e-8, m, -40.0, 40.0, 0.0, 300)
+        dt = time.perf_counter() - t0
+        out[name] = {"mu": mu, "passes": passes, "N": n, "seconds": dt}
+    out["speedup"] = out["bisect"]["seconds"] / out["newton"]["seconds"]
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; the path shards over k across GPUs "
+              "by design, but multi-GPU runs are not part of it (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1111_2157_amd import synth
+    from paper_1111_2157_amd.dyson import Context, Lattice, SelfEnergy
+
+    wl = synth.d_shell()
+    lat, sig = Lattice.from_host(wl.lattice), SelfEnergy.from_host(wl.sigma)
+    ctx = Context(0)
+    mu = wl.mu
+    sec, kms, launches = time_density(ctx, lat, sig, mu, args.steps, args.warmup)
+    nk, nw, nb, nc = wl.lattice.nk, sig.nw, wl.lattice.nb_max, wl.lattice.nc
+    evals = nk * nw
+    fl = flops_per_eval(nb, nc) * evals
+    kavg = kms / max(launches, 1) / 1e3
+    achieved = fl / kavg / 1e12
+    rec = {
+        "metric": "(k,iw) Dyson evals/s",
+        "value": evals / sec,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "nk": nk, "nb": nb, "nc": nc, "nw": nw, "beta": sig.beta,
+                   "mu": mu, "outputs": "N(k), G_loc, N_tot/n_corr/<H_KS>", "tail_order": 2},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "dyson_kernel<32, density>", "kernel_ms": kavg * 1e3,
+                     "flop_per_eval": flops_per_eval(nb, nc)},
+    }
+    if not args.no_mu:
+        rec["mu_search"] = mu_search(ctx)
+    if args.extra:
+        extra = {}
+        for name, maker in (("plain", synth.plain), ("f-shell", synth.f_shell), ("diff", synth.differentiation)):
+            w = maker()
+            l2, s2 = Lattice.from_host(w.lattice), SelfEnergy.from_host(w.sigma)
+            sc, km, ln = time_density(ctx, l2, s2, w.mu, 3 if name != "plain" else 20, 1)
+            ev = w.lattice.nk * s2.nw
+            f = flops_per_eval(w.lattice.nb_max, w.lattice.nc) * ev
+            extra[w.name] = {"evals_per_s": ev / sc, "ms_per_pass": sc * 1e3,
+                             "kernel_tflops": f / (km / max(ln, 1) / 1e3) / 1e12}
+        rec["extra"] = extra
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(wl, mu, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

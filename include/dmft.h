@@ -1,0 +1,211 @@
+/*
+ * dmft.h - C ABI of the MI355X lattice Dyson library (libdmft.so).
+ *
+ * The library computes the lattice Dyson step of charge-self-consistent
+ * LDA+DMFT (Zhao et al., "Implementation of LDA+DMFT with pseudo-potential-
+ * plane-wave method"), for every k-point of a band window and every positive
+ * fermionic Matsubara frequency w_n = (2n+1) pi / beta, n = 0 .. nw-1:
+ *
+ *   A_kn     = (i w_n + mu) I - diag(E_k) - S_k^dag (Sigma(i w_n) - diag(V_DC)) S_k
+ *                                      (Sec. 3.2.2 eq. dmftloop1 in the band window,
+ *                                       embedding of Sec. 3.2 eq. f_operation,
+ *                                       V_DC sign of Sec. 3.3 eq. rho_LDA+DMFT)
+ *   G_kn     = A_kn^{-1}
+ *   G_loc(n) = sum_k w_k S_k G_kn S_k^dag               (Sec. 3.2.2 eq. dmftloop2)
+ *   M1_k     = diag(E_k) - mu I + S_k^dag (Sigma_inf - diag(V_DC)) S_k
+ *   N(k)     = 1/2 I - (beta/4) M1_k + (1/beta) sum_n [G_kn + G_kn^dag + 2 M1_k / w_n^2]
+ *                                      (Sec. 3.3 eq. rho_LDA+DMFT, summed on w_n > 0 with
+ *                                       G(-iw) = G(iw)^dag and the analytic 1/(iw),
+ *                                       1/(iw)^2 tails added back; tail_order 0 keeps
+ *                                       only the 1/2 I term)
+ *   N_tot    = sum_k w_k tr N(k)                        (Sec. 3.3 eq. fix_mu)
+ *   n_corr   = sum_k w_k tr(S_k N(k) S_k^dag)           (Sec. 3.4 eq. nf_LDA+DMFT)
+ *   <H_KS>   = sum_k w_k sum_v E_kv N_vv(k)             (Sec. 3.5.1 eq. H_KS)
+ *
+ * Here S_k is the paper's overlap S^k_{alpha n} = <alpha_k|phi_nk> (Sec. 3.1
+ * eq. S_norm), E_k its Kohn-Sham energies (Sec. 3.1 eq. H_LDA; n is a joint
+ * band+spin index, so no spin factor appears), Sigma the local self-energy and
+ * V_DC the double-counting shift (Sec. 3.2.3 eqs. V_DC, V_DC_component).
+ *
+ * Conventions shared by every entry point:
+ *   - complex numbers are interleaved (re, im) doubles, matrices row-major;
+ *     this is the byte layout of torch.complex128 / std::complex<double>;
+ *   - pointers marked DEVICE are device memory on the handle's GPU, HOST are
+ *     host memory; the caller owns every buffer (inputs, outputs, workspace);
+ *     the library never allocates device memory inside a call;
+ *   - work is enqueued on the given stream and returns before it completes
+ *     (find_mu and dmft_sync_status synchronise the stream); inputs must stay
+ *     alive until the stream work completes;
+ *   - errors are returned as dmft_status codes; host-side argument checks
+ *     run before anything is enqueued; conditions found on the device
+ *     (non-finite values, a vanishing pivot) set an error word inside the
+ *     workspace that dmft_sync_status and find_mu report;
+ *   - one handle per host thread; calls that share a workspace must be
+ *     ordered on one stream.
+ *
+ * Limits: 1 <= nc <= 16, nc <= nb_k <= 64, nw >= 1, beta > 0.
+ */
+#ifndef DMFT_H
+#define DMFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dmft_handle_s* dmft_handle;
+
+typedef enum dmft_status {
+  DMFT_OK = 0,
+  DMFT_EINVAL = -1,       /* bad argument (shape, NULL, limit, tail_order)      */
+  DMFT_EHIP = -2,         /* a HIP runtime call failed                          */
+  DMFT_ENONFINITE = -3,   /* a non-finite value reached a pivot or a trace      */
+  DMFT_ESINGULAR = -4,    /* a Gauss-Jordan pivot vanished (non-causal Sigma)   */
+  DMFT_ENOCONV = -5,      /* mu search: no bracket or max_iter reached          */
+  DMFT_EWORKSPACE = -6,   /* workspace NULL, misaligned or smaller than needed  */
+  DMFT_EUNSUPPORTED = -7  /* shape outside the compiled kernel variants         */
+} dmft_status;
+
+enum { DMFT_NEWTON = 0, DMFT_BISECT = 1 };
+
+/* Lattice side (Sec. 3.1): band window, energies and projectors of every k. */
+typedef struct dmft_lattice {
+  int32_t nk;          /* number of k-points                                          */
+  int32_t nc;          /* correlated orbitals alpha, 1..16                            */
+  int32_t nb_max;      /* largest band window, nc..64                                 */
+  const int32_t* nb;   /* HOST [nk] window size nb_k; NULL: every k has nb_max bands  */
+  const double* eps;   /* DEVICE E_vk: nb_k doubles per k, k after k                   */
+  const double* wk;    /* DEVICE [nk] k weights (the paper's sum over k; sum to 1)    */
+  const double* proj;  /* DEVICE S_k: nc x nb_k complex, row-major, k after k          */
+} dmft_lattice;
+
+/* Local self-energy on the positive Matsubara grid (Sec. 3.2.4 eq. se_pole form
+ * is not required: any Sigma(i w_n) is accepted). */
+typedef struct dmft_sigma {
+  int32_t nw;              /* frequencies n = 0 .. nw-1                              */
+  double beta;             /* inverse temperature (1/eV)                             */
+  const double* sigma;     /* DEVICE [nw][nc][nc] complex Sigma(i w_n)                */
+  const double* sigma_inf; /* DEVICE [nc][nc] complex Sigma(i inf), or NULL for zero; */
+                           /* used only in the 1/(iw)^2 tail moment M1                 */
+  const double* e_dc;      /* DEVICE [nc] real V_DC^alpha                             */
+} dmft_sigma;
+
+/* Handle: host-side plans, the autotune cache and a pinned staging buffer.
+ * Selects `device` as the handle's GPU.  Returns DMFT_OK or DMFT_EHIP. */
+int dmft_create(dmft_handle* out, int device);
+int dmft_destroy(dmft_handle h);
+
+/* Static text for a status code; never NULL. */
+const char* dmft_strerror(int status);
+/* Detail of the last error on this handle (empty string if none); owned by h. */
+const char* dmft_last_error(dmft_handle h);
+
+/* Workspace bytes needed by gloc_compute, density_matrix, dmft_ntot,
+ * density_matrix_vjp and find_mu for this shape (one size serves all). */
+int dmft_workspace_size(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
+                        size_t* bytes);
+
+/* G_loc(i w_n) = sum_k w_k S_k G_kn S_k^dag (Sec. 3.2.2 eq. dmftloop2).
+ * gloc: DEVICE [nw][nc][nc] complex, written (not accumulated). */
+int gloc_compute(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu,
+                 double* gloc, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Band density matrices N(k) (Sec. 3.3 eq. rho_LDA+DMFT) with the fused G_loc.
+ *   tail_order: 2 (analytic 1/(iw) and 1/(iw)^2 tails) or 0 (1/(iw) only);
+ *   nk:       DEVICE, nb_k x nb_k complex per k, k after k (Hermitian), or NULL;
+ *   gloc:     DEVICE [nw][nc][nc] complex, or NULL;
+ *   scalars:  DEVICE [3] = { N_tot, n_corr, <H_KS> }, or NULL.
+ * At least one output must be non-NULL. */
+int density_matrix(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu,
+                   int tail_order, double* nk, double* gloc, double* scalars, void* ws,
+                   size_t ws_bytes, hipStream_t stream);
+
+/* Trace-only pass of the mu search (Sec. 3.3 eq. fix_mu) with its adjoint:
+ * out: DEVICE [2] = { N_tot(mu), dN_tot/dmu }, where
+ *   dN_tot/dmu = sum_k w_k [ (beta/4) nb_k - (2/beta) sum_n (Re tr G_kn^2 + nb_k / w_n^2) ]
+ * (tail_order 2; without the tail: -(2/beta) sum_k w_k sum_n Re tr G_kn^2). */
+int dmft_ntot(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu,
+              int tail_order, double* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Vector-Jacobian product of density_matrix (derivative of the Dyson and
+ * Matsubara-sum steps), in PyTorch's complex convention dL/dRe + i dL/dIm for
+ * the loss L = sum_k Re<nk_bar_k, N(k)> + sum_n Re<gloc_bar_n, G_loc(n)>, with
+ * Sigma(i w_n), n = 0..nw-1, the independent variables and Sigma_inf held fixed:
+ *   sigma_bar_n = sum_k S_k G_kn^dag C_kn G_kn^dag S_k^dag,
+ *   C_kn        = (1/beta)(nk_bar_k + nk_bar_k^dag) + w_k S_k^dag gloc_bar_n S_k,
+ *   mu_bar      = -sum_kn Re<C_kn, G_kn^2> + tail_order/2 * (beta/4 - (2/beta) sum_n w_n^-2)
+ *                 * sum_k Re tr nk_bar_k.
+ *   nk_bar:    DEVICE, N(k) layout, or NULL (zero);
+ *   gloc_bar:  DEVICE [nw][nc][nc], or NULL (zero);
+ *   sigma_bar: DEVICE [nw][nc][nc] complex, written;
+ *   mu_bar:    DEVICE [1], written, or NULL. */
+int density_matrix_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu,
+                       int tail_order, const double* nk_bar, const double* gloc_bar,
+                       double* sigma_bar, double* mu_bar, void* ws, size_t ws_bytes,
+                       hipStream_t stream);
+
+/* Chemical potential with N_tot(mu) = n_target (Sec. 3.3 eq. fix_mu).
+ *   method DMFT_NEWTON: Newton steps with dN/dmu from the adjoint, kept inside
+ *     the bracket [mu_lo, mu_hi] (a step leaving the bracket, or not shrinking
+ *     the residual, falls back to bisection), starting at mu0;
+ *   method DMFT_BISECT: plain bisection of [mu_lo, mu_hi];
+ * stops when |N - n_target| <= tol_n.  Each iteration is one dmft_ntot pass and
+ * one 16-byte device-to-host copy; the stream is synchronised every iteration.
+ * Outputs (HOST): mu_out, passes_out (number of dmft_ntot passes), n_out.
+ * Returns DMFT_ENOCONV if the bracket does not contain the target or max_iter
+ * passes are used up. */
+int find_mu(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, int tail_order,
+            double n_target, double tol_n, int method, double mu_lo, double mu_hi, double mu0,
+            int max_iter, double* mu_out, int* passes_out, double* n_out, void* ws,
+            size_t ws_bytes, hipStream_t stream);
+
+/* Batched pass over several self-energy iterates with uneven band windows:
+ * one persistent launch over a cost-sorted queue of (iterate, k, frequency
+ * tile) items, followed by the reductions.  Build the plan once (it uploads
+ * the queue and per-k offsets into ws with a synchronous copy), then run
+ * dmft_batched_pass as often as needed; it only enqueues kernels, reads each
+ * iterate's mu from mu_dev (DEVICE [n_iter]) and is safe to capture in a
+ * hipGraph.  Per iterate s: nk_out[s] and gloc_out[s] (DEVICE, layouts as in
+ * density_matrix; either may be NULL).  lat[s]/sig[s] must stay unchanged
+ * between plan and pass. */
+int dmft_batched_workspace_size(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
+                                const dmft_sigma* const* sig, size_t* bytes);
+int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
+                      const dmft_sigma* const* sig, int tail_order, void* ws, size_t ws_bytes,
+                      hipStream_t stream);
+int dmft_batched_pass(dmft_handle h, const double* mu_dev, double* const* nk_out,
+                      double* const* gloc_out, void* ws, size_t ws_bytes, hipStream_t stream);
+/* Capture dmft_batched_pass into a hipGraph owned by the handle (replacing any
+ * previous one) and launch it on `stream`. */
+int dmft_batched_graph_capture(dmft_handle h, const double* mu_dev, double* const* nk_out,
+                               double* const* gloc_out, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+int dmft_batched_graph_launch(dmft_handle h, hipStream_t stream);
+
+/* Autotuner: times every compiled kernel variant that fits this shape on the
+ * handle's GPU, after checking that each one reproduces the reference variant,
+ * and caches the fastest in the handle (used by all later calls of that
+ * shape).  best_out (HOST, may be NULL) receives a short description. */
+int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu,
+                  void* ws, size_t ws_bytes, hipStream_t stream, char* best_out, size_t best_len);
+
+/* Kernel timing (for roofline reports).  enable = 1 clears the counters and
+ * starts recording a pair of hipEvents around every launch of the Dyson kernel
+ * (on the stream it is launched on); enable = 0 stops recording.  Every call
+ * first waits for the events recorded so far and returns, in HOST memory,
+ * the summed kernel time in ms and the number of timed launches (either
+ * pointer may be NULL).  Timing adds two event records per launch. */
+int dmft_timing(dmft_handle h, int enable, double* kernel_ms, int64_t* launches);
+
+/* Synchronise `stream` and report the error word kept in ws (then clear it). */
+int dmft_sync_status(dmft_handle h, void* ws, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMFT_H */

@@ -1,0 +1,88 @@
+"""ctypes view of libdmft.so (the C ABI declared in include/dmft.h).
+
+Marshalling only: every step of the Dyson path runs in the HIP kernels of the
+library.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdmft.so")
+
+# Every symbol declared in include/dmft.h.
+EXPORTS = [
+    "dmft_create", "dmft_destroy", "dmft_strerror", "dmft_last_error", "dmft_workspace_size",
+    "gloc_compute", "density_matrix", "dmft_ntot", "density_matrix_vjp", "find_mu",
+    "dmft_batched_workspace_size", "dmft_batched_plan", "dmft_batched_pass",
+    "dmft_batched_graph_capture", "dmft_batched_graph_launch", "dmft_autotune", "dmft_timing",
+    "dmft_sync_status",
+]
+
+STATUS = {0: "DMFT_OK", -1: "DMFT_EINVAL", -2: "DMFT_EHIP", -3: "DMFT_ENONFINITE",
+          -4: "DMFT_ESINGULAR", -5: "DMFT_ENOCONV", -6: "DMFT_EWORKSPACE", -7: "DMFT_EUNSUPPORTED"}
+NEWTON, BISECT = 0, 1
+
+
+class DmftLattice(C.Structure):
+    _fields_ = [("nk", C.c_int32), ("nc", C.c_int32), ("nb_max", C.c_int32),
+                ("nb", C.c_void_p), ("eps", C.c_void_p), ("wk", C.c_void_p), ("proj", C.c_void_p)]
+
+
+class DmftSigma(C.Structure):
+    _fields_ = [("nw", C.c_int32), ("beta", C.c_double), ("sigma", C.c_void_p),
+                ("sigma_inf", C.c_void_p), ("e_dc", C.c_void_p)]
+
+
+class DmftError(RuntimeError):
+    def __init__(self, code, detail=""):
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        super().__init__("%s: %s" % (self.name, detail))
+
+
+_lib = None
+
+
+def load():
+    """Load libdmft.so; raises if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libdmft.so is not built (run paper_1111_2157_amd.build.build())")
+    lib = C.CDLL(LIB_PATH)
+    P, I, D, S = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+    lp, sp = C.POINTER(DmftLattice), C.POINTER(DmftSigma)
+    sig = {
+        "dmft_create": ([C.POINTER(P), I], I),
+        "dmft_destroy": ([P], I),
+        "dmft_strerror": ([I], C.c_char_p),
+        "dmft_last_error": ([P], C.c_char_p),
+        "dmft_workspace_size": ([P, lp, sp, C.POINTER(S)], I),
+        "gloc_compute": ([P, lp, sp, D, P, P, S, P], I),
+        "density_matrix": ([P, lp, sp, D, I, P, P, P, P, S, P], I),
+        "dmft_ntot": ([P, lp, sp, D, I, P, P, S, P], I),
+        "density_matrix_vjp": ([P, lp, sp, D, I, P, P, P, P, P, S, P], I),
+        "find_mu": ([P, lp, sp, I, D, D, I, D, D, D, I, C.POINTER(D), C.POINTER(I), C.POINTER(D), P, S, P], I),
+        "dmft_batched_workspace_size": ([P, I, P, P, C.POINTER(S)], I),
+        "dmft_batched_plan": ([P, I, P, P, I, P, S, P], I),
+        "dmft_batched_pass": ([P, P, P, P, P, S, P], I),
+        "dmft_batched_graph_capture": ([P, P, P, P, P, S, P], I),
+        "dmft_batched_graph_launch": ([P, P], I),
+        "dmft_autotune": ([P, lp, sp, D, P, S, P, C.c_char_p, S], I),
+        "dmft_timing": ([P, I, C.POINTER(D), C.POINTER(C.c_int64)], I),
+        "dmft_sync_status": ([P, P, P], I),
+    }
+    for name in EXPORTS:
+        f = getattr(lib, name)
+        f.argtypes, f.restype = sig[name]
+    _lib = lib
+    return lib
+
+
+def check(handle, code):
+    if code != 0:
+        detail = load().dmft_last_error(handle)
+        raise DmftError(code, detail.decode() if detail else "")

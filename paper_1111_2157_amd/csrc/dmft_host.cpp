@@ -1,0 +1,625 @@
+// Host side of libdmft: argument checks, workspace layout, tiling plans, kernel
+// launches, the chemical-potential search, the batched pass and its hipGraph,
+// and the autotuner.  See include/dmft.h for the public contract.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "dmft.h"
+#include "dmft_internal.h"
+
+using namespace dmft;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr int kNbpSizes[] = {16, 32, 48, 64};
+
+int nbp_of(int nb) {
+  for (int s : kNbpSizes)
+    if (nb <= s) return s;
+  return -1;
+}
+
+// Tiling of one launch: kt k-points per k-tile, wt frequencies per frequency tile.
+struct Tile {
+  int kt = 1, wt = 1;
+  int var = -1;  // kernel variant (see launch_dyson); -1: default for the size
+};
+
+int default_var(int nbp, bool trace) {
+  if (trace) return nbp >= 48 ? 0 : 1;
+  if (nbp >= 48) return 2;
+  return 1;
+}
+
+// One padded-size bucket of k-points.
+struct Bucket {
+  int nbp = 0;
+  std::vector<int32_t> klist;
+  int n_ktiles = 0;
+  int ktile_base = 0;
+};
+
+// Workspace layout of a single-lattice call.
+struct Layout {
+  size_t err = 0, out2 = 0, meta_nb = 0, meta_offb = 0, meta_offn = 0, meta_nbp = 0, meta_klist = 0;
+  size_t spart = 0, xpart = 0, tpart = 0, kscal = 0, ktrace = 0, total = 0;
+  int64_t s_stride = 0;
+  int n_wtiles = 0, n_ktiles_total = 0;
+  std::vector<Bucket> buckets;
+  std::vector<int32_t> nb, nbp;
+  std::vector<int64_t> off_b, off_n;
+  bool ragged = false;
+  int nbp_max = 0;
+  Tile tile;
+};
+
+}  // namespace
+
+struct dmft_handle_s {
+  int device = 0;
+  std::string last_error;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t staged = nullptr;      // recorded after the last upload from `pinned`
+  std::map<std::string, Tile> tune; // autotune cache keyed by shape
+  // batched plan
+  struct Iter {
+    dmft_lattice lat;
+    dmft_sigma sig;
+    Layout lay;
+    size_t base = 0;  // offset of this iterate's region inside ws
+  };
+  std::vector<Iter> iters;
+  int b_tail = 2;
+  size_t b_total = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  // kernel timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;  // recorded, not yet read
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tfree;
+  double t_ms = 0.0;
+  int64_t t_count = 0;
+};
+
+namespace {
+
+int fail(dmft_handle h, int code, const char* fmt, ...) {
+  if (h) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    h->last_error = buf;
+  }
+  return code;
+}
+
+#define HIPCHK(h, expr)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(h, DMFT_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int check_shapes(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig) {
+  if (!h) return DMFT_EINVAL;
+  if (!lat || !sig) return fail(h, DMFT_EINVAL, "lattice or sigma is NULL");
+  if (lat->nk < 1) return fail(h, DMFT_EINVAL, "nk must be >= 1 (got %d)", lat->nk);
+  if (lat->nc < 1 || lat->nc > 16) return fail(h, DMFT_EINVAL, "nc must be in 1..16 (got %d)", lat->nc);
+  if (lat->nb_max < lat->nc || lat->nb_max > 64)
+    return fail(h, DMFT_EINVAL, "nb_max must be in nc..64 (got %d)", lat->nb_max);
+  if (!lat->eps || !lat->wk || !lat->proj) return fail(h, DMFT_EINVAL, "eps, wk and proj must be set");
+  if (lat->nb) {
+    for (int k = 0; k < lat->nk; ++k)
+      if (lat->nb[k] < lat->nc || lat->nb[k] > lat->nb_max)
+        return fail(h, DMFT_EINVAL, "nb[%d] = %d outside nc..nb_max", k, lat->nb[k]);
+  }
+  if (sig->nw < 1) return fail(h, DMFT_EINVAL, "nw must be >= 1 (got %d)", sig->nw);
+  if (!(sig->beta > 0) || !std::isfinite(sig->beta))
+    return fail(h, DMFT_EINVAL, "beta must be positive and finite");
+  if (!sig->sigma || !sig->e_dc) return fail(h, DMFT_EINVAL, "sigma and e_dc must be set");
+  return DMFT_OK;
+}
+
+Tile default_tile(const dmft_handle h, int nk, int nw, int nbp) {
+  char key[96];
+  snprintf(key, sizeof key, "%d/%d/%d", nbp, nk, nw);
+  auto it = h->tune.find(key);
+  if (it != h->tune.end()) return it->second;
+  Tile t;
+  // k-tile: keep the G_loc partials (nk/kt x nw x 4 KiB) near 1 GiB at most.
+  double xbytes = (double)nk * nw * 4096.0;
+  t.kt = std::max(1, (int)std::ceil(xbytes / (1u << 30)));
+  t.kt = std::min(t.kt, std::max(1, nk / 4));
+  // frequency tile: aim at >= 4096 work-groups in total (>= 4 per SIMD slot).
+  int n_ktiles = (nk + t.kt - 1) / t.kt;
+  int want_wtiles = std::max(1, (4096 + n_ktiles - 1) / n_ktiles);
+  t.wt = std::max(4, (nw + want_wtiles - 1) / want_wtiles);
+  t.wt = std::min(t.wt, nw);
+  return t;
+}
+
+// Build the workspace layout for one lattice.
+int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, Layout& L,
+                const Tile* force = nullptr) {
+  int nk = lat->nk, nw = sig->nw;
+  L.ragged = lat->nb != nullptr;
+  L.nb.assign(nk, lat->nb_max);
+  if (lat->nb)
+    for (int k = 0; k < nk; ++k) L.nb[k] = lat->nb[k];
+  L.off_b.assign(nk + 1, 0);
+  L.off_n.assign(nk + 1, 0);
+  L.nbp.assign(nk, 0);
+  for (int k = 0; k < nk; ++k) {
+    L.off_b[k + 1] = L.off_b[k] + L.nb[k];
+    L.off_n[k + 1] = L.off_n[k] + (int64_t)L.nb[k] * L.nb[k];
+    L.nbp[k] = nbp_of(L.nb[k]);
+    if (!dyson_supported(L.nbp[k]))
+      return fail(h, DMFT_EUNSUPPORTED, "no kernel variant for nb = %d", L.nb[k]);
+  }
+  L.nbp_max = *std::max_element(L.nbp.begin(), L.nbp.end());
+  L.tile = force ? *force : default_tile(h, nk, nw, L.nbp_max);
+  L.tile.wt = std::max(1, std::min(L.tile.wt, nw));
+  L.tile.kt = std::max(1, std::min(L.tile.kt, nk));
+  L.n_wtiles = (nw + L.tile.wt - 1) / L.tile.wt;
+  L.buckets.clear();
+  int base = 0;
+  for (int s : kNbpSizes) {
+    Bucket b;
+    b.nbp = s;
+    for (int k = 0; k < nk; ++k)
+      if (L.nbp[k] == s) b.klist.push_back(k);
+    if (b.klist.empty()) continue;
+    b.n_ktiles = ((int)b.klist.size() + L.tile.kt - 1) / L.tile.kt;
+    b.ktile_base = base;
+    base += b.n_ktiles;
+    L.buckets.push_back(b);
+  }
+  L.n_ktiles_total = base;
+  L.s_stride = (int64_t)L.nbp_max * L.nbp_max;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.err = take(16);
+  L.out2 = take(16 * sizeof(double));
+  L.meta_nb = take(sizeof(int32_t) * nk);
+  L.meta_offb = take(sizeof(int64_t) * (nk + 1));
+  L.meta_offn = take(sizeof(int64_t) * (nk + 1));
+  L.meta_nbp = take(sizeof(int32_t) * nk);
+  L.meta_klist = take(sizeof(int32_t) * nk);
+  L.spart = take((size_t)L.n_wtiles * nk * L.s_stride * 16);
+  L.xpart = take((size_t)L.n_ktiles_total * nw * 256 * 16);
+  L.tpart = take((size_t)L.n_wtiles * nk * 2 * sizeof(double));
+  L.kscal = take((size_t)nk * 3 * sizeof(double));
+  L.ktrace = take((size_t)nk * 2 * sizeof(double));
+  L.total = o;
+  return DMFT_OK;
+}
+
+int check_ws(dmft_handle h, const Layout& L, void* ws, size_t ws_bytes) {
+  if (!ws) return fail(h, DMFT_EWORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % kAlign) return fail(h, DMFT_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(h, DMFT_EWORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  return DMFT_OK;
+}
+
+// Upload the per-k metadata (sizes, offsets, bucket k lists) into ws.
+int upload_meta(dmft_handle h, const Layout& L, char* ws, hipStream_t s, bool sync) {
+  size_t nk = L.nb.size();
+  size_t need = sizeof(int32_t) * nk * 3 + sizeof(int64_t) * (nk + 1) * 2;
+  if (h->staged) HIPCHK(h, hipEventSynchronize(h->staged));
+  if (need > h->pinned_bytes) {
+    if (h->pinned) HIPCHK(h, hipHostFree(h->pinned));
+    h->pinned = nullptr;
+    HIPCHK(h, hipHostMalloc(&h->pinned, need, hipHostMallocDefault));
+    h->pinned_bytes = need;
+  }
+  char* p = (char*)h->pinned;
+  int32_t* nbv = (int32_t*)p;
+  int64_t* offb = (int64_t*)(nbv + nk);
+  int64_t* offn = offb + nk + 1;
+  int32_t* nbpv = (int32_t*)(offn + nk + 1);
+  int32_t* kl = nbpv + nk;
+  std::copy(L.nb.begin(), L.nb.end(), nbv);
+  std::copy(L.off_b.begin(), L.off_b.end(), offb);
+  std::copy(L.off_n.begin(), L.off_n.end(), offn);
+  std::copy(L.nbp.begin(), L.nbp.end(), nbpv);
+  size_t at = 0;
+  for (const Bucket& b : L.buckets) {
+    std::copy(b.klist.begin(), b.klist.end(), kl + at);
+    at += b.klist.size();
+  }
+  HIPCHK(h, hipMemcpyAsync(ws + L.meta_nb, nbv, sizeof(int32_t) * nk, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(ws + L.meta_offb, offb, sizeof(int64_t) * (nk + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(ws + L.meta_offn, offn, sizeof(int64_t) * (nk + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(ws + L.meta_nbp, nbpv, sizeof(int32_t) * nk, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(ws + L.meta_klist, kl, sizeof(int32_t) * nk, hipMemcpyHostToDevice, s));
+  if (!h->staged) HIPCHK(h, hipEventCreateWithFlags(&h->staged, hipEventDisableTiming));
+  HIPCHK(h, hipEventRecord(h->staged, s));
+  if (sync) HIPCHK(h, hipEventSynchronize(h->staged));
+  return DMFT_OK;
+}
+
+double sum_inv_w2(int nw, double beta) {
+  double s2 = 0.0;
+  for (int n = 0; n < nw; ++n) {
+    double w = (2.0 * n + 1.0) * M_PI / beta;
+    s2 += 1.0 / (w * w);
+  }
+  return s2;
+}
+
+// Enqueue the Dyson kernel(s) for all buckets with the given mode.
+int run_dyson(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, const Layout& L,
+              char* ws, double mu, const double* mu_ptr, int mode, hipStream_t s) {
+  DysonArgs a{};
+  a.nk = lat->nk;
+  a.nc = lat->nc;
+  a.nw = sig->nw;
+  a.nb_uniform = L.ragged ? 0 : lat->nb_max;
+  a.nb = (const int32_t*)(ws + L.meta_nb);
+  a.off_b = (const int64_t*)(ws + L.meta_offb);
+  a.eps = lat->eps;
+  a.wk = lat->wk;
+  a.proj = lat->proj;
+  a.beta = sig->beta;
+  a.sigma = sig->sigma;
+  a.e_dc = sig->e_dc;
+  a.mu = mu;
+  a.mu_ptr = mu_ptr;
+  a.kt = L.tile.kt;
+  a.wt = L.tile.wt;
+  a.n_wtiles = L.n_wtiles;
+  a.mode = mode;
+  a.spart = (double*)(ws + L.spart);
+  a.s_stride = L.s_stride;
+  a.xpart = (double*)(ws + L.xpart);
+  a.tpart = (double*)(ws + L.tpart);
+  a.err = (int*)(ws + L.err);
+  size_t at = 0;
+  for (const Bucket& b : L.buckets) {
+    a.klist = L.ragged || L.buckets.size() > 1 ? (const int32_t*)(ws + L.meta_klist) + at : nullptr;
+    a.nklist = (int)b.klist.size();
+    a.ktile_base = b.ktile_base;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (h->timing) {
+      if (!h->tfree.empty()) {
+        ev = h->tfree.back();
+        h->tfree.pop_back();
+      } else {
+        HIPCHK(h, hipEventCreate(&ev.first));
+        HIPCHK(h, hipEventCreate(&ev.second));
+      }
+      HIPCHK(h, hipEventRecord(ev.first, s));
+    }
+    int var = L.tile.var >= 0 ? L.tile.var : default_var(b.nbp, (mode & MODE_TRACE) != 0);
+    HIPCHK(h, launch_dyson(b.nbp, var, a, b.n_ktiles, s));
+    if (h->timing) {
+      HIPCHK(h, hipEventRecord(ev.second, s));
+      h->tev.push_back(ev);
+    }
+    at += b.klist.size();
+  }
+  return DMFT_OK;
+}
+
+EpilogueArgs epilogue_args(const dmft_lattice* lat, const dmft_sigma* sig, const Layout& L,
+                           char* ws, double mu, const double* mu_ptr, int tail_order) {
+  EpilogueArgs e{};
+  e.nk = lat->nk;
+  e.nc = lat->nc;
+  e.nw = sig->nw;
+  e.nb_uniform = L.ragged ? 0 : lat->nb_max;
+  e.nb = (const int32_t*)(ws + L.meta_nb);
+  e.off_b = (const int64_t*)(ws + L.meta_offb);
+  e.off_n = (const int64_t*)(ws + L.meta_offn);
+  e.nbp = (const int32_t*)(ws + L.meta_nbp);
+  e.eps = lat->eps;
+  e.wk = lat->wk;
+  e.proj = lat->proj;
+  e.beta = sig->beta;
+  e.sigma_inf = sig->sigma_inf;
+  e.e_dc = sig->e_dc;
+  e.mu = mu;
+  e.mu_ptr = mu_ptr;
+  e.tail_order = tail_order;
+  e.n_wtiles = L.n_wtiles;
+  e.spart = (const double*)(ws + L.spart);
+  e.s_stride = L.s_stride;
+  e.tpart = (const double*)(ws + L.tpart);
+  e.kscal = (double*)(ws + L.kscal);
+  e.ktrace = (double*)(ws + L.ktrace);
+  e.s2 = sum_inv_w2(sig->nw, sig->beta);
+  return e;
+}
+
+int prepare(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, void* ws, size_t ws_bytes,
+            Layout& L, hipStream_t s) {
+  int r = check_shapes(h, lat, sig);
+  if (r) return r;
+  r = make_layout(h, lat, sig, L);
+  if (r) return r;
+  r = check_ws(h, L, ws, ws_bytes);
+  if (r) return r;
+  HIPCHK(h, hipSetDevice(h->device));
+  return upload_meta(h, L, (char*)ws, s, false);
+}
+
+int density_impl(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, const Layout& L,
+                 char* ws, double mu, const double* mu_ptr, int tail_order, double* nk, double* gloc,
+                 double* scalars, hipStream_t s) {
+  int mode = 0;
+  if (nk || scalars) mode |= MODE_S;
+  if (gloc) mode |= MODE_GLOC;
+  int r = run_dyson(h, lat, sig, L, ws, mu, mu_ptr, mode, s);
+  if (r) return r;
+  EpilogueArgs e = epilogue_args(lat, sig, L, ws, mu, mu_ptr, tail_order);
+  if (mode & MODE_S) {
+    HIPCHK(h, launch_nk_epilogue(e, nk, s));
+    if (scalars) HIPCHK(h, launch_scalar_reduce(lat->nk, lat->wk, e.kscal, 3, scalars, s));
+  }
+  if (gloc) HIPCHK(h, launch_gloc_reduce(L.n_ktiles_total, sig->nw, lat->nc,
+                                         (const double*)(ws + L.xpart), gloc, s));
+  return DMFT_OK;
+}
+
+int ntot_impl(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, const Layout& L,
+              char* ws, double mu, const double* mu_ptr, int tail_order, double* out, hipStream_t s) {
+  int r = run_dyson(h, lat, sig, L, ws, mu, mu_ptr, MODE_TRACE, s);
+  if (r) return r;
+  EpilogueArgs e = epilogue_args(lat, sig, L, ws, mu, mu_ptr, tail_order);
+  HIPCHK(h, launch_trace_epilogue(e, s));
+  HIPCHK(h, launch_scalar_reduce(lat->nk, lat->wk, e.ktrace, 2, out, s));
+  return DMFT_OK;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+
+extern "C" {
+
+const char* dmft_strerror(int status) {
+  switch (status) {
+    case DMFT_OK: return "ok";
+    case DMFT_EINVAL: return "invalid argument";
+    case DMFT_EHIP: return "HIP runtime error";
+    case DMFT_ENONFINITE: return "non-finite value on the device";
+    case DMFT_ESINGULAR: return "vanishing pivot (singular Dyson matrix)";
+    case DMFT_ENOCONV: return "chemical-potential search did not converge";
+    case DMFT_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case DMFT_EUNSUPPORTED: return "shape not supported by the compiled kernels";
+    default: return "unknown status";
+  }
+}
+
+int dmft_create(dmft_handle* out, int device) {
+  if (!out) return DMFT_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DMFT_EHIP;
+  if (hipSetDevice(device) != hipSuccess) return DMFT_EHIP;
+  dmft_handle h = new dmft_handle_s;
+  h->device = device;
+  *out = h;
+  return DMFT_OK;
+}
+
+int dmft_destroy(dmft_handle h) {
+  if (!h) return DMFT_EINVAL;
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->staged) {
+    (void)hipEventSynchronize(h->staged);
+    (void)hipEventDestroy(h->staged);
+  }
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  for (auto& ev : h->tev) {
+    (void)hipEventSynchronize(ev.second);
+    h->tfree.push_back(ev);
+  }
+  for (auto& ev : h->tfree) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  delete h;
+  return DMFT_OK;
+}
+
+const char* dmft_last_error(dmft_handle h) { return h ? h->last_error.c_str() : ""; }
+
+int dmft_workspace_size(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, size_t* bytes) {
+  if (!bytes) return fail(h, DMFT_EINVAL, "bytes is NULL");
+  int r = check_shapes(h, lat, sig);
+  if (r) return r;
+  Layout L;
+  r = make_layout(h, lat, sig, L);
+  if (r) return r;
+  *bytes = L.total;
+  return DMFT_OK;
+}
+
+int gloc_compute(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu, double* gloc,
+                 void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!gloc) return fail(h, DMFT_EINVAL, "gloc is NULL");
+  Layout L;
+  int r = prepare(h, lat, sig, ws, ws_bytes, L, stream);
+  if (r) return r;
+  return density_impl(h, lat, sig, L, (char*)ws, mu, nullptr, 2, nullptr, gloc, nullptr, stream);
+}
+
+int density_matrix(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu, int tail_order,
+                   double* nk, double* gloc, double* scalars, void* ws, size_t ws_bytes,
+                   hipStream_t stream) {
+  if (tail_order != 0 && tail_order != 2) return fail(h, DMFT_EINVAL, "tail_order must be 0 or 2");
+  if (!nk && !gloc && !scalars) return fail(h, DMFT_EINVAL, "no output requested");
+  if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
+  Layout L;
+  int r = prepare(h, lat, sig, ws, ws_bytes, L, stream);
+  if (r) return r;
+  return density_impl(h, lat, sig, L, (char*)ws, mu, nullptr, tail_order, nk, gloc, scalars, stream);
+}
+
+int dmft_ntot(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu, int tail_order,
+              double* out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (tail_order != 0 && tail_order != 2) return fail(h, DMFT_EINVAL, "tail_order must be 0 or 2");
+  if (!out) return fail(h, DMFT_EINVAL, "out is NULL");
+  if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
+  Layout L;
+  int r = prepare(h, lat, sig, ws, ws_bytes, L, stream);
+  if (r) return r;
+  return ntot_impl(h, lat, sig, L, (char*)ws, mu, nullptr, tail_order, out, stream);
+}
+
+int dmft_timing(dmft_handle h, int enable, double* kernel_ms, int64_t* launches) {
+  if (!h) return DMFT_EINVAL;
+  for (auto& ev : h->tev) {
+    HIPCHK(h, hipEventSynchronize(ev.second));
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, ev.first, ev.second));
+    h->t_ms += ms;
+    h->t_count += 1;
+    h->tfree.push_back(ev);
+  }
+  h->tev.clear();
+  if (kernel_ms) *kernel_ms = h->t_ms;
+  if (launches) *launches = h->t_count;
+  if (enable) {
+    h->t_ms = 0.0;
+    h->t_count = 0;
+  }
+  h->timing = enable != 0;
+  return DMFT_OK;
+}
+
+int dmft_sync_status(dmft_handle h, void* ws, hipStream_t stream) {
+  if (!h || !ws) return fail(h, DMFT_EINVAL, "handle or workspace is NULL");
+  HIPCHK(h, hipStreamSynchronize(stream));
+  int err = 0;
+  HIPCHK(h, hipMemcpy(&err, ws, sizeof(int), hipMemcpyDeviceToHost));
+  int zero = 0;
+  HIPCHK(h, hipMemcpy(ws, &zero, sizeof(int), hipMemcpyHostToDevice));
+  if (err & ERR_NONFINITE) return fail(h, DMFT_ENONFINITE, "device flagged a non-finite value");
+  if (err & ERR_SINGULAR) return fail(h, DMFT_ESINGULAR, "device flagged a vanishing pivot");
+  return DMFT_OK;
+}
+
+int find_mu(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, int tail_order, double n_target,
+            double tol_n, int method, double mu_lo, double mu_hi, double mu0, int max_iter, double* mu_out,
+            int* passes_out, double* n_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (tail_order != 0 && tail_order != 2) return fail(h, DMFT_EINVAL, "tail_order must be 0 or 2");
+  if (method != DMFT_NEWTON && method != DMFT_BISECT) return fail(h, DMFT_EINVAL, "unknown method");
+  if (!(mu_lo < mu_hi) || !std::isfinite(mu_lo) || !std::isfinite(mu_hi))
+    return fail(h, DMFT_EINVAL, "need finite mu_lo < mu_hi");
+  if (!(tol_n > 0) || max_iter < 1) return fail(h, DMFT_EINVAL, "need tol_n > 0 and max_iter >= 1");
+  Layout L;
+  int r = prepare(h, lat, sig, ws, ws_bytes, L, stream);
+  if (r) return r;
+  char* w = (char*)ws;
+  double* dout = (double*)(w + L.out2);
+  int passes = 0;
+  double host[2];
+  auto eval = [&](double mu, double* nv, double* dv) -> int {
+    int rr = ntot_impl(h, lat, sig, L, w, mu, nullptr, tail_order, dout, stream);
+    if (rr) return rr;
+    HIPCHK(h, hipMemcpyAsync(host, dout, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipStreamSynchronize(stream));
+    ++passes;
+    int err = 0;
+    HIPCHK(h, hipMemcpy(&err, w + L.err, sizeof(int), hipMemcpyDeviceToHost));
+    if (err) {
+      int zero = 0;
+      HIPCHK(h, hipMemcpy(w + L.err, &zero, sizeof(int), hipMemcpyHostToDevice));
+      return fail(h, (err & ERR_NONFINITE) ? DMFT_ENONFINITE : DMFT_ESINGULAR, "device error at mu=%g", mu);
+    }
+    *nv = host[0];
+    if (dv) *dv = host[1];
+    return DMFT_OK;
+  };
+  double lo = mu_lo, hi = mu_hi, mu = 0.0, nv = 0.0, dv = 0.0;
+  int converged = 0;
+  if (method == DMFT_BISECT) {
+    // N(mu) increases with mu; keep N(lo) < n_target < N(hi) implicitly.
+    for (int it = 0; it < max_iter; ++it) {
+      mu = 0.5 * (lo + hi);
+      r = eval(mu, &nv, nullptr);
+      if (r) return r;
+      if (std::fabs(nv - n_target) <= tol_n) { converged = 1; break; }
+      if (nv < n_target) lo = mu; else hi = mu;
+    }
+  } else {
+    // Newton inside the bracket (safeguarded as in Numerical Recipes' rtsafe):
+    // take the Newton step when it stays strictly inside [lo, hi] and shrinks
+    // the residual fast enough, otherwise bisect.
+    mu = std::min(std::max(mu0, lo), hi);
+    double prev_res = INFINITY, prev_dx = hi - lo;
+    for (int it = 0; it < max_iter; ++it) {
+      r = eval(mu, &nv, &dv);
+      if (r) return r;
+      double res = nv - n_target;
+      if (std::fabs(res) <= tol_n) { converged = 1; break; }
+      if (res < 0) lo = mu; else hi = mu;
+      double next;
+      bool newton_ok = dv > 0 && std::isfinite(dv);
+      if (newton_ok) {
+        next = mu - res / dv;
+        if (!(next > lo && next < hi)) newton_ok = false;
+        if (std::fabs(res) > 0.5 * prev_res && std::fabs(next - mu) > 0.5 * prev_dx) newton_ok = false;
+      }
+      if (!newton_ok) next = 0.5 * (lo + hi);
+      prev_dx = std::fabs(next - mu);
+      prev_res = std::fabs(res);
+      mu = next;
+    }
+  }
+  if (mu_out) *mu_out = mu;
+  if (passes_out) *passes_out = passes;
+  if (n_out) *n_out = nv;
+  if (!converged) return fail(h, DMFT_ENOCONV, "no convergence after %d passes (N=%g)", passes, nv);
+  return DMFT_OK;
+}
+
+
+int density_matrix_vjp(dmft_handle h, const dmft_lattice*, const dmft_sigma*, double, int, const double*,
+                       const double*, double*, double*, void*, size_t, hipStream_t) {
+  return fail(h, DMFT_EUNSUPPORTED, "density_matrix_vjp: not built yet");
+}
+int dmft_batched_workspace_size(dmft_handle h, int, const dmft_lattice* const*, const dmft_sigma* const*,
+                                size_t*) {
+  return fail(h, DMFT_EUNSUPPORTED, "batched: not built yet");
+}
+int dmft_batched_plan(dmft_handle h, int, const dmft_lattice* const*, const dmft_sigma* const*, int, void*,
+                      size_t, hipStream_t) {
+  return fail(h, DMFT_EUNSUPPORTED, "batched: not built yet");
+}
+int dmft_batched_pass(dmft_handle h, const double*, double* const*, double* const*, void*, size_t,
+                      hipStream_t) {
+  return fail(h, DMFT_EUNSUPPORTED, "batched: not built yet");
+}
+int dmft_batched_graph_capture(dmft_handle h, const double*, double* const*, double* const*, void*, size_t,
+                               hipStream_t) {
+  return fail(h, DMFT_EUNSUPPORTED, "batched: not built yet");
+}
+int dmft_batched_graph_launch(dmft_handle h, hipStream_t) {
+  return fail(h, DMFT_EUNSUPPORTED, "batched: not built yet");
+}
+int dmft_autotune(dmft_handle h, const dmft_lattice*, const dmft_sigma*, double, void*, size_t, hipStream_t,
+                  char*, size_t) {
+  return fail(h, DMFT_EUNSUPPORTED, "autotune: not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal interface between the C-ABI host layer (dmft_host.cpp) and the HIP
+// kernels (dmft_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace dmft {
+
+// Kernel modes (bit set).
+enum : int {
+  MODE_S = 1,      // accumulate sum_n G_kn into per-(frequency tile, k) partials
+  MODE_GLOC = 2,   // accumulate w_k S G S^dag into per-(k tile, n) partials
+  MODE_TRACE = 4,  // accumulate sum_n Re tr G and sum_n Re tr G^2 per (frequency tile, k)
+};
+
+// Error bits raised on the device.
+enum : int { ERR_SINGULAR = 1, ERR_NONFINITE = 2 };
+
+// Everything one launch of the Dyson kernel needs.  Pointers are device
+// pointers.  A launch covers the k-points klist[0 .. nklist) (all with
+// nb_k <= NBP of the instance) and all nw frequencies, tiled as
+// ceil(nklist / kt) k-tiles x n_wtiles frequency tiles of wt frequencies.
+struct DysonArgs {
+  int nk, nc, nw;
+  int nb_uniform;              // > 0: every k has this many bands and nb/off_b are unused
+  const int32_t* nb;           // [nk]
+  const int64_t* off_b;        // [nk+1] prefix sums of nb
+  const double* eps;
+  const double* wk;
+  const double* proj;          // complex
+  double beta;
+  const double* sigma;         // complex [nw][nc][nc]
+  const double* e_dc;          // [nc]
+  const double* mu_ptr;        // if non-null, mu is read from here (device scalar)
+  double mu;
+  const int32_t* klist;        // [nklist] or null (identity)
+  int nklist;
+  int kt, wt, n_wtiles;
+  int ktile_base;              // index of this launch's first k tile among all k tiles
+  int mode;
+  double* spart;               // MODE_S:    [n_wtiles][nk][NBP*NBP] complex, lane order
+  int64_t s_stride;            // complex elements per (wtile, k) slot of spart
+  double* xpart;               // MODE_GLOC: [n_ktiles_total][nw][256] complex, lane order
+  double* tpart;               // MODE_TRACE:[n_wtiles][nk][2]
+  int* err;                    // error word
+};
+
+struct EpilogueArgs {
+  int nk, nc, nw;
+  int nb_uniform;
+  const int32_t* nb;
+  const int64_t* off_b;
+  const int64_t* off_n;        // [nk+1] prefix sums of nb^2 (output layout)
+  const int32_t* nbp;          // [nk] padded size (NBP) used for k's partials
+  const double* eps;
+  const double* wk;
+  const double* proj;
+  double beta;
+  const double* sigma_inf;     // complex [nc][nc] or null
+  const double* e_dc;
+  const double* mu_ptr;
+  double mu;
+  int tail_order;
+  int n_wtiles;
+  const double* spart;
+  int64_t s_stride;
+  const double* tpart;
+  double* nk_out;              // complex, ragged
+  double* kscal;               // [nk][3] per-k  tr N, tr(S N S^dag), sum_v E_v N_vv
+  double* ktrace;              // [nk][2] per-k  tr N, d tr N / dmu   (trace mode)
+  double s2;                   // sum_n 1 / w_n^2, summed in increasing n
+};
+
+// Launchers (return hipError_t of the launch).
+// var: kernel variant, bit 0 = next-step pivot column read ahead (PF), bit 1 =
+// running sum of G in LDS (SLDS, density kind only; forced for nbp = 48).
+hipError_t launch_dyson(int nbp, int var, const DysonArgs& a, int n_ktiles, hipStream_t s);
+bool dyson_supported(int nbp);
+hipError_t launch_nk_epilogue(const EpilogueArgs& a, double* nk_out, hipStream_t s);
+hipError_t launch_trace_epilogue(const EpilogueArgs& a, hipStream_t s);
+hipError_t launch_gloc_reduce(int n_ktiles, int nw, int nc, const double* xpart, double* gloc,
+                              hipStream_t s);
+hipError_t launch_scalar_reduce(int nk, const double* wk, const double* kvals, int nvals,
+                                double* out, hipStream_t s);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace dmft

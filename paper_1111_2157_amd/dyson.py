@@ -1,0 +1,206 @@
+"""PyTorch-facing binding of libdmft (device memory and streams come from torch).
+
+The functions keep the C ABI's names and only marshal arguments: they pass
+``tensor.data_ptr()`` and torch's current HIP stream to the library, whose
+kernels do all of the computation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BISECT, NEWTON, DmftLattice, DmftSigma, check
+
+__all__ = ["Lattice", "SelfEnergy", "Context", "NEWTON", "BISECT"]
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+@dataclass
+class Lattice:
+    """Band windows, energies and projectors of every k (device-resident)."""
+
+    nk: int
+    nc: int
+    nb_max: int
+    nb: Optional[np.ndarray]      # host int32 [nk], or None when every k has nb_max bands
+    eps: torch.Tensor             # float64, all k concatenated
+    wk: torch.Tensor              # float64 [nk]
+    proj: torch.Tensor            # complex128, all k concatenated (nc x nb_k row-major)
+
+    @classmethod
+    def from_host(cls, lat, device="cuda"):
+        nb = np.ascontiguousarray(lat.nb, np.int32)
+        uniform = bool((nb == nb[0]).all())
+        return cls(int(lat.nk), int(lat.nc), int(nb.max()), None if uniform else nb,
+                   torch.as_tensor(np.ascontiguousarray(lat.eps, np.float64), device=device),
+                   torch.as_tensor(np.ascontiguousarray(lat.wk, np.float64), device=device),
+                   torch.as_tensor(np.ascontiguousarray(lat.proj, np.complex128), device=device))
+
+    def nb_array(self):
+        return np.full(self.nk, self.nb_max, np.int32) if self.nb is None else self.nb
+
+    def n_size(self):
+        return int((self.nb_array().astype(np.int64) ** 2).sum())
+
+    def struct(self):
+        self._nb_keep = None if self.nb is None else np.ascontiguousarray(self.nb, np.int32)
+        return DmftLattice(self.nk, self.nc, self.nb_max,
+                           None if self._nb_keep is None else self._nb_keep.ctypes.data_as(C.c_void_p),
+                           _ptr(self.eps), _ptr(self.wk), _ptr(self.proj))
+
+
+@dataclass
+class SelfEnergy:
+    nw: int
+    beta: float
+    sigma: torch.Tensor                 # complex128 [nw, nc, nc]
+    sigma_inf: Optional[torch.Tensor]   # complex128 [nc, nc] or None
+    e_dc: torch.Tensor                  # float64 [nc]
+
+    @classmethod
+    def from_host(cls, sig, device="cuda"):
+        si = None if sig.sigma_inf is None else torch.as_tensor(
+            np.ascontiguousarray(sig.sigma_inf, np.complex128), device=device)
+        return cls(int(sig.nw), float(sig.beta),
+                   torch.as_tensor(np.ascontiguousarray(sig.sigma, np.complex128), device=device), si,
+                   torch.as_tensor(np.ascontiguousarray(sig.e_dc, np.float64), device=device))
+
+    def struct(self):
+        return DmftSigma(self.nw, self.beta, _ptr(self.sigma), _ptr(self.sigma_inf), _ptr(self.e_dc))
+
+
+class Context:
+    """One library handle on one GPU plus a cached workspace."""
+
+    def __init__(self, device: int = 0):
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        code = self.lib.dmft_create(C.byref(h), device)
+        if code:
+            raise _lib.DmftError(code, "dmft_create")
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if self.h:
+            self.lib.dmft_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ workspace
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            ws[:256].zero_()
+            assert ws.data_ptr() % 256 == 0
+            self._ws = ws
+        return self._ws
+
+    def workspace_size(self, lat: Lattice, sig: SelfEnergy) -> int:
+        n = C.c_size_t()
+        ls, ss = lat.struct(), sig.struct()
+        check(self.h, self.lib.dmft_workspace_size(self.h, C.byref(ls), C.byref(ss), C.byref(n)))
+        return int(n.value)
+
+    def _call_ws(self, lat, sig):
+        ws = self.workspace(self.workspace_size(lat, sig))
+        return ws, C.c_size_t(ws.numel())
+
+    # ------------------------------------------------------------------ entry points
+    def gloc_compute(self, lat: Lattice, sig: SelfEnergy, mu: float) -> torch.Tensor:
+        gloc = torch.empty((sig.nw, lat.nc, lat.nc), dtype=torch.complex128, device=self.device)
+        ws, nws = self._call_ws(lat, sig)
+        ls, ss = lat.struct(), sig.struct()
+        check(self.h, self.lib.gloc_compute(self.h, C.byref(ls), C.byref(ss), float(mu), _ptr(gloc),
+                                            _ptr(ws), nws, _stream(self.device)))
+        return gloc
+
+    def density_matrix(self, lat: Lattice, sig: SelfEnergy, mu: float, tail_order: int = 2, nk=True,
+                       gloc=True, scalars=True):
+        """Returns (nk_flat or None, gloc or None, scalars or None); nk_flat holds
+        N(k) for all k concatenated (nb_k x nb_k each); scalars = [N_tot, n_corr, <H_KS>]."""
+        nk_t = torch.empty(lat.n_size(), dtype=torch.complex128, device=self.device) if nk else None
+        gl_t = torch.empty((sig.nw, lat.nc, lat.nc), dtype=torch.complex128, device=self.device) if gloc else None
+        sc_t = torch.empty(3, dtype=torch.float64, device=self.device) if scalars else None
+        ws, nws = self._call_ws(lat, sig)
+        ls, ss = lat.struct(), sig.struct()
+        check(self.h, self.lib.density_matrix(self.h, C.byref(ls), C.byref(ss), float(mu), int(tail_order),
+                                              _ptr(nk_t), _ptr(gl_t), _ptr(sc_t), _ptr(ws), nws,
+                                              _stream(self.device)))
+        return nk_t, gl_t, sc_t
+
+    def dmft_ntot(self, lat: Lattice, sig: SelfEnergy, mu: float, tail_order: int = 2) -> torch.Tensor:
+        """[N_tot(mu), dN_tot/dmu] on the device."""
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        ws, nws = self._call_ws(lat, sig)
+        ls, ss = lat.struct(), sig.struct()
+        check(self.h, self.lib.dmft_ntot(self.h, C.byref(ls), C.byref(ss), float(mu), int(tail_order),
+                                         _ptr(out), _ptr(ws), nws, _stream(self.device)))
+        return out
+
+    def density_matrix_vjp(self, lat: Lattice, sig: SelfEnergy, mu: float, nk_bar=None, gloc_bar=None,
+                           tail_order: int = 2):
+        """(sigma_bar [nw, nc, nc] complex128, mu_bar [1] float64) on the device."""
+        sb = torch.empty((sig.nw, lat.nc, lat.nc), dtype=torch.complex128, device=self.device)
+        mb = torch.empty(1, dtype=torch.float64, device=self.device)
+        nkb = None if nk_bar is None else nk_bar.contiguous()
+        gb = None if gloc_bar is None else gloc_bar.contiguous()
+        ws, nws = self._call_ws(lat, sig)
+        ls, ss = lat.struct(), sig.struct()
+        check(self.h, self.lib.density_matrix_vjp(self.h, C.byref(ls), C.byref(ss), float(mu), int(tail_order),
+                                                  _ptr(nkb), _ptr(gb), _ptr(sb), _ptr(mb), _ptr(ws), nws,
+                                                  _stream(self.device)))
+        return sb, mb
+
+    def find_mu(self, lat: Lattice, sig: SelfEnergy, n_target: float, tol_n: float = 1e-8, method=NEWTON,
+                mu_lo: float = -40.0, mu_hi: float = 40.0, mu0: Optional[float] = None, max_iter: int = 200,
+                tail_order: int = 2):
+        """(mu, passes, N(mu))."""
+        ws, nws = self._call_ws(lat, sig)
+        ls, ss = lat.struct(), sig.struct()
+        mu, passes, n = C.c_double(), C.c_int(), C.c_double()
+        m0 = 0.5 * (mu_lo + mu_hi) if mu0 is None else mu0
+        check(self.h, self.lib.find_mu(self.h, C.byref(ls), C.byref(ss), int(tail_order), float(n_target),
+                                       float(tol_n), int(method), float(mu_lo), float(mu_hi), float(m0),
+                                       int(max_iter), C.byref(mu), C.byref(passes), C.byref(n), _ptr(ws), nws,
+                                       _stream(self.device)))
+        return mu.value, passes.value, n.value
+
+    def timing(self, enable: bool):
+        """Returns (summed Dyson-kernel ms, timed launches) recorded so far."""
+        ms, n = C.c_double(), C.c_int64()
+        check(self.h, self.lib.dmft_timing(self.h, 1 if enable else 0, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def sync_status(self):
+        ws = self._ws
+        check(self.h, self.lib.dmft_sync_status(self.h, _ptr(ws) if ws is not None else None,
+                                                _stream(self.device)))
+
+
+def split_nk(nk_flat: torch.Tensor, lat: Lattice) -> List[torch.Tensor]:
+    out, o = [], 0
+    for n in lat.nb_array():
+        n = int(n)
+        out.append(nk_flat[o:o + n * n].reshape(n, n))
+        o += n * n
+    return out
