@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-mu", action="store_true", help="skip the mu-search comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
     ap.add_argument("--extra", action="store_true", help="also time the other workloads")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (use the default variants)")
     return ap.parse_args()
 
 
@@ -93,7 +94,7 @@ def cpu_baseline(wl, mu, target_s):
                       % (nsel, lat.nk, sig.nw, evals, t)}
 
 
-def mu_search(ctx):
+def mu_search(ctx, tune=True):
     import torch
 
     from paper_1111_2157_amd import synth
@@ -101,6 +102,8 @@ def mu_search(ctx):
 
     wl = synth.differentiation()
     lat, sig = Lattice.from_host(wl.lattice), SelfEnergy.from_host(wl.sigma)
+    if tune:
+        ctx.autotune(lat, sig, 0.0)
     ctx.dmft_ntot(lat, sig, 0.0)  # warm-up
     torch.cuda.synchronize()
     out = {"workload": wl.name, "n_target": wl.n_target, "tol": 1e-8, "bracket": [-40.0, 40.0]}
@@ -129,6 +132,12 @@ def main():
     lat, sig = Lattice.from_host(wl.lattice), SelfEnergy.from_host(wl.sigma)
     ctx = Context(0)
     mu = wl.mu
+    tune = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        rep = ctx.autotune(lat, sig, mu)
+        tune = {"seconds": time.perf_counter() - t0,
+                "best": [l for l in rep.splitlines() if l.startswith("best")]}
     sec, kms, launches = time_density(ctx, lat, sig, mu, args.steps, args.warmup)
     nk, nw, nb, nc = wl.lattice.nk, sig.nw, wl.lattice.nb_max, wl.lattice.nc
     evals = nk * nw
@@ -154,14 +163,17 @@ def main():
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "kernel": "dyson_kernel<32, density>", "kernel_ms": kavg * 1e3,
                      "flop_per_eval": flops_per_eval(nb, nc)},
+        "autotune": tune,
     }
     if not args.no_mu:
-        rec["mu_search"] = mu_search(ctx)
+        rec["mu_search"] = mu_search(ctx, not args.no_tune)
     if args.extra:
         extra = {}
         for name, maker in (("plain", synth.plain), ("f-shell", synth.f_shell), ("diff", synth.differentiation)):
             w = maker()
             l2, s2 = Lattice.from_host(w.lattice), SelfEnergy.from_host(w.sigma)
+            if not args.no_tune:
+                ctx.autotune(l2, s2, w.mu)
             sc, km, ln = time_density(ctx, l2, s2, w.mu, 3 if name != "plain" else 20, 1)
             ev = w.lattice.nk * s2.nw
             f = flops_per_eval(w.lattice.nb_max, w.lattice.nc) * ev

@@ -193,6 +193,15 @@ int dmft_batched_graph_launch(dmft_handle h, hipStream_t stream);
 int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu,
                   void* ws, size_t ws_bytes, hipStream_t stream, char* best_out, size_t best_len);
 
+/* Kernel variants.  kind 0 = density pass (density_matrix, gloc_compute),
+ * kind 1 = trace pass (dmft_ntot, find_mu); nbp = padded band-window size
+ * (16, 32 or 48).  dmft_variants writes up to max variant codes into out (HOST)
+ * and returns their number (the first is the default); dmft_set_variant pins
+ * one for later calls on this handle (var = -1 restores the default) and
+ * returns DMFT_EINVAL for a code that is not instantiated. */
+int dmft_variants(int kind, int nbp, int* out, int max);
+int dmft_set_variant(dmft_handle h, int kind, int nbp, int var);
+
 /* Kernel timing (for roofline reports).  enable = 1 clears the counters and
  * starts recording a pair of hipEvents around every launch of the Dyson kernel
  * (on the stream it is launched on); enable = 0 stops recording.  Every call

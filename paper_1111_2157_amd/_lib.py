@@ -16,7 +16,8 @@ EXPORTS = [
     "dmft_create", "dmft_destroy", "dmft_strerror", "dmft_last_error", "dmft_workspace_size",
     "gloc_compute", "density_matrix", "dmft_ntot", "density_matrix_vjp", "find_mu",
     "dmft_batched_workspace_size", "dmft_batched_plan", "dmft_batched_pass",
-    "dmft_batched_graph_capture", "dmft_batched_graph_launch", "dmft_autotune", "dmft_timing",
+    "dmft_batched_graph_capture", "dmft_batched_graph_launch", "dmft_autotune", "dmft_variants",
+    "dmft_set_variant", "dmft_timing",
     "dmft_sync_status",
 ]
 
@@ -72,6 +73,8 @@ def load():
         "dmft_batched_graph_capture": ([P, P, P, P, P, S, P], I),
         "dmft_batched_graph_launch": ([P, P], I),
         "dmft_autotune": ([P, lp, sp, D, P, S, P, C.c_char_p, S], I),
+        "dmft_variants": ([I, I, C.POINTER(I), I], I),
+        "dmft_set_variant": ([P, I, I, I], I),
         "dmft_timing": ([P, I, C.POINTER(D), C.POINTER(C.c_int64)], I),
         "dmft_sync_status": ([P, P, P], I),
     }

@@ -31,14 +31,9 @@ int nbp_of(int nb) {
 // Tiling of one launch: kt k-points per k-tile, wt frequencies per frequency tile.
 struct Tile {
   int kt = 1, wt = 1;
-  int var = -1;  // kernel variant (see launch_dyson); -1: default for the size
 };
 
-int default_var(int nbp, bool trace) {
-  if (trace) return nbp >= 48 ? 0 : 1;
-  if (nbp >= 48) return 2;
-  return 1;
-}
+enum { KIND_DENSITY = 0, KIND_TRACE = 1 };
 
 // One padded-size bucket of k-points.
 struct Bucket {
@@ -59,7 +54,9 @@ struct Layout {
   std::vector<int64_t> off_b, off_n;
   bool ragged = false;
   int nbp_max = 0;
+  int kind = KIND_DENSITY;
   Tile tile;
+  size_t tune_a = 0, tune_b = 0;  // autotuner scratch: two result copies
 };
 
 }  // namespace
@@ -70,7 +67,8 @@ struct dmft_handle_s {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   hipEvent_t staged = nullptr;      // recorded after the last upload from `pinned`
-  std::map<std::string, Tile> tune; // autotune cache keyed by shape
+  std::map<std::string, Tile> tune;  // autotuned tiles keyed by kind/size/nk/nw
+  std::map<std::string, int> tvar;   // autotuned kernel variant keyed by kind/size
   // batched plan
   struct Iter {
     dmft_lattice lat;
@@ -131,17 +129,19 @@ int check_shapes(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig) 
   return DMFT_OK;
 }
 
-Tile default_tile(const dmft_handle h, int nk, int nw, int nbp) {
+std::string tile_key(int kind, int nbp, int nk, int nw) {
   char key[96];
-  snprintf(key, sizeof key, "%d/%d/%d", nbp, nk, nw);
-  auto it = h->tune.find(key);
-  if (it != h->tune.end()) return it->second;
+  snprintf(key, sizeof key, "%d/%d/%d/%d", kind, nbp, nk, nw);
+  return key;
+}
+
+Tile heuristic_tile(int nk, int nw) {
   Tile t;
   // k-tile: keep the G_loc partials (nk/kt x nw x 4 KiB) near 1 GiB at most.
   double xbytes = (double)nk * nw * 4096.0;
   t.kt = std::max(1, (int)std::ceil(xbytes / (1u << 30)));
   t.kt = std::min(t.kt, std::max(1, nk / 4));
-  // frequency tile: aim at >= 4096 work-groups in total (>= 4 per SIMD slot).
+  // frequency tile: aim at >= 4096 work-groups in total (>= 2 per wavefront slot).
   int n_ktiles = (nk + t.kt - 1) / t.kt;
   int want_wtiles = std::max(1, (4096 + n_ktiles - 1) / n_ktiles);
   t.wt = std::max(4, (nw + want_wtiles - 1) / want_wtiles);
@@ -149,8 +149,22 @@ Tile default_tile(const dmft_handle h, int nk, int nw, int nbp) {
   return t;
 }
 
+Tile choose_tile(const dmft_handle h, int kind, int nk, int nw, int nbp) {
+  auto it = h->tune.find(tile_key(kind, nbp, nk, nw));
+  return it != h->tune.end() ? it->second : heuristic_tile(nk, nw);
+}
+
+int choose_var(const dmft_handle h, int kind, int nbp) {
+  char key[32];
+  snprintf(key, sizeof key, "%d/%d", kind, nbp);
+  auto it = h->tvar.find(key);
+  if (it != h->tvar.end()) return it->second;
+  int v[16];
+  return dyson_variants(nbp, kind, v, 16) > 0 ? v[0] : -1;
+}
+
 // Build the workspace layout for one lattice.
-int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, Layout& L,
+int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, Layout& L, int kind,
                 const Tile* force = nullptr) {
   int nk = lat->nk, nw = sig->nw;
   L.ragged = lat->nb != nullptr;
@@ -168,7 +182,8 @@ int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, L
       return fail(h, DMFT_EUNSUPPORTED, "no kernel variant for nb = %d", L.nb[k]);
   }
   L.nbp_max = *std::max_element(L.nbp.begin(), L.nbp.end());
-  L.tile = force ? *force : default_tile(h, nk, nw, L.nbp_max);
+  L.kind = kind;
+  L.tile = force ? *force : choose_tile(h, kind, nk, nw, L.nbp_max);
   L.tile.wt = std::max(1, std::min(L.tile.wt, nw));
   L.tile.kt = std::max(1, std::min(L.tile.kt, nk));
   L.n_wtiles = (nw + L.tile.wt - 1) / L.tile.wt;
@@ -205,6 +220,8 @@ int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, L
   L.tpart = take((size_t)L.n_wtiles * nk * 2 * sizeof(double));
   L.kscal = take((size_t)nk * 3 * sizeof(double));
   L.ktrace = take((size_t)nk * 2 * sizeof(double));
+  L.tune_a = take((size_t)nw * lat->nc * lat->nc * 16 + 64);
+  L.tune_b = take((size_t)nw * lat->nc * lat->nc * 16 + 64);
   L.total = o;
   return DMFT_OK;
 }
@@ -306,7 +323,7 @@ int run_dyson(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, con
       }
       HIPCHK(h, hipEventRecord(ev.first, s));
     }
-    int var = L.tile.var >= 0 ? L.tile.var : default_var(b.nbp, (mode & MODE_TRACE) != 0);
+    int var = choose_var(h, (mode & MODE_TRACE) ? KIND_TRACE : KIND_DENSITY, b.nbp);
     HIPCHK(h, launch_dyson(b.nbp, var, a, b.n_ktiles, s));
     if (h->timing) {
       HIPCHK(h, hipEventRecord(ev.second, s));
@@ -348,10 +365,10 @@ EpilogueArgs epilogue_args(const dmft_lattice* lat, const dmft_sigma* sig, const
 }
 
 int prepare(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, void* ws, size_t ws_bytes,
-            Layout& L, hipStream_t s) {
+            Layout& L, int kind, hipStream_t s) {
   int r = check_shapes(h, lat, sig);
   if (r) return r;
-  r = make_layout(h, lat, sig, L);
+  r = make_layout(h, lat, sig, L, kind);
   if (r) return r;
   r = check_ws(h, L, ws, ws_bytes);
   if (r) return r;
@@ -446,10 +463,12 @@ int dmft_workspace_size(dmft_handle h, const dmft_lattice* lat, const dmft_sigma
   if (!bytes) return fail(h, DMFT_EINVAL, "bytes is NULL");
   int r = check_shapes(h, lat, sig);
   if (r) return r;
-  Layout L;
-  r = make_layout(h, lat, sig, L);
+  Layout L, L2;
+  r = make_layout(h, lat, sig, L, KIND_DENSITY);
   if (r) return r;
-  *bytes = L.total;
+  r = make_layout(h, lat, sig, L2, KIND_TRACE);
+  if (r) return r;
+  *bytes = std::max(L.total, L2.total);
   return DMFT_OK;
 }
 
@@ -457,7 +476,7 @@ int gloc_compute(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, 
                  void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!gloc) return fail(h, DMFT_EINVAL, "gloc is NULL");
   Layout L;
-  int r = prepare(h, lat, sig, ws, ws_bytes, L, stream);
+  int r = prepare(h, lat, sig, ws, ws_bytes, L, KIND_DENSITY, stream);
   if (r) return r;
   return density_impl(h, lat, sig, L, (char*)ws, mu, nullptr, 2, nullptr, gloc, nullptr, stream);
 }
@@ -469,7 +488,7 @@ int density_matrix(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig
   if (!nk && !gloc && !scalars) return fail(h, DMFT_EINVAL, "no output requested");
   if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
   Layout L;
-  int r = prepare(h, lat, sig, ws, ws_bytes, L, stream);
+  int r = prepare(h, lat, sig, ws, ws_bytes, L, KIND_DENSITY, stream);
   if (r) return r;
   return density_impl(h, lat, sig, L, (char*)ws, mu, nullptr, tail_order, nk, gloc, scalars, stream);
 }
@@ -480,9 +499,35 @@ int dmft_ntot(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, dou
   if (!out) return fail(h, DMFT_EINVAL, "out is NULL");
   if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
   Layout L;
-  int r = prepare(h, lat, sig, ws, ws_bytes, L, stream);
+  int r = prepare(h, lat, sig, ws, ws_bytes, L, KIND_TRACE, stream);
   if (r) return r;
   return ntot_impl(h, lat, sig, L, (char*)ws, mu, nullptr, tail_order, out, stream);
+}
+
+int dmft_variants(int kind, int nbp, int* out, int max) {
+  if (kind != 0 && kind != 1) return 0;
+  int v[16];
+  int n = dyson_variants(nbp, kind, v, 16);
+  for (int i = 0; i < n && i < max && out; ++i) out[i] = v[i];
+  return n;
+}
+
+int dmft_set_variant(dmft_handle h, int kind, int nbp, int var) {
+  if (!h) return DMFT_EINVAL;
+  char key[32];
+  snprintf(key, sizeof key, "%d/%d", kind, nbp);
+  if (var < 0) {
+    h->tvar.erase(key);
+    return DMFT_OK;
+  }
+  int v[16];
+  int n = dyson_variants(nbp, kind, v, 16);
+  for (int i = 0; i < n; ++i)
+    if (v[i] == var) {
+      h->tvar[key] = var;
+      return DMFT_OK;
+    }
+  return fail(h, DMFT_EINVAL, "variant %d not instantiated for kind %d, nbp %d", var, kind, nbp);
 }
 
 int dmft_timing(dmft_handle h, int enable, double* kernel_ms, int64_t* launches) {
@@ -527,7 +572,7 @@ int find_mu(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, int t
     return fail(h, DMFT_EINVAL, "need finite mu_lo < mu_hi");
   if (!(tol_n > 0) || max_iter < 1) return fail(h, DMFT_EINVAL, "need tol_n > 0 and max_iter >= 1");
   Layout L;
-  int r = prepare(h, lat, sig, ws, ws_bytes, L, stream);
+  int r = prepare(h, lat, sig, ws, ws_bytes, L, KIND_TRACE, stream);
   if (r) return r;
   char* w = (char*)ws;
   double* dout = (double*)(w + L.out2);
@@ -617,9 +662,115 @@ int dmft_batched_graph_capture(dmft_handle h, const double*, double* const*, dou
 int dmft_batched_graph_launch(dmft_handle h, hipStream_t) {
   return fail(h, DMFT_EUNSUPPORTED, "batched: not built yet");
 }
-int dmft_autotune(dmft_handle h, const dmft_lattice*, const dmft_sigma*, double, void*, size_t, hipStream_t,
-                  char*, size_t) {
-  return fail(h, DMFT_EUNSUPPORTED, "autotune: not built yet");
+
+
+
+// Autotuner: for each kind (density pass, trace pass) time every instantiated
+// kernel variant of the shape's largest padded size on a few frequency-tile
+// sizes, after checking that each candidate reproduces the default candidate
+// (G_loc and the scalars, or N and dN/dmu, to 1e-11 relative); keep the fastest.
+int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu, void* ws,
+                  size_t ws_bytes, hipStream_t stream, char* best_out, size_t best_len) {
+  int r = check_shapes(h, lat, sig);
+  if (r) return r;
+  if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
+  HIPCHK(h, hipSetDevice(h->device));
+  char* w = (char*)ws;
+  std::string report;
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  for (int kind : {KIND_DENSITY, KIND_TRACE}) {
+    Layout L0;
+    r = make_layout(h, lat, sig, L0, kind);
+    if (r) return r;
+    r = check_ws(h, L0, ws, ws_bytes);
+    if (r) return r;
+    int nbp = L0.nbp_max, nk = lat->nk, nw = sig->nw, nc = lat->nc;
+    int vars[16];
+    int nv = dyson_variants(nbp, kind, vars, 16);
+    Tile base = heuristic_tile(nk, nw);
+    std::vector<Tile> tiles;
+    for (int f : {1, 2, 4, 8}) {
+      Tile t = base;
+      t.wt = std::max(4, std::min(nw, base.wt * f / 2));
+      bool dup = false;
+      for (auto& u : tiles) dup |= (u.wt == t.wt && u.kt == t.kt);
+      if (!dup) tiles.push_back(t);
+    }
+    size_t nres = kind == KIND_DENSITY ? (size_t)nw * nc * nc * 2 + 3 : 2;
+    std::vector<double> ref(nres), got(nres);
+    bool have_ref = false;
+    double best_ms = 1e300;
+    Tile best_tile = base;
+    int best_var = vars[0];
+    char key[32];
+    snprintf(key, sizeof key, "%d/%d", kind, nbp);
+    for (int vi = 0; vi < nv; ++vi) {
+      h->tvar[key] = vars[vi];
+      for (const Tile& t : tiles) {
+        Layout L;
+        r = make_layout(h, lat, sig, L, kind, &t);
+        if (r) return r;
+        if (check_ws(h, L, ws, ws_bytes)) continue;
+        r = upload_meta(h, L, w, stream, true);
+        if (r) return r;
+        double* out = (double*)(w + (have_ref ? L.tune_b : L.tune_a));
+        auto run = [&]() -> int {
+          if (kind == KIND_DENSITY)
+            return density_impl(h, lat, sig, L, w, mu, nullptr, 2, nullptr, out, out + (size_t)nw * nc * nc * 2,
+                                stream);
+          return ntot_impl(h, lat, sig, L, w, mu, nullptr, 2, out, stream);
+        };
+        r = run();
+        if (r) return r;
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIPCHK(h, hipEventRecord(e0, stream));
+          r = run();
+          if (r) return r;
+          HIPCHK(h, hipEventRecord(e1, stream));
+          HIPCHK(h, hipEventSynchronize(e1));
+          float m = 0.f;
+          HIPCHK(h, hipEventElapsedTime(&m, e0, e1));
+          ms = std::min(ms, m);
+        }
+        HIPCHK(h, hipMemcpy(have_ref ? got.data() : ref.data(), out, nres * sizeof(double), hipMemcpyDeviceToHost));
+        bool ok = true;
+        if (have_ref) {
+          double dn = 0.0, rn = 0.0;
+          for (size_t i = 0; i < nres; ++i) {
+            dn = std::max(dn, std::fabs(got[i] - ref[i]));
+            rn = std::max(rn, std::fabs(ref[i]));
+          }
+          ok = std::isfinite(dn) && dn <= 1e-11 * std::max(rn, 1e-300);
+        }
+        have_ref = true;
+        char line[160];
+        snprintf(line, sizeof line, "%s nbp=%d var=%d kt=%d wt=%d: %.3f ms%s\n",
+                 kind == KIND_DENSITY ? "density" : "trace", nbp, vars[vi], t.kt, t.wt, ms, ok ? "" : " (rejected)");
+        report += line;
+        if (ok && ms < best_ms) {
+          best_ms = ms;
+          best_tile = t;
+          best_var = vars[vi];
+        }
+      }
+    }
+    h->tvar[key] = best_var;
+    h->tune[tile_key(kind, nbp, nk, nw)] = best_tile;
+    char line[160];
+    snprintf(line, sizeof line, "best %s: var=%d kt=%d wt=%d %.3f ms\n", kind == KIND_DENSITY ? "density" : "trace",
+             best_var, best_tile.kt, best_tile.wt, best_ms);
+    report += line;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best_out && best_len) {
+    strncpy(best_out, report.c_str(), best_len - 1);
+    best_out[best_len - 1] = 0;
+  }
+  return DMFT_OK;
 }
 
 }  // extern "C"

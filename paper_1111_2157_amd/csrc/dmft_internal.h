@@ -76,8 +76,11 @@ struct EpilogueArgs {
 
 // Launchers (return hipError_t of the launch).
 // var: kernel variant, bit 0 = next-step pivot column read ahead (PF), bit 1 =
-// running sum of G in LDS (SLDS, density kind only; forced for nbp = 48).
+// running sum of G in LDS (SLDS, density kind only), bit 2 = two wavefronts per
+// SIMD.  dyson_variants lists the instantiated variants of a size and kind
+// (kind 0 = density, 1 = trace); the first one is the default.
 hipError_t launch_dyson(int nbp, int var, const DysonArgs& a, int n_ktiles, hipStream_t s);
+int dyson_variants(int nbp, int kind, int* out, int max);
 bool dyson_supported(int nbp);
 hipError_t launch_nk_epilogue(const EpilogueArgs& a, double* nk_out, hipStream_t s);
 hipError_t launch_trace_epilogue(const EpilogueArgs& a, hipStream_t s);

@@ -535,47 +535,30 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
   if (nonfinite) atomicOr(a.err, ERR_NONFINITE);
 }
 
-// Launch one variant: var bit 0 = PF, bit 1 = SLDS (density only).
-template <int NBP>
-hipError_t launch_dyson_nbp(int var, const DysonArgs& a, dim3 grid, hipStream_t s);
+// Kernel variants: bit 0 = PF, bit 1 = SLDS (density only), bit 2 = two
+// wavefronts per SIMD (register budget 256).  Each size instantiates the
+// variants listed in its unit; launch_variant returns hipErrorInvalidValue for
+// the others.
+template <int NBP, int KIND, int VAR>
+hipError_t launch_one(const DysonArgs& a, dim3 grid, hipStream_t s) {
+  hipLaunchKernelGGL((dyson_kernel<NBP, KIND, VAR & 1, (VAR >> 1) & 1, (VAR & 4) ? 2 : 1>), grid, dim3(64), 0, s,
+                     a);
+  return hipGetLastError();
+}
 
-#define DMFT_DEFINE_LAUNCH(N)                                                                              \
-  template <>                                                                                              \
-  hipError_t launch_dyson_nbp<N>(int var, const DysonArgs& a, dim3 grid, hipStream_t s) {                 \
-    dim3 block(64);                                                                                        \
-    if (a.mode & MODE_TRACE) {                                                                             \
-      if (var & 1)                                                                                         \
-        hipLaunchKernelGGL((dyson_kernel<N, KIND_TRACE, 1, 0>), grid, block, 0, s, a);                     \
-      else                                                                                                 \
-        hipLaunchKernelGGL((dyson_kernel<N, KIND_TRACE, 0, 0>), grid, block, 0, s, a);                     \
-    } else {                                                                                               \
-      switch (var & 3) {                                                                                   \
-        case 0: hipLaunchKernelGGL((dyson_kernel<N, KIND_DENSITY, 0, 0>), grid, block, 0, s, a); break;    \
-        case 1: hipLaunchKernelGGL((dyson_kernel<N, KIND_DENSITY, 1, 0>), grid, block, 0, s, a); break;    \
-        case 2: hipLaunchKernelGGL((dyson_kernel<N, KIND_DENSITY, 0, 1>), grid, block, 0, s, a); break;    \
-        default: hipLaunchKernelGGL((dyson_kernel<N, KIND_DENSITY, 1, 1>), grid, block, 0, s, a); break;   \
-      }                                                                                                    \
-    }                                                                                                      \
-    return hipGetLastError();                                                                              \
+template <int NBP, int KIND, int... VARS>
+struct VariantSet {
+  static hipError_t launch(int var, const DysonArgs& a, dim3 grid, hipStream_t s) {
+    hipError_t r = hipErrorInvalidValue;
+    bool hit = ((var == VARS ? (r = launch_one<NBP, KIND, VARS>(a, grid, s), true) : false) || ...);
+    (void)hit;
+    return r;
   }
-
-// Sizes whose running sum of G only fits in LDS: the density variants keep SLDS = 1.
-#define DMFT_DEFINE_LAUNCH_SLDS(N)                                                                         \
-  template <>                                                                                              \
-  hipError_t launch_dyson_nbp<N>(int var, const DysonArgs& a, dim3 grid, hipStream_t s) {                 \
-    dim3 block(64);                                                                                        \
-    if (a.mode & MODE_TRACE) {                                                                             \
-      if (var & 1)                                                                                         \
-        hipLaunchKernelGGL((dyson_kernel<N, KIND_TRACE, 1, 0>), grid, block, 0, s, a);                     \
-      else                                                                                                 \
-        hipLaunchKernelGGL((dyson_kernel<N, KIND_TRACE, 0, 0>), grid, block, 0, s, a);                     \
-    } else {                                                                                               \
-      if (var & 1)                                                                                         \
-        hipLaunchKernelGGL((dyson_kernel<N, KIND_DENSITY, 1, 1>), grid, block, 0, s, a);                   \
-      else                                                                                                 \
-        hipLaunchKernelGGL((dyson_kernel<N, KIND_DENSITY, 0, 1>), grid, block, 0, s, a);                   \
-    }                                                                                                      \
-    return hipGetLastError();                                                                              \
+  static int list(int* out, int max) {
+    int n = 0;
+    ((n < max ? (out[n++] = VARS, 0) : 0), ...);
+    return n;
   }
+};
 
 }  // namespace dmft

@@ -185,6 +185,25 @@ class Context:
                                        _stream(self.device)))
         return mu.value, passes.value, n.value
 
+    def autotune(self, lat: Lattice, sig: SelfEnergy, mu: float) -> str:
+        """Times the kernel variants and tile sizes of this shape and keeps the
+        fastest in the handle; returns the library's report."""
+        ws = self.workspace(2 * self.workspace_size(lat, sig))
+        nws = C.c_size_t(ws.numel())
+        ls, ss = lat.struct(), sig.struct()
+        buf = C.create_string_buffer(8192)
+        check(self.h, self.lib.dmft_autotune(self.h, C.byref(ls), C.byref(ss), float(mu), _ptr(ws), nws,
+                                             _stream(self.device), buf, 8192))
+        return buf.value.decode()
+
+    def variants(self, kind: int, nbp: int):
+        buf = (C.c_int * 16)()
+        n = self.lib.dmft_variants(int(kind), int(nbp), buf, 16)
+        return list(buf[:n])
+
+    def set_variant(self, kind: int, nbp: int, var: int):
+        check(self.h, self.lib.dmft_set_variant(self.h, int(kind), int(nbp), int(var)))
+
     def timing(self, enable: bool):
         """Returns (summed Dyson-kernel ms, timed launches) recorded so far."""
         ms, n = C.c_double(), C.c_int64()

@@ -156,3 +156,48 @@ def test_invalid_arguments_rejected_before_launch(ctx):
     with pytest.raises(DmftError) as e:
         ctx.density_matrix(dl, ds, 0.0)
     assert e.value.name == "DMFT_EINVAL"
+
+
+def test_autotune_then_parity(ctx):
+    from paper_1111_2157_amd.dyson import Context, Lattice, SelfEnergy
+
+    c = Context(0)
+    wl = synth.d_shell(nk=32, nw=128)
+    dl, ds = Lattice.from_host(wl.lattice), SelfEnergy.from_host(wl.sigma)
+    rep = c.autotune(dl, ds, 0.1)
+    assert "best density" in rep and "best trace" in rep
+    assert "rejected" not in rep, rep
+    mats, gl, sc = gpu_density(c, wl, 0.1)
+    assert_nk_parity(mats, wl.lattice, wl.sigma, 0.1)
+    assert_gloc_parity(gl, wl.lattice, wl.sigma, 0.1)
+    out = c.dmft_ntot(dl, ds, 0.1).cpu().numpy()
+    n, d = oracle.trace(wl.lattice, wl.sigma, 0.1)
+    assert abs(out[0] - n) <= RTOL * abs(n) and abs(out[1] - d) <= RTOL * abs(d)
+    c.close()
+
+
+VARIANT_CASES = [(16, lambda: synth.plain(nk=6, nw=40), -1.0), (32, lambda: synth.d_shell(nk=8, nw=40), 0.0),
+                 (48, lambda: synth.f_shell(nk=6, nw=32), 0.1)]
+
+
+@pytest.mark.parametrize("nbp,maker,mu", VARIANT_CASES)
+def test_every_kernel_variant_matches_oracle(nbp, maker, mu):
+    from paper_1111_2157_amd.dyson import Context, Lattice, SelfEnergy
+
+    wl = maker()
+    c = Context(0)
+    dl, ds = Lattice.from_host(wl.lattice), SelfEnergy.from_host(wl.sigma)
+    n_ref, d_ref = oracle.trace(wl.lattice, wl.sigma, mu)
+    for var in c.variants(0, nbp):
+        print("density variant", nbp, var, flush=True)
+        c.set_variant(0, nbp, var)
+        mats, gl, sc = gpu_density(c, wl, mu)
+        assert_nk_parity(mats, wl.lattice, wl.sigma, mu)
+        assert_gloc_parity(gl, wl.lattice, wl.sigma, mu)
+    for var in c.variants(1, nbp):
+        print("trace variant", nbp, var, flush=True)
+        c.set_variant(1, nbp, var)
+        out = c.dmft_ntot(dl, ds, mu).cpu().numpy()
+        c.sync_status()
+        assert abs(out[0] - n_ref) <= RTOL * abs(n_ref) and abs(out[1] - d_ref) <= RTOL * abs(d_ref)
+    c.close()
