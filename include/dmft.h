@@ -148,6 +148,17 @@ int density_matrix_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma*
                        double* sigma_bar, double* mu_bar, void* ws, size_t ws_bytes,
                        hipStream_t stream);
 
+/* Fused scalar adjoint of N_tot in one pass (the derivative of the Dyson and
+ * Matsubara-sum steps, Sec. 3.3 eqs. rho_LDA+DMFT and fix_mu):
+ *   out:       DEVICE [2] = { N_tot(mu), dN_tot/dmu } (as dmft_ntot), or NULL;
+ *   sigma_bar: DEVICE [nw][nc][nc] complex
+ *              dN_tot/dSigma(i w_n) = (2/beta) [ sum_k w_k S_k G_kn^2 S_k^dag ]^dag
+ *              in PyTorch's complex convention, or NULL.  Equal to
+ *              density_matrix_vjp with nk_bar_k = w_k I and no gloc_bar. */
+int dmft_ntot_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu,
+                  int tail_order, double* sigma_bar, double* out, void* ws, size_t ws_bytes,
+                  hipStream_t stream);
+
 /* Chemical potential with N_tot(mu) = n_target (Sec. 3.3 eq. fix_mu).
  *   method DMFT_NEWTON: Newton steps with dN/dmu from the adjoint, kept inside
  *     the bracket [mu_lo, mu_hi] (a step leaving the bracket, or not shrinking

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libdmft.so")
 # Every symbol declared in include/dmft.h.
 EXPORTS = [
     "dmft_create", "dmft_destroy", "dmft_strerror", "dmft_last_error", "dmft_workspace_size",
-    "gloc_compute", "density_matrix", "dmft_ntot", "density_matrix_vjp", "find_mu",
+    "gloc_compute", "density_matrix", "dmft_ntot", "dmft_ntot_vjp", "density_matrix_vjp", "find_mu",
     "dmft_batched_workspace_size", "dmft_batched_plan", "dmft_batched_pass",
     "dmft_batched_graph_capture", "dmft_batched_graph_launch", "dmft_autotune", "dmft_variants",
     "dmft_set_variant", "dmft_timing",
@@ -66,6 +66,7 @@ def load():
         "density_matrix": ([P, lp, sp, D, I, P, P, P, P, S, P], I),
         "dmft_ntot": ([P, lp, sp, D, I, P, P, S, P], I),
         "density_matrix_vjp": ([P, lp, sp, D, I, P, P, P, P, P, S, P], I),
+        "dmft_ntot_vjp": ([P, lp, sp, D, I, P, P, P, S, P], I),
         "find_mu": ([P, lp, sp, I, D, D, I, D, D, D, I, C.POINTER(D), C.POINTER(I), C.POINTER(D), P, S, P], I),
         "dmft_batched_workspace_size": ([P, I, P, P, C.POINTER(S)], I),
         "dmft_batched_plan": ([P, I, P, P, I, P, S, P], I),

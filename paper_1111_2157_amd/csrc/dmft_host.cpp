@@ -33,7 +33,7 @@ struct Tile {
   int kt = 1, wt = 1;
 };
 
-enum { KIND_DENSITY = 0, KIND_TRACE = 1 };
+enum { KIND_DENSITY = 0, KIND_TRACE = 1, KIND_ADJOINT = 2 };
 
 // One padded-size bucket of k-points.
 struct Bucket {
@@ -217,7 +217,7 @@ int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, L
   L.meta_klist = take(sizeof(int32_t) * nk);
   L.spart = take((size_t)L.n_wtiles * nk * L.s_stride * 16);
   L.xpart = take((size_t)L.n_ktiles_total * nw * 256 * 16);
-  L.tpart = take((size_t)L.n_wtiles * nk * 2 * sizeof(double));
+  L.tpart = take((size_t)L.n_wtiles * nk * 3 * sizeof(double));
   L.kscal = take((size_t)nk * 3 * sizeof(double));
   L.ktrace = take((size_t)nk * 2 * sizeof(double));
   L.tune_a = take((size_t)nw * lat->nc * lat->nc * 16 + 64);
@@ -281,8 +281,14 @@ double sum_inv_w2(int nw, double beta) {
 }
 
 // Enqueue the Dyson kernel(s) for all buckets with the given mode.
+struct AdjReq {
+  int gen = -1;  // -1: Dyson kernel; 0/1: adjoint kernel generation
+  const double* nbar = nullptr;
+  const double* gbar = nullptr;
+};
+
 int run_dyson(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, const Layout& L,
-              char* ws, double mu, const double* mu_ptr, int mode, hipStream_t s) {
+              char* ws, double mu, const double* mu_ptr, int mode, hipStream_t s, const AdjReq& adj = AdjReq()) {
   DysonArgs a{};
   a.nk = lat->nk;
   a.nc = lat->nc;
@@ -323,8 +329,13 @@ int run_dyson(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, con
       }
       HIPCHK(h, hipEventRecord(ev.first, s));
     }
-    int var = choose_var(h, (mode & MODE_TRACE) ? KIND_TRACE : KIND_DENSITY, b.nbp);
-    HIPCHK(h, launch_dyson(b.nbp, var, a, b.n_ktiles, s));
+    if (adj.gen >= 0) {
+      HIPCHK(h, launch_adjoint(b.nbp, adj.gen, a, adj.nbar, L.ragged ? (const int64_t*)(ws + L.meta_offn) : nullptr,
+                               adj.gbar, (double*)(ws + L.xpart), (double*)(ws + L.tpart), b.n_ktiles, s));
+    } else {
+      int var = choose_var(h, (mode & MODE_TRACE) ? KIND_TRACE : KIND_DENSITY, b.nbp);
+      HIPCHK(h, launch_dyson(b.nbp, var, a, b.n_ktiles, s));
+    }
     if (h->timing) {
       HIPCHK(h, hipEventRecord(ev.second, s));
       h->tev.push_back(ev);
@@ -468,7 +479,10 @@ int dmft_workspace_size(dmft_handle h, const dmft_lattice* lat, const dmft_sigma
   if (r) return r;
   r = make_layout(h, lat, sig, L2, KIND_TRACE);
   if (r) return r;
-  *bytes = std::max(L.total, L2.total);
+  Layout L3;
+  r = make_layout(h, lat, sig, L3, KIND_ADJOINT);
+  if (r) return r;
+  *bytes = std::max(std::max(L.total, L2.total), L3.total);
   return DMFT_OK;
 }
 
@@ -548,6 +562,61 @@ int dmft_timing(dmft_handle h, int enable, double* kernel_ms, int64_t* launches)
     h->t_count = 0;
   }
   h->timing = enable != 0;
+  return DMFT_OK;
+}
+
+int dmft_ntot_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu, int tail_order,
+                  double* sigma_bar, double* out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (tail_order != 0 && tail_order != 2) return fail(h, DMFT_EINVAL, "tail_order must be 0 or 2");
+  if (!sigma_bar && !out) return fail(h, DMFT_EINVAL, "no output requested");
+  if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
+  Layout L;
+  int r = prepare(h, lat, sig, ws, ws_bytes, L, KIND_ADJOINT, stream);
+  if (r) return r;
+  char* w = (char*)ws;
+  AdjReq adj;
+  adj.gen = 0;
+  r = run_dyson(h, lat, sig, L, w, mu, nullptr, 0, stream, adj);
+  if (r) return r;
+  EpilogueArgs e = epilogue_args(lat, sig, L, w, mu, nullptr, tail_order);
+  if (out) {
+    HIPCHK(h, launch_adj_epilogue(e, nullptr, stream));
+    // per-k values are [tr N, d tr N/dmu, mubar_k]: reduce all three, return the first two
+    HIPCHK(h, launch_scalar_reduce_mask(lat->nk, lat->wk, e.kscal, 3, 4, (double*)(w + L.out2), stream));
+    HIPCHK(h, hipMemcpyAsync(out, w + L.out2, 2 * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  }
+  if (sigma_bar)
+    HIPCHK(h, launch_sigma_bar_reduce(L.n_ktiles_total, sig->nw, lat->nc, (const double*)(w + L.xpart),
+                                      2.0 / sig->beta, 1, sigma_bar, stream));
+  return DMFT_OK;
+}
+
+int density_matrix_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu, int tail_order,
+                       const double* nk_bar, const double* gloc_bar, double* sigma_bar, double* mu_bar, void* ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  if (tail_order != 0 && tail_order != 2) return fail(h, DMFT_EINVAL, "tail_order must be 0 or 2");
+  if (!sigma_bar) return fail(h, DMFT_EINVAL, "sigma_bar is NULL");
+  if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
+  Layout L;
+  int r = prepare(h, lat, sig, ws, ws_bytes, L, KIND_ADJOINT, stream);
+  if (r) return r;
+  char* w = (char*)ws;
+  AdjReq adj;
+  adj.gen = 1;
+  adj.nbar = nk_bar;
+  adj.gbar = gloc_bar;
+  r = run_dyson(h, lat, sig, L, w, mu, nullptr, 0, stream, adj);
+  if (r) return r;
+  HIPCHK(h, launch_sigma_bar_reduce(L.n_ktiles_total, sig->nw, lat->nc, (const double*)(w + L.xpart), 1.0, 0,
+                                    sigma_bar, stream));
+  if (mu_bar) {
+    EpilogueArgs e = epilogue_args(lat, sig, L, w, mu, nullptr, tail_order);
+    HIPCHK(h, launch_adj_epilogue(e, nk_bar, stream));
+    // mubar = sum_k mubar_k (unweighted: the k weights are inside C)
+    HIPCHK(h, launch_scalar_reduce_mask(lat->nk, lat->wk, e.kscal, 3, 4, (double*)(w + L.out2), stream));
+    HIPCHK(h, hipMemcpyAsync(mu_bar, w + L.out2 + 2 * sizeof(double), sizeof(double), hipMemcpyDeviceToDevice,
+                             stream));
+  }
   return DMFT_OK;
 }
 
@@ -639,10 +708,7 @@ int find_mu(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, int t
 }
 
 
-int density_matrix_vjp(dmft_handle h, const dmft_lattice*, const dmft_sigma*, double, int, const double*,
-                       const double*, double*, double*, void*, size_t, hipStream_t) {
-  return fail(h, DMFT_EUNSUPPORTED, "density_matrix_vjp: not built yet");
-}
+
 int dmft_batched_workspace_size(dmft_handle h, int, const dmft_lattice* const*, const dmft_sigma* const*,
                                 size_t*) {
   return fail(h, DMFT_EUNSUPPORTED, "batched: not built yet");

@@ -89,5 +89,16 @@ hipError_t launch_gloc_reduce(int n_ktiles, int nw, int nc, const double* xpart,
 hipError_t launch_scalar_reduce(int nk, const double* wk, const double* kvals, int nvals,
                                 double* out, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+// Adjoint kernel: gen 0 = fused scalar adjoint of N_tot (partials of w_k S G^2 S^dag),
+// gen 1 = general vector-Jacobian product.  tpart: [n_wtiles][nk][3].
+hipError_t launch_adjoint(int nbp, int gen, const DysonArgs& a, const double* nbar, const int64_t* off_n,
+                          const double* gbar, double* mpart, double* tpart, int n_ktiles, hipStream_t s);
+hipError_t launch_sigma_bar_reduce(int n_ktiles, int nw, int nc, const double* mpart, double scale, int dagger,
+                                   double* out, hipStream_t s);
+// Per-k [tr N, d tr N/dmu, mubar_k] from the adjoint partials (tail terms included).
+hipError_t launch_adj_epilogue(const EpilogueArgs& a, const double* nbar, hipStream_t s);
+// out[j] = sum_k weight_j(k) kvals[k][j], weight = w_k, or 1 where bit j of unit_mask is set.
+hipError_t launch_scalar_reduce_mask(int nk, const double* wk, const double* kvals, int nvals, int unit_mask,
+                                     double* out, hipStream_t s);
 
 }  // namespace dmft

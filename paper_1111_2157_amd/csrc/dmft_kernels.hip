@@ -180,6 +180,61 @@ __global__ void __launch_bounds__(64) trace_epilogue_kernel(EpilogueArgs a) {
   }
 }
 
+// Per-k [tr N, d tr N/dmu, mubar_k] from the adjoint kernel's [n_wtiles][nk][3]
+// partials; mubar_k gets the tail term (beta/4 - 2 s2/beta) Re tr Nbar_k.
+__global__ void __launch_bounds__(64) adj_epilogue_kernel(EpilogueArgs a, const double* nbar) {
+  __shared__ double red[64];
+  const int k = blockIdx.x;
+  const int nc = a.nc;
+  const int nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
+  const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
+  const int64_t on = a.nb_uniform > 0 ? (int64_t)k * nb * nb : a.off_n[k];
+  const double* eps = a.eps + ob;
+  const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
+  const double2* sinf = reinterpret_cast<const double2*>(a.sigma_inf);
+  const double mu = a.mu_ptr ? *a.mu_ptr : a.mu;
+  const double beta = a.beta;
+  double trm = 0.0, trn = 0.0;
+  for (int v = threadIdx.x; v < nb; v += blockDim.x) {
+    trm += eps[v] - mu;
+    for (int al = 0; al < nc; ++al)
+      for (int be = 0; be < nc; ++be) {
+        double2 m = sinf ? sinf[al * nc + be] : make_double2(0.0, 0.0);
+        if (al == be) m.x -= a.e_dc[al];
+        double2 pb = P[be * nb + v], pa = P[al * nb + v];
+        double2 ss = make_double2(pb.x * pa.x + pb.y * pa.y, pb.y * pa.x - pb.x * pa.y);
+        trm += m.x * ss.x - m.y * ss.y;
+      }
+    if (nbar) trn += reinterpret_cast<const double2*>(nbar)[on + (int64_t)v * nb + v].x;
+  }
+  trm = block_sum(trm, red);
+  trn = block_sum(trn, red);
+  if (threadIdx.x == 0) {
+    double trg = 0.0, trg2 = 0.0, mub = 0.0;
+    for (int w = 0; w < a.n_wtiles; ++w) {
+      const double* tp = a.tpart + ((int64_t)w * a.nk + k) * 3;
+      trg += tp[0];
+      trg2 += tp[1];
+      mub += tp[2];
+    }
+    double tr = 0.5 * nb + 2.0 * trg / beta;
+    double d = -2.0 * trg2 / beta;
+    if (a.tail_order == 2) {
+      tr += -0.25 * beta * trm + 2.0 * a.s2 * trm / beta;
+      d += 0.25 * beta * nb - 2.0 * a.s2 * nb / beta;
+      mub += (0.25 * beta - 2.0 * a.s2 / beta) * trn;
+    }
+    a.kscal[k * 3 + 0] = tr;
+    a.kscal[k * 3 + 1] = d;
+    a.kscal[k * 3 + 2] = mub;
+  }
+}
+
+hipError_t launch_adj_epilogue(const EpilogueArgs& a, const double* nbar, hipStream_t s) {
+  hipLaunchKernelGGL(adj_epilogue_kernel, dim3(a.nk), dim3(64), 0, s, a, nbar);
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256) gloc_reduce_kernel(int n_ktiles, int nw, int nc, const double* xpart,
                                                           double* gloc) {
   int n = blockIdx.x;
@@ -198,11 +253,12 @@ __global__ void __launch_bounds__(256) gloc_reduce_kernel(int n_ktiles, int nw, 
 }
 
 __global__ void __launch_bounds__(256) scalar_reduce_kernel(int nk, const double* wk, const double* kvals,
-                                                            int nvals, double* out) {
+                                                            int nvals, int unit_mask, double* out) {
   __shared__ double red[256];
   for (int j = 0; j < nvals; ++j) {
     double acc = 0.0;
-    for (int k = threadIdx.x; k < nk; k += blockDim.x) acc += wk[k] * kvals[(int64_t)k * nvals + j];
+    const bool unit = (unit_mask >> j) & 1;
+    for (int k = threadIdx.x; k < nk; k += blockDim.x) acc += (unit ? 1.0 : wk[k]) * kvals[(int64_t)k * nvals + j];
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) out[j] = acc;
   }
@@ -230,7 +286,13 @@ hipError_t launch_gloc_reduce(int n_ktiles, int nw, int nc, const double* xpart,
 
 hipError_t launch_scalar_reduce(int nk, const double* wk, const double* kvals, int nvals, double* out,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(scalar_reduce_kernel, dim3(1), dim3(256), 0, s, nk, wk, kvals, nvals, out);
+  hipLaunchKernelGGL(scalar_reduce_kernel, dim3(1), dim3(256), 0, s, nk, wk, kvals, nvals, 0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalar_reduce_mask(int nk, const double* wk, const double* kvals, int nvals, int unit_mask,
+                                     double* out, hipStream_t s) {
+  hipLaunchKernelGGL(scalar_reduce_kernel, dim3(1), dim3(256), 0, s, nk, wk, kvals, nvals, unit_mask, out);
   return hipGetLastError();
 }
 

@@ -171,6 +171,16 @@ class Context:
                                                   _stream(self.device)))
         return sb, mb
 
+    def dmft_ntot_vjp(self, lat: Lattice, sig: SelfEnergy, mu: float, tail_order: int = 2):
+        """(out [N_tot, dN/dmu] float64, dN/dSigma [nw, nc, nc] complex128) on the device."""
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        sb = torch.empty((sig.nw, lat.nc, lat.nc), dtype=torch.complex128, device=self.device)
+        ws, nws = self._call_ws(lat, sig)
+        ls, ss = lat.struct(), sig.struct()
+        check(self.h, self.lib.dmft_ntot_vjp(self.h, C.byref(ls), C.byref(ss), float(mu), int(tail_order),
+                                             _ptr(sb), _ptr(out), _ptr(ws), nws, _stream(self.device)))
+        return out, sb
+
     def find_mu(self, lat: Lattice, sig: SelfEnergy, n_target: float, tol_n: float = 1e-8, method=NEWTON,
                 mu_lo: float = -40.0, mu_hi: float = 40.0, mu0: Optional[float] = None, max_iter: int = 200,
                 tail_order: int = 2):
