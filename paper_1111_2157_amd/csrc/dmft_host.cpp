@@ -573,6 +573,7 @@ int dmft_ntot_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
   Layout L;
   int r = prepare(h, lat, sig, ws, ws_bytes, L, KIND_ADJOINT, stream);
   if (r) return r;
+  if (L.nbp_max > 48) return fail(h, DMFT_EUNSUPPORTED, "the adjoint supports band windows up to 48");
   char* w = (char*)ws;
   AdjReq adj;
   adj.gen = 0;
@@ -600,6 +601,7 @@ int density_matrix_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma*
   Layout L;
   int r = prepare(h, lat, sig, ws, ws_bytes, L, KIND_ADJOINT, stream);
   if (r) return r;
+  if (L.nbp_max > 48) return fail(h, DMFT_EUNSUPPORTED, "the adjoint supports band windows up to 48");
   char* w = (char*)ws;
   AdjReq adj;
   adj.gen = 1;

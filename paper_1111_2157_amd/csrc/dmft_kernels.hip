@@ -13,6 +13,8 @@ namespace dmft {
 hipError_t launch_dyson_16(int var, const DysonArgs& a, dim3 grid, hipStream_t s);
 hipError_t launch_dyson_32(int var, const DysonArgs& a, dim3 grid, hipStream_t s);
 hipError_t launch_dyson_48(int var, const DysonArgs& a, dim3 grid, hipStream_t s);
+hipError_t launch_dyson_64(int var, const DysonArgs& a, dim3 grid, hipStream_t s);
+int variants_64(int kind, int* out, int max);
 int variants_16(int kind, int* out, int max);
 int variants_32(int kind, int* out, int max);
 int variants_48(int kind, int* out, int max);
@@ -22,11 +24,12 @@ int dyson_variants(int nbp, int kind, int* out, int max) {
     case 16: return variants_16(kind, out, max);
     case 32: return variants_32(kind, out, max);
     case 48: return variants_48(kind, out, max);
+    case 64: return variants_64(kind, out, max);
     default: return 0;
   }
 }
 
-bool dyson_supported(int nbp) { return nbp == 16 || nbp == 32 || nbp == 48; }
+bool dyson_supported(int nbp) { return nbp == 16 || nbp == 32 || nbp == 48 || nbp == 64; }
 
 hipError_t launch_dyson(int nbp, int var, const DysonArgs& a, int n_ktiles, hipStream_t s) {
   dim3 grid((unsigned)(n_ktiles * a.n_wtiles));
@@ -34,6 +37,7 @@ hipError_t launch_dyson(int nbp, int var, const DysonArgs& a, int n_ktiles, hipS
     case 16: return launch_dyson_16(var, a, grid, s);
     case 32: return launch_dyson_32(var, a, grid, s);
     case 48: return launch_dyson_48(var, a, grid, s);
+    case 64: return launch_dyson_64(var, a, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

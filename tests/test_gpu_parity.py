@@ -32,6 +32,8 @@ CASES = {
     "nb19-pad": (lambda: synth.f_shell(nk=6, nb=19, nc=14, nw=40, n_narrow=5), 0.2),
     "nb16-nc16": (lambda: synth.f_shell(nk=6, nb=16, nc=16, nw=36, n_narrow=5), 0.0),
     "nb33-nc1": (lambda: synth.plain(nk=5, nb=33, nc=1, nw=30), 0.5),
+    "nb64-f": (lambda: synth.f_shell(nk=5, nb=64, nw=24), -0.2),
+    "nb57-d": (lambda: synth.d_shell(nk=4, nb=57, nw=20), 0.3),
 }
 
 
@@ -61,7 +63,7 @@ def test_tail_order_zero(ctx):
 
 
 def test_ragged_windows(ctx):
-    wl = synth.batched(nk=20, nb_lo=14, nb_hi=48, nw=48, n_iter=2)
+    wl = synth.batched(nk=24, nb_lo=14, nb_hi=64, nw=40, n_iter=2)
     for s in range(2):
         lat = wl.lattices[s]
         assert len(set(lat.nb.tolist())) > 5
@@ -74,7 +76,8 @@ def test_ntot_trace_pass(ctx):
     from paper_1111_2157_amd.dyson import Lattice, SelfEnergy
 
     for wl, mu in ((synth.plain(), -2.1), (synth.f_shell(nk=8, nw=48), 0.3),
-                   (synth.batched(nk=12, nb_lo=14, nb_hi=40, nw=32, n_iter=1), 0.0)):
+                   (synth.batched(nk=12, nb_lo=14, nb_hi=64, nw=32, n_iter=1), 0.0),
+                   (synth.f_shell(nk=3, nb=64, nw=20), 0.1)):
         out = ctx.dmft_ntot(Lattice.from_host(wl.lattice), SelfEnergy.from_host(wl.sigma), mu).cpu().numpy()
         ctx.sync_status()
         n, d = oracle.trace(wl.lattice, wl.sigma, mu)
@@ -177,7 +180,7 @@ def test_autotune_then_parity(ctx):
 
 
 VARIANT_CASES = [(16, lambda: synth.plain(nk=6, nw=40), -1.0), (32, lambda: synth.d_shell(nk=8, nw=40), 0.0),
-                 (48, lambda: synth.f_shell(nk=6, nw=32), 0.1)]
+                 (48, lambda: synth.f_shell(nk=6, nw=32), 0.1), (64, lambda: synth.f_shell(nk=3, nb=64, nw=20), 0.0)]
 
 
 @pytest.mark.parametrize("nbp,maker,mu", VARIANT_CASES)
