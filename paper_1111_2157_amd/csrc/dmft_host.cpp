@@ -46,12 +46,13 @@ struct Bucket {
 // Workspace layout of a single-lattice call.
 struct Layout {
   size_t err = 0, out2 = 0, meta_nb = 0, meta_offb = 0, meta_offn = 0, meta_nbp = 0, meta_klist = 0;
+  size_t meta_offs = 0;
   size_t spart = 0, xpart = 0, tpart = 0, kscal = 0, ktrace = 0, total = 0;
   int64_t s_stride = 0;
   int n_wtiles = 0, n_ktiles_total = 0;
   std::vector<Bucket> buckets;
   std::vector<int32_t> nb, nbp;
-  std::vector<int64_t> off_b, off_n;
+  std::vector<int64_t> off_b, off_n, off_s;
   bool ragged = false;
   int nbp_max = 0;
   int kind = KIND_DENSITY;
@@ -77,8 +78,12 @@ struct dmft_handle_s {
     size_t base = 0;  // offset of this iterate's region inside ws
   };
   std::vector<Iter> iters;
+  std::vector<std::vector<int32_t>> iter_nb;  // host copies of the ragged window sizes
   int b_tail = 2;
-  size_t b_total = 0;
+  size_t b_total = 0, b_args = 0, b_items = 0, b_counters = 0, b_mu = 0;
+  int b_nbig = 0, b_nsmall = 0, b_nargs = 0, b_wgs = 0;
+  void* b_ws = nullptr;
+  hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   // kernel timing
@@ -173,6 +178,7 @@ int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, L
     for (int k = 0; k < nk; ++k) L.nb[k] = lat->nb[k];
   L.off_b.assign(nk + 1, 0);
   L.off_n.assign(nk + 1, 0);
+  L.off_s.assign(nk + 1, 0);
   L.nbp.assign(nk, 0);
   for (int k = 0; k < nk; ++k) {
     L.off_b[k + 1] = L.off_b[k] + L.nb[k];
@@ -180,6 +186,7 @@ int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, L
     L.nbp[k] = nbp_of(L.nb[k]);
     if (!dyson_supported(L.nbp[k]))
       return fail(h, DMFT_EUNSUPPORTED, "no kernel variant for nb = %d", L.nb[k]);
+    L.off_s[k + 1] = L.off_s[k] + (int64_t)L.nbp[k] * L.nbp[k];
   }
   L.nbp_max = *std::max_element(L.nbp.begin(), L.nbp.end());
   L.kind = kind;
@@ -201,7 +208,7 @@ int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, L
     L.buckets.push_back(b);
   }
   L.n_ktiles_total = base;
-  L.s_stride = (int64_t)L.nbp_max * L.nbp_max;
+  L.s_stride = L.off_s[nk];
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -215,7 +222,8 @@ int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, L
   L.meta_offn = take(sizeof(int64_t) * (nk + 1));
   L.meta_nbp = take(sizeof(int32_t) * nk);
   L.meta_klist = take(sizeof(int32_t) * nk);
-  L.spart = take((size_t)L.n_wtiles * nk * L.s_stride * 16);
+  L.meta_offs = take(sizeof(int64_t) * (nk + 1));
+  L.spart = take((size_t)L.n_wtiles * L.s_stride * 16);
   L.xpart = take((size_t)L.n_ktiles_total * nw * 256 * 16);
   L.tpart = take((size_t)L.n_wtiles * nk * 3 * sizeof(double));
   L.kscal = take((size_t)nk * 3 * sizeof(double));
@@ -237,7 +245,7 @@ int check_ws(dmft_handle h, const Layout& L, void* ws, size_t ws_bytes) {
 // Upload the per-k metadata (sizes, offsets, bucket k lists) into ws.
 int upload_meta(dmft_handle h, const Layout& L, char* ws, hipStream_t s, bool sync) {
   size_t nk = L.nb.size();
-  size_t need = sizeof(int32_t) * nk * 3 + sizeof(int64_t) * (nk + 1) * 2;
+  size_t need = sizeof(int32_t) * nk * 3 + sizeof(int64_t) * (nk + 1) * 3;
   if (h->staged) HIPCHK(h, hipEventSynchronize(h->staged));
   if (need > h->pinned_bytes) {
     if (h->pinned) HIPCHK(h, hipHostFree(h->pinned));
@@ -251,10 +259,12 @@ int upload_meta(dmft_handle h, const Layout& L, char* ws, hipStream_t s, bool sy
   int64_t* offn = offb + nk + 1;
   int32_t* nbpv = (int32_t*)(offn + nk + 1);
   int32_t* kl = nbpv + nk;
+  int64_t* offs = (int64_t*)(kl + nk);
   std::copy(L.nb.begin(), L.nb.end(), nbv);
   std::copy(L.off_b.begin(), L.off_b.end(), offb);
   std::copy(L.off_n.begin(), L.off_n.end(), offn);
   std::copy(L.nbp.begin(), L.nbp.end(), nbpv);
+  std::copy(L.off_s.begin(), L.off_s.end(), offs);
   size_t at = 0;
   for (const Bucket& b : L.buckets) {
     std::copy(b.klist.begin(), b.klist.end(), kl + at);
@@ -265,6 +275,7 @@ int upload_meta(dmft_handle h, const Layout& L, char* ws, hipStream_t s, bool sy
   HIPCHK(h, hipMemcpyAsync(ws + L.meta_offn, offn, sizeof(int64_t) * (nk + 1), hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemcpyAsync(ws + L.meta_nbp, nbpv, sizeof(int32_t) * nk, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemcpyAsync(ws + L.meta_klist, kl, sizeof(int32_t) * nk, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(ws + L.meta_offs, offs, sizeof(int64_t) * (nk + 1), hipMemcpyHostToDevice, s));
   if (!h->staged) HIPCHK(h, hipEventCreateWithFlags(&h->staged, hipEventDisableTiming));
   HIPCHK(h, hipEventRecord(h->staged, s));
   if (sync) HIPCHK(h, hipEventSynchronize(h->staged));
@@ -310,6 +321,7 @@ int run_dyson(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, con
   a.mode = mode;
   a.spart = (double*)(ws + L.spart);
   a.s_stride = L.s_stride;
+  a.off_s = (const int64_t*)(ws + L.meta_offs);
   a.xpart = (double*)(ws + L.xpart);
   a.tpart = (double*)(ws + L.tpart);
   a.err = (int*)(ws + L.err);
@@ -368,6 +380,7 @@ EpilogueArgs epilogue_args(const dmft_lattice* lat, const dmft_sigma* sig, const
   e.n_wtiles = L.n_wtiles;
   e.spart = (const double*)(ws + L.spart);
   e.s_stride = L.s_stride;
+  e.off_s = (const int64_t*)(ws + L.meta_offs);
   e.tpart = (const double*)(ws + L.tpart);
   e.kscal = (double*)(ws + L.kscal);
   e.ktrace = (double*)(ws + L.ktrace);
@@ -451,6 +464,7 @@ int dmft_destroy(dmft_handle h) {
   if (!h) return DMFT_EINVAL;
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->staged) {
     (void)hipEventSynchronize(h->staged);
     (void)hipEventDestroy(h->staged);
@@ -711,25 +725,11 @@ int find_mu(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, int t
 
 
 
-int dmft_batched_workspace_size(dmft_handle h, int, const dmft_lattice* const*, const dmft_sigma* const*,
-                                size_t*) {
-  return fail(h, DMFT_EUNSUPPORTED, "batched: not built yet");
-}
-int dmft_batched_plan(dmft_handle h, int, const dmft_lattice* const*, const dmft_sigma* const*, int, void*,
-                      size_t, hipStream_t) {
-  return fail(h, DMFT_EUNSUPPORTED, "batched: not built yet");
-}
-int dmft_batched_pass(dmft_handle h, const double*, double* const*, double* const*, void*, size_t,
-                      hipStream_t) {
-  return fail(h, DMFT_EUNSUPPORTED, "batched: not built yet");
-}
-int dmft_batched_graph_capture(dmft_handle h, const double*, double* const*, double* const*, void*, size_t,
-                               hipStream_t) {
-  return fail(h, DMFT_EUNSUPPORTED, "batched: not built yet");
-}
-int dmft_batched_graph_launch(dmft_handle h, hipStream_t) {
-  return fail(h, DMFT_EUNSUPPORTED, "batched: not built yet");
-}
+
+
+
+
+
 
 
 
@@ -838,6 +838,303 @@ int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
     strncpy(best_out, report.c_str(), best_len - 1);
     best_out[best_len - 1] = 0;
   }
+  return DMFT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batched pass
+
+namespace {
+
+// Layouts of all iterates inside one workspace, plus the argument array, the
+// work queue, the queue counters and per-iterate mu slots.
+int batched_layout(dmft_handle h, int n_iter, const dmft_lattice* const* lat, const dmft_sigma* const* sig,
+                   std::vector<Layout>& Ls, std::vector<size_t>& base, const std::vector<Tile>* tiles,
+                   size_t* total, size_t* o_args, size_t* o_items, size_t* o_cnt, size_t* o_mu, int* n_args,
+                   int* n_items) {
+  if (n_iter < 1 || !lat || !sig) return fail(h, DMFT_EINVAL, "need n_iter >= 1 and lattice/sigma arrays");
+  Ls.assign(n_iter, Layout());
+  base.assign(n_iter, 0);
+  size_t o = 0;
+  int na = 0, ni = 0;
+  for (int s = 0; s < n_iter; ++s) {
+    int r = check_shapes(h, lat[s], sig[s]);
+    if (r) return r;
+    Tile t;
+    if (tiles) {
+      t = (*tiles)[s];
+    } else {
+      // few, large frequency tiles: the queue is drained dynamically, and the
+      // partial sums over frequency tiles stay a few GiB even for big batches
+      t = heuristic_tile(lat[s]->nk, sig[s]->nw);
+      t.wt = std::max(t.wt, (sig[s]->nw + 7) / 8);
+    }
+    r = make_layout(h, lat[s], sig[s], Ls[s], KIND_DENSITY, &t);
+    if (r) return r;
+    base[s] = o;
+    o = align_up(o + Ls[s].total);
+    for (const Bucket& b : Ls[s].buckets) {
+      ++na;
+      ni += b.n_ktiles * Ls[s].n_wtiles;
+    }
+  }
+  *o_args = o;
+  o = align_up(o + sizeof(DysonArgs) * na);
+  *o_items = o;
+  o = align_up(o + sizeof(BatchItemHost) * ni);
+  *o_cnt = o;
+  o = align_up(o + 2 * sizeof(int));
+  *o_mu = o;
+  o = align_up(o + sizeof(double) * n_iter);
+  *total = o;
+  *n_args = na;
+  *n_items = ni;
+  return DMFT_OK;
+}
+
+int batched_pass_impl(dmft_handle h, const double* mu_dev, double* const* nk_out, double* const* gloc_out,
+                      void* ws, size_t ws_bytes, hipStream_t stream, bool kernel_only) {
+  if (h->iters.empty()) return fail(h, DMFT_EINVAL, "no batched plan (call dmft_batched_plan first)");
+  if (ws != h->b_ws || ws_bytes < h->b_total) return fail(h, DMFT_EWORKSPACE, "workspace differs from the plan's");
+  if (!mu_dev) return fail(h, DMFT_EINVAL, "mu_dev is NULL");
+  char* w = (char*)ws;
+  int n_iter = (int)h->iters.size();
+  HIPCHK(h, launch_copy_doubles(mu_dev, (double*)(w + h->b_mu), n_iter, stream));
+  HIPCHK(h, launch_fill_zero(w + h->b_counters, 2 * sizeof(int), stream));
+  HIPCHK(h, launch_batched(w + h->b_items, h->b_nbig, h->b_nsmall, (const DysonArgs*)(w + h->b_args),
+                           (int*)(w + h->b_counters), h->b_wgs, stream));
+  if (kernel_only) return DMFT_OK;
+  for (int s = 0; s < n_iter; ++s) {
+    const auto& it = h->iters[s];
+    char* wb = w + it.base;
+    const double* mup = (const double*)(w + h->b_mu) + s;
+    EpilogueArgs e = epilogue_args(&it.lat, &it.sig, it.lay, wb, 0.0, mup, h->b_tail);
+    if (nk_out && nk_out[s]) HIPCHK(h, launch_nk_epilogue(e, nk_out[s], stream));
+    if (gloc_out && gloc_out[s])
+      HIPCHK(h, launch_gloc_reduce(it.lay.n_ktiles_total, it.sig.nw, it.lat.nc, (const double*)(wb + it.lay.xpart),
+                                   gloc_out[s], stream));
+  }
+  return DMFT_OK;
+}
+
+int batched_build(dmft_handle h, int n_iter, const dmft_lattice* const* lat, const dmft_sigma* const* sig,
+                  int tail_order, void* ws, size_t ws_bytes, hipStream_t stream, const std::vector<Tile>* tiles) {
+  std::vector<Layout> Ls;
+  std::vector<size_t> base;
+  size_t total, o_args, o_items, o_cnt, o_mu;
+  int na, ni;
+  int r = batched_layout(h, n_iter, lat, sig, Ls, base, tiles, &total, &o_args, &o_items, &o_cnt, &o_mu, &na, &ni);
+  if (r) return r;
+  if (!ws || (uintptr_t)ws % kAlign) return fail(h, DMFT_EWORKSPACE, "workspace NULL or misaligned");
+  if (ws_bytes < total) return fail(h, DMFT_EWORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, total);
+  HIPCHK(h, hipSetDevice(h->device));
+  char* w = (char*)ws;
+  h->iters.clear();
+  h->iter_nb.assign(n_iter, {});
+  std::vector<DysonArgs> args;
+  struct Q {
+    BatchItemHost it;
+    double cost;
+  };
+  std::vector<Q> big, small;
+  for (int s = 0; s < n_iter; ++s) {
+    Layout& L = Ls[s];
+    r = upload_meta(h, L, w + base[s], stream, true);
+    if (r) return r;
+    dmft_handle_s::Iter itr;
+    itr.lat = *lat[s];
+    if (lat[s]->nb) {
+      h->iter_nb[s].assign(lat[s]->nb, lat[s]->nb + lat[s]->nk);
+      itr.lat.nb = h->iter_nb[s].data();
+    }
+    itr.sig = *sig[s];
+    itr.lay = L;
+    itr.base = base[s];
+    h->iters.push_back(itr);
+    char* wb = w + base[s];
+    const double* mup = (const double*)(w + o_mu) + s;
+    size_t at = 0;
+    for (const Bucket& b : L.buckets) {
+      DysonArgs a{};
+      a.nk = lat[s]->nk;
+      a.nc = lat[s]->nc;
+      a.nw = sig[s]->nw;
+      a.nb_uniform = L.ragged ? 0 : lat[s]->nb_max;
+      a.nb = (const int32_t*)(wb + L.meta_nb);
+      a.off_b = (const int64_t*)(wb + L.meta_offb);
+      a.eps = lat[s]->eps;
+      a.wk = lat[s]->wk;
+      a.proj = lat[s]->proj;
+      a.beta = sig[s]->beta;
+      a.sigma = sig[s]->sigma;
+      a.e_dc = sig[s]->e_dc;
+      a.mu_ptr = mup;
+      a.klist = (const int32_t*)(wb + L.meta_klist) + at;
+      a.nklist = (int)b.klist.size();
+      a.kt = L.tile.kt;
+      a.wt = L.tile.wt;
+      a.n_wtiles = L.n_wtiles;
+      a.ktile_base = b.ktile_base;
+      a.mode = MODE_S | MODE_GLOC;
+      a.spart = (double*)(wb + L.spart);
+      a.s_stride = L.s_stride;
+      a.off_s = (const int64_t*)(wb + L.meta_offs);
+      a.xpart = (double*)(wb + L.xpart);
+      a.tpart = (double*)(wb + L.tpart);
+      a.err = (int*)(w + base[0] + Ls[0].err);
+      int ai = (int)args.size();
+      args.push_back(a);
+      at += b.klist.size();
+      for (int kt = 0; kt < b.n_ktiles; ++kt) {
+        int nkt = std::min(L.tile.kt, (int)b.klist.size() - kt * L.tile.kt);
+        for (int wt = 0; wt < L.n_wtiles; ++wt) {
+          int nwt = std::min(L.tile.wt, sig[s]->nw - wt * L.tile.wt);
+          double c = (double)b.nbp * b.nbp * (b.nbp + 2.0 * lat[s]->nc) * nkt * nwt;
+          Q qq{{ai, b.nbp, kt, wt}, c};
+          (b.nbp == 64 ? big : small).push_back(qq);
+        }
+      }
+    }
+  }
+  auto by_cost = [](const Q& x, const Q& y) { return x.cost > y.cost; };
+  std::stable_sort(big.begin(), big.end(), by_cost);
+  std::stable_sort(small.begin(), small.end(), by_cost);
+  std::vector<BatchItemHost> items;
+  for (auto& x : big) items.push_back(x.it);
+  for (auto& x : small) items.push_back(x.it);
+  HIPCHK(h, hipMemcpy(w + o_args, args.data(), sizeof(DysonArgs) * args.size(), hipMemcpyHostToDevice));
+  if (!items.empty())
+    HIPCHK(h, hipMemcpy(w + o_items, items.data(), sizeof(BatchItemHost) * items.size(), hipMemcpyHostToDevice));
+  int zero = 0;
+  HIPCHK(h, hipMemcpy(w + base[0] + Ls[0].err, &zero, sizeof(int), hipMemcpyHostToDevice));
+  int ncu = 0;
+  HIPCHK(h, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
+  h->b_tail = tail_order;
+  h->b_total = total;
+  h->b_args = o_args;
+  h->b_items = o_items;
+  h->b_counters = o_cnt;
+  h->b_mu = o_mu;
+  h->b_nbig = (int)big.size();
+  h->b_nsmall = (int)small.size();
+  h->b_nargs = (int)args.size();
+  h->b_wgs = 2 * std::max(ncu, 1);
+  h->b_ws = ws;
+  return DMFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dmft_batched_workspace_size(dmft_handle h, int n_iter, const dmft_lattice* const* lat, const dmft_sigma* const* sig,
+                                size_t* bytes) {
+  if (!bytes) return fail(h, DMFT_EINVAL, "bytes is NULL");
+  std::vector<Layout> Ls;
+  std::vector<size_t> base;
+  size_t total, a, b, c, d;
+  int na, ni;
+  int r = batched_layout(h, n_iter, lat, sig, Ls, base, nullptr, &total, &a, &b, &c, &d, &na, &ni);
+  if (r) return r;
+  *bytes = total;
+  return DMFT_OK;
+}
+
+int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat, const dmft_sigma* const* sig,
+                      int tail_order, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!h) return DMFT_EINVAL;
+  if (tail_order != 0 && tail_order != 2) return fail(h, DMFT_EINVAL, "tail_order must be 0 or 2");
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  if (h->graph) {
+    (void)hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  int r = batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, nullptr);
+  if (r) return r;
+  // Autotune the frequency-tile size of the persistent launch: time the kernel
+  // with a few tile sizes that fit the workspace, keep the fastest plan.
+  std::vector<Tile> base_tiles;
+  for (auto& it : h->iters) base_tiles.push_back(it.lay.tile);
+  std::vector<double> mu0(n_iter, 0.0);
+  char* w = (char*)ws;
+  double* mu_tmp = (double*)(w + h->b_mu);
+  HIPCHK(h, hipMemcpy(mu_tmp, mu0.data(), sizeof(double) * n_iter, hipMemcpyHostToDevice));
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  double best = 1e300;
+  std::vector<Tile> best_tiles = base_tiles;
+  for (int f : {1, 2, 4}) {
+    std::vector<Tile> cand = base_tiles;
+    for (int s = 0; s < n_iter; ++s) cand[s].wt = std::max(4, base_tiles[s].wt / f);
+    std::vector<Layout> Ls;
+    std::vector<size_t> bs;
+    size_t total, a, b, c, d;
+    int na, ni;
+    r = batched_layout(h, n_iter, lat, sig, Ls, bs, &cand, &total, &a, &b, &c, &d, &na, &ni);
+    if (r) return r;
+    if (total > ws_bytes) continue;
+    r = batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, &cand);
+    if (r) return r;
+    HIPCHK(h, hipMemcpy(w + h->b_mu, mu0.data(), sizeof(double) * n_iter, hipMemcpyHostToDevice));
+    HIPCHK(h, hipEventRecord(e0, stream));
+    r = batched_pass_impl(h, (const double*)(w + h->b_mu), nullptr, nullptr, ws, ws_bytes, stream, true);
+    if (r) return r;
+    HIPCHK(h, hipEventRecord(e1, stream));
+    HIPCHK(h, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_tiles = cand;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, &best_tiles);
+}
+
+int dmft_batched_pass(dmft_handle h, const double* mu_dev, double* const* nk_out, double* const* gloc_out, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  if (!h) return DMFT_EINVAL;
+  return batched_pass_impl(h, mu_dev, nk_out, gloc_out, ws, ws_bytes, stream, false);
+}
+
+int dmft_batched_graph_capture(dmft_handle h, const double* mu_dev, double* const* nk_out, double* const* gloc_out,
+                               void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!h) return DMFT_EINVAL;
+  if (h->iters.empty()) return fail(h, DMFT_EINVAL, "no batched plan (call dmft_batched_plan first)");
+  if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  if (h->graph) {
+    (void)hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  int r = batched_pass_impl(h, mu_dev, nk_out, gloc_out, ws, ws_bytes, h->cap_stream, false);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (r) {
+    if (g) (void)hipGraphDestroy(g);
+    return r;
+  }
+  if (e != hipSuccess) return fail(h, DMFT_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  h->graph = g;
+  HIPCHK(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+  return dmft_batched_graph_launch(h, stream);
+}
+
+int dmft_batched_graph_launch(dmft_handle h, hipStream_t stream) {
+  if (!h) return DMFT_EINVAL;
+  if (!h->gexec) return fail(h, DMFT_EINVAL, "no captured graph");
+  HIPCHK(h, hipGraphLaunch(h->gexec, stream));
   return DMFT_OK;
 }
 

@@ -41,8 +41,9 @@ struct DysonArgs {
   int kt, wt, n_wtiles;
   int ktile_base;              // index of this launch's first k tile among all k tiles
   int mode;
-  double* spart;               // MODE_S:    [n_wtiles][nk][NBP*NBP] complex, lane order
-  int64_t s_stride;            // complex elements per (wtile, k) slot of spart
+  double* spart;               // MODE_S: per frequency tile, per k an NBP_k^2 complex slot (lane order)
+  int64_t s_stride;            // complex elements per frequency tile of spart
+  const int64_t* off_s;        // [nk+1] start of k's slot within a frequency tile
   double* xpart;               // MODE_GLOC: [n_ktiles_total][nw][256] complex, lane order
   double* tpart;               // MODE_TRACE:[n_wtiles][nk][2]
   int* err;                    // error word
@@ -66,7 +67,8 @@ struct EpilogueArgs {
   int tail_order;
   int n_wtiles;
   const double* spart;
-  int64_t s_stride;
+  int64_t s_stride;            // complex elements per frequency tile of spart
+  const int64_t* off_s;        // [nk+1] start of k's slot within a frequency tile
   const double* tpart;
   double* nk_out;              // complex, ragged
   double* kscal;               // [nk][3] per-k  tr N, tr(S N S^dag), sum_v E_v N_vv
@@ -95,6 +97,14 @@ hipError_t launch_adjoint(int nbp, int gen, const DysonArgs& a, const double* nb
                           const double* gbar, double* mpart, double* tpart, int n_ktiles, hipStream_t s);
 hipError_t launch_sigma_bar_reduce(int n_ktiles, int nw, int nc, const double* mpart, double scale, int dagger,
                                    double* out, hipStream_t s);
+// Persistent batched launch over a queue of items (see batched.hip): items[0 .. n_big)
+// need a two-wavefront work-group, items[n_big .. n_big + n_small) one wavefront.
+struct BatchItemHost {
+  int32_t args, nbp, ktile, wtile;
+};
+hipError_t launch_batched(const void* items, int n_big, int n_small, const DysonArgs* args, int* counters,
+                          int n_workgroups, hipStream_t s);
+hipError_t launch_copy_doubles(const double* src, double* dst, int n, hipStream_t s);
 // Per-k [tr N, d tr N/dmu, mubar_k] from the adjoint partials (tail terms included).
 hipError_t launch_adj_epilogue(const EpilogueArgs& a, const double* nbar, hipStream_t s);
 // out[j] = sum_k weight_j(k) kvals[k][j], weight = w_k, or 1 where bit j of unit_mask is set.

@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(256) nk_epilogue_kernel(EpilogueArgs a, double
     double2 acc = make_double2(0.0, 0.0);
     const double2* sp = reinterpret_cast<const double2*>(a.spart);
     for (int w = 0; w < a.n_wtiles; ++w) {
-      double2 v = sp[((int64_t)w * a.nk + k) * a.s_stride + e * 64 + lane];
+      double2 v = sp[(int64_t)w * a.s_stride + a.off_s[k] + e * 64 + lane];
       acc.x += v.x;
       acc.y += v.y;
     }

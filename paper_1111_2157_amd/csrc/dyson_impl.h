@@ -344,13 +344,12 @@ __device__ __forceinline__ void build_a(Mat<NBP>& g, const DysonArgs& a, const d
     }
 }
 
-template <int NBP, int KIND, int PF, int SLDS, int OCC = 1>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) dyson_kernel(DysonArgs a) {
+// One (k-tile, frequency-tile) work item on one wavefront (lane = 0..63).
+template <int NBP, int KIND, int PF, int SLDS>
+__device__ __forceinline__ void dyson_tile(const DysonArgs& a, int ktile, int wtile,
+                                           KernelShared<NBP, KIND, SLDS>& sh, int lane) {
   constexpr int T = NBP / 16;
-  __shared__ KernelShared<NBP, KIND, SLDS> sh;
-  const int lane = threadIdx.x, q = lane >> 4, c16 = lane & 15;
-  const int wtile = blockIdx.x % a.n_wtiles;
-  const int ktile = blockIdx.x / a.n_wtiles;
+  const int q = lane >> 4, c16 = lane & 15;
   const int n0 = wtile * a.wt;
   const int n1 = min(n0 + a.wt, a.nw);
   const int kk0 = ktile * a.kt;
@@ -505,7 +504,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
     }  // frequencies
 
     if (want_s) {
-      double2* sp = reinterpret_cast<double2*>(a.spart) + ((int64_t)wtile * a.nk + k) * a.s_stride;
+      double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
 #pragma unroll
       for (int t = 0; t < T; ++t)
 #pragma unroll
@@ -533,6 +532,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
   }  // k
   if (bad) atomicOr(a.err, ERR_SINGULAR);
   if (nonfinite) atomicOr(a.err, ERR_NONFINITE);
+}
+
+template <int NBP, int KIND, int PF, int SLDS, int OCC = 1>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) dyson_kernel(DysonArgs a) {
+  __shared__ KernelShared<NBP, KIND, SLDS> sh;
+  dyson_tile<NBP, KIND, PF, SLDS>(a, blockIdx.x / a.n_wtiles, blockIdx.x % a.n_wtiles, sh, threadIdx.x);
 }
 
 // Kernel variants: bit 0 = PF, bit 1 = SLDS (density only), bit 2 = two

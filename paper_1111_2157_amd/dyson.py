@@ -206,6 +206,51 @@ class Context:
                                              _stream(self.device), buf, 8192))
         return buf.value.decode()
 
+    # ------------------------------------------------------------------ batched pass
+    def batched_plan(self, lats: List[Lattice], sigs: List[SelfEnergy], tail_order: int = 2):
+        """Plan one persistent pass over several (lattice, self-energy) iterates.
+        Returns the plan's workspace (kept alive by the context)."""
+        n = len(lats)
+        self._b_ls = [l.struct() for l in lats]
+        self._b_ss = [s.struct() for s in sigs]
+        lp = (C.c_void_p * n)(*[C.addressof(x) for x in self._b_ls])
+        sp = (C.c_void_p * n)(*[C.addressof(x) for x in self._b_ss])
+        self._b_lp, self._b_sp = lp, sp
+        nb = C.c_size_t()
+        check(self.h, self.lib.dmft_batched_workspace_size(self.h, n, lp, sp, C.byref(nb)))
+        self._b_ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        self._b_ws[:256].zero_()
+        self._b_keep = (lats, sigs)
+        check(self.h, self.lib.dmft_batched_plan(self.h, n, lp, sp, int(tail_order), _ptr(self._b_ws),
+                                                 C.c_size_t(self._b_ws.numel()), _stream(self.device)))
+        return self._b_ws
+
+    def _batched_ptrs(self, outs):
+        n = len(self._b_ls)
+        return (C.c_void_p * n)(*[(o.data_ptr() if o is not None else 0) for o in outs])
+
+    def batched_outputs(self):
+        lats, sigs = self._b_keep
+        nks = [torch.empty(l.n_size(), dtype=torch.complex128, device=self.device) for l in lats]
+        gls = [torch.empty((s.nw, l.nc, l.nc), dtype=torch.complex128, device=self.device) for l, s in zip(lats, sigs)]
+        return nks, gls
+
+    def batched_pass(self, mu_dev: torch.Tensor, nks, gls):
+        check(self.h, self.lib.dmft_batched_pass(self.h, _ptr(mu_dev), self._batched_ptrs(nks), self._batched_ptrs(gls),
+                                                 _ptr(self._b_ws), C.c_size_t(self._b_ws.numel()),
+                                                 _stream(self.device)))
+
+    def batched_graph_capture(self, mu_dev: torch.Tensor, nks, gls):
+        check(self.h, self.lib.dmft_batched_graph_capture(self.h, _ptr(mu_dev), self._batched_ptrs(nks),
+                                                          self._batched_ptrs(gls), _ptr(self._b_ws),
+                                                          C.c_size_t(self._b_ws.numel()), _stream(self.device)))
+
+    def batched_graph_launch(self):
+        check(self.h, self.lib.dmft_batched_graph_launch(self.h, _stream(self.device)))
+
+    def batched_sync_status(self):
+        check(self.h, self.lib.dmft_sync_status(self.h, _ptr(self._b_ws), _stream(self.device)))
+
     def variants(self, kind: int, nbp: int):
         buf = (C.c_int * 16)()
         n = self.lib.dmft_variants(int(kind), int(nbp), buf, 16)
