@@ -23,6 +23,8 @@ from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -50,6 +52,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
     ap.add_argument("--extra", action="store_true", help="also time the other workloads")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (use the default variants)")
+    ap.add_argument("--batched", action="store_true", help="also time the batched workload (8 iterates, graph)")
     return ap.parse_args()
 
 
@@ -117,6 +120,43 @@ def mu_search(ctx, tune=True):
     return out
 
 
+def batched(ctx, steps=2):
+    """The batched workload: Nk=4096, nb_k ~ U{20..64}, 8 self-energy iterates
+    (Nc 5 and 14), Nw=2048, beta=40: one persistent launch per pass, replayed
+    from its hipGraph."""
+    import torch
+
+    from paper_1111_2157_amd import synth
+    from paper_1111_2157_amd.dyson import Lattice, SelfEnergy
+
+    wl = synth.batched()
+    lats = [Lattice.from_host(l) for l in wl.lattices]
+    sigs = [SelfEnergy.from_host(s) for s in wl.sigmas]
+    t0 = time.perf_counter()
+    ctx.batched_plan(lats, sigs, 2)
+    plan_s = time.perf_counter() - t0
+    mu_dev = torch.zeros(len(lats), dtype=torch.float64, device="cuda")
+    nks, gls = ctx.batched_outputs()
+    ctx.batched_graph_capture(mu_dev, nks, gls)
+    torch.cuda.synchronize()
+    ctx.batched_sync_status()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.batched_graph_launch()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    evals = sum(l.nk for l in wl.lattices) * wl.sigmas[0].nw
+    flops = 0.0
+    for l, s in zip(wl.lattices, wl.sigmas):
+        nb = l.nb.astype(float)
+        flops += s.nw * float(np.sum(8.0 * (nb ** 3 + 2 * nb * nb * l.nc + 2 * nb * l.nc * l.nc)))
+    del nks, gls
+    ctx._b_ws = None
+    torch.cuda.empty_cache()
+    return {"workload": wl.name, "evals_per_s": evals / sec, "ms_per_pass": sec * 1e3,
+            "tflops": flops / sec / 1e12, "plan_seconds": plan_s, "graph": True}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -180,6 +220,8 @@ def main():
             extra[w.name] = {"evals_per_s": ev / sc, "ms_per_pass": sc * 1e3,
                              "kernel_tflops": f / (km / max(ln, 1) / 1e3) / 1e12}
         rec["extra"] = extra
+    if args.batched:
+        rec["batched"] = batched(ctx)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl, mu, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

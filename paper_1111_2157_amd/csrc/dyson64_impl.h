@@ -67,22 +67,30 @@ __device__ __forceinline__ void publish(const LMat& g, Shared& sh, int w, int q,
 }
 
 template <int K>
-__device__ __forceinline__ void fetch(RowB& rb, ColB& cb, const Shared& sh, int w, int q, int c16) {
+__device__ __forceinline__ void fetch_row(RowB& rb, const Shared& sh, int c16) {
   constexpr int s = K & 1;
 #pragma unroll
   for (int b = 0; b < T; ++b) rb.rv[b] = sh.row[s][16 * b + c16];
   rb.p = sh.piv[s];
+}
+
+template <int K>
+__device__ __forceinline__ void fetch_col(ColB& cb, const Shared& sh, int w, int q) {
+  constexpr int s = K & 1;
 #pragma unroll
   for (int tl = 0; tl < TL; ++tl)
 #pragma unroll
     for (int i = 0; i < 4; ++i) cb.cc[tl][i] = sh.col[s][16 * (2 * w + tl) + 4 * i + q];
 }
 
+// Step K.  On entry rb holds step K's pivot row and pivot; the pivot column is
+// read here (it is only needed for this wavefront's rows).
 template <int K>
 __device__ __forceinline__ void steps(LMat& g, RowB& rb, ColB& cb, Shared& sh, int w, int q, int c16, int nb,
                                       int& bad) {
   if constexpr (K < NBP) {
     if (K >= nb) return;
+    fetch_col<K>(cb, sh, w, q);
     double2 ip = crecip(rb.p);
     bad |= (rb.p.x == 0.0 && rb.p.y == 0.0);
     double2 rs[T];
@@ -103,8 +111,7 @@ __device__ __forceinline__ void steps(LMat& g, RowB& rb, ColB& cb, Shared& sh, i
       publish<K1>(g, sh, w, q, c16);
       __syncthreads();
       RowB rn;
-      ColB cn;
-      fetch<K1>(rn, cn, sh, w, q, c16);
+      fetch_row<K1>(rn, sh, c16);
 #pragma unroll
       for (int tl = 0; tl < TL; ++tl)
 #pragma unroll
@@ -119,7 +126,7 @@ __device__ __forceinline__ void steps(LMat& g, RowB& rb, ColB& cb, Shared& sh, i
             upd(g.re[tl][b], g.im[tl][b], i, cb.cc[tl][i], rs[b]);
           }
         }
-      steps<K + 1>(g, rn, cn, sh, w, q, c16, nb, bad);
+      steps<K + 1>(g, rn, cb, sh, w, q, c16, nb, bad);
     } else {
 #pragma unroll
       for (int tl = 0; tl < TL; ++tl)
@@ -190,12 +197,14 @@ __device__ __forceinline__ void tile(const DysonArgs& a, int ktile, int wtile, S
           sa_r[j] = v.x;
           sa_i[j] = v.y;
         }
+        const int kc = (nc + 3) >> 2;
         v4d vr[T], vi[T];
 #pragma unroll
         for (int b = 0; b < T; ++b) {
           vr[b] = vi[b] = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
+            if (j >= kc) break;
             vr[b] = mma(sa_r[j], pr.pa_r[j][b], vr[b]);
             vr[b] = mms(sa_i[j], pr.pa_i[j][b], vr[b]);
             vi[b] = mma(sa_r[j], pr.pa_i[j][b], vi[b]);
@@ -219,6 +228,7 @@ __device__ __forceinline__ void tile(const DysonArgs& a, int ktile, int wtile, S
             // t is wave-dependent, so select it from the four tiles
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
+              if (i >= kc) break;
               double ar = pr.pa_r[i][0], ai = pr.pa_i[i][0];
 #pragma unroll
               for (int tt = 1; tt < T; ++tt)
@@ -243,7 +253,7 @@ __device__ __forceinline__ void tile(const DysonArgs& a, int ktile, int wtile, S
         ColB cb;
         publish<0>(g, sh, w, q, c16);
         __syncthreads();
-        fetch<0>(rb, cb, sh, w, q, c16);
+        fetch_row<0>(rb, sh, c16);
         steps<0>(g, rb, cb, sh, w, q, c16, nb, bad);
         __syncthreads();
       }

@@ -306,13 +306,16 @@ __device__ __forceinline__ void build_a(Mat<NBP>& g, const DysonArgs& a, const d
     sa_r[j] = v.x;
     sa_i[j] = v.y;
   }
-  // V = Sigma' S  (16 x NBP)
+  // V = Sigma' S  (16 x NBP); chunk j holds orbitals q + 4 j, so chunks with
+  // 4 j >= nc are all padding and are skipped (uniform branch)
+  const int kc = (nc + 3) >> 2;
   v4d vr[T], vi[T];
 #pragma unroll
   for (int b = 0; b < T; ++b) {
     vr[b] = vi[b] = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
+      if (j >= kc) break;
       vr[b] = mma(sa_r[j], pr.pa_r[j][b], vr[b]);
       vr[b] = mms(sa_i[j], pr.pa_i[j][b], vr[b]);
       vi[b] = mma(sa_r[j], pr.pa_i[j][b], vi[b]);
@@ -334,6 +337,7 @@ __device__ __forceinline__ void build_a(Mat<NBP>& g, const DysonArgs& a, const d
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
+        if (i >= kc) break;
         zr = mms(pr.pa_r[i][t], vr[b][i], zr);
         zr = mms(pr.pa_i[i][t], vi[b][i], zr);
         zi = mms(pr.pa_r[i][t], vi[b][i], zi);
