@@ -79,8 +79,10 @@ struct EpilogueArgs {
 // Launchers (return hipError_t of the launch).
 // var: kernel variant, bit 0 = next-step pivot column read ahead (PF), bit 1 =
 // running sum of G in LDS (SLDS, density kind only), bit 2 = two wavefronts per
-// SIMD.  dyson_variants lists the instantiated variants of a size and kind
-// (kind 0 = density, 1 = trace); the first one is the default.
+// SIMD, bit 3 = low-rank (Woodbury) form instead of the band-window inversion
+// (lowrank_impl.h; there bit 0 = projector fragments re-read at every use).  dyson_variants lists the
+// instantiated variants of a size and kind (kind 0 = density, 1 = trace); the
+// first one is the default.
 hipError_t launch_dyson(int nbp, int var, const DysonArgs& a, int n_ktiles, hipStream_t s);
 int dyson_variants(int nbp, int kind, int* out, int max);
 bool dyson_supported(int nbp);

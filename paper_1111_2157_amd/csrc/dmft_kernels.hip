@@ -18,21 +18,27 @@ int variants_64(int kind, int* out, int max);
 int variants_16(int kind, int* out, int max);
 int variants_32(int kind, int* out, int max);
 int variants_48(int kind, int* out, int max);
+hipError_t launch_lowrank(int nbp, int var, const DysonArgs& a, dim3 grid, hipStream_t s);
+int lowrank_variants(int nbp, int kind, int* out, int max);
 
+// Dense variants first (the first one is the default), then the low-rank ones.
 int dyson_variants(int nbp, int kind, int* out, int max) {
+  int n = 0;
   switch (nbp) {
-    case 16: return variants_16(kind, out, max);
-    case 32: return variants_32(kind, out, max);
-    case 48: return variants_48(kind, out, max);
-    case 64: return variants_64(kind, out, max);
+    case 16: n = variants_16(kind, out, max); break;
+    case 32: n = variants_32(kind, out, max); break;
+    case 48: n = variants_48(kind, out, max); break;
+    case 64: n = variants_64(kind, out, max); break;
     default: return 0;
   }
+  return n + lowrank_variants(nbp, kind, out + n, max - n);
 }
 
 bool dyson_supported(int nbp) { return nbp == 16 || nbp == 32 || nbp == 48 || nbp == 64; }
 
 hipError_t launch_dyson(int nbp, int var, const DysonArgs& a, int n_ktiles, hipStream_t s) {
   dim3 grid((unsigned)(n_ktiles * a.n_wtiles));
+  if (var & 8) return launch_lowrank(nbp, var, a, grid, s);
   switch (nbp) {
     case 16: return launch_dyson_16(var, a, grid, s);
     case 32: return launch_dyson_32(var, a, grid, s);

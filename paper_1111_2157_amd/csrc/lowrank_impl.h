@@ -1,0 +1,389 @@
+// Low-rank form of the lattice Dyson step, on the register layout of dyson_impl.h.
+//
+// The self-energy enters the band window only through the nc correlated
+// orbitals (the embedding of the DMFT-loop section), so with D = diag(d),
+// d_v = 1 / (i w_n + mu - E_v), the band-window matrix is a rank-nc
+// correction of a diagonal one:  A = D^-1 - S^dag Sigma' S,  Sigma' = Sigma - V_DC.
+// With the nc x nc matrices
+//
+//     X   = S D S^dag                      (projected bare propagator)
+//     K   = X^-1 - Sigma'
+//     R   = Sigma' K^-1 X^-1                (= (I - Sigma' X)^-1 Sigma')
+//
+// the Woodbury identity gives, exactly,
+//
+//     G           = D + D S^dag R S D
+//     S G S^dag   = K^-1
+//     tr G        = sum_v d_v + tr(R X2)                            X_j = S D^j S^dag
+//     tr G^2      = sum_v d_v^2 + 2 tr(R X3) + tr(R X2 R X2)
+//
+// so the nb^3 inversion becomes rank-nc products on the matrix cores and two
+// nc x nc inversions.  Both are done by the Gauss-Jordan sweep of dyson_impl.h
+// without pivoting, which is safe here for the same reason as for A: the rows
+// of S are orthonormal (the projector construction of the projection section),
+// so the anti-Hermitian part of X, S Im(D) S^dag, is negative definite; that of
+// K = X^-1 - Sigma' is then positive definite for a causal Sigma, and every
+// leading block of either matrix is invertible.
+//
+// Operand bookkeeping (16x16x4 matrix-core instruction): a matrix M used as the
+// A operand is taken from registers holding M^T in the output layout, as the
+// B operand from registers holding M.  Every product below is ordered so that
+// its operands are already in the right form, and no transpose is needed
+// except one (through LDS) in tr(E^2), E = R X2:
+//   X-regs        from  A = S[c16][r] d_r,  B = S[c16][r]  (conjugated)
+//   Xi-regs       Gauss-Jordan of X
+//   K-regs        Xi - Sigma'
+//   Gl-regs       Gauss-Jordan of K                          -> S G S^dag
+//   V  = Gl^T Sigma'^T     (A: Gl-regs,  B: Sigma'[c16][q + 4 j])
+//   R^T = Xi^T V           (A: Xi-regs,  B: V-regs)           -> R^T-regs hold R[c16][q + 4 i]
+//   Q  = (R S) D           (A: R^T-regs, B: S[q + 4 j][16 b + c16])
+//   sum_n G += D + (D S^dag) Q
+#pragma once
+
+#include "dyson_impl.h"
+
+namespace dmft {
+
+struct LRShared {
+  GJShared<16> gj;
+  double2 tp[16 * 17];  // 16x16 transpose
+};
+
+// 1 / (zr + i zi - e) for real e.
+__device__ __forceinline__ double2 inv_z_minus(double zr, double zi, double e) {
+  double x = zr - e;
+  double d = x * x + zi * zi;
+  double r = __builtin_amdgcn_rcp(d);
+  double t = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, t, r);
+  t = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, t, r);
+  return make_double2(x * r, -zi * r);
+}
+
+// Complex products on the 16x16x4 matrix core (real and imaginary parts in
+// separate accumulators):  cmma: D += A B,  cmma_cb: D += A conj(B).
+__device__ __forceinline__ void cmma(v4d& dr, v4d& di, double ar, double ai, double br, double bi) {
+  dr = mma(ar, br, dr);
+  dr = mms(ai, bi, dr);
+  di = mma(ar, bi, di);
+  di = mma(ai, br, di);
+}
+__device__ __forceinline__ void cmma_cb(v4d& dr, v4d& di, double ar, double ai, double br, double bi) {
+  dr = mma(ar, br, dr);
+  dr = mma(ai, bi, dr);
+  di = mma(ai, br, di);
+  di = mms(ar, bi, di);
+}
+
+// 16x16 output-layout tile transposed through LDS: out register i holds in[c16][q + 4 i].
+__device__ __forceinline__ void tile_transpose(const v4d& inr, const v4d& ini, v4d& outr, v4d& outi, double2* buf,
+                                               int q, int c16) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) buf[(q + 4 * i) * 17 + c16] = make_double2(inr[i], ini[i]);
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double2 v = buf[c16 * 17 + q + 4 * i];
+    outr[i] = v.x;
+    outi[i] = v.y;
+  }
+  wave_sync();
+}
+
+// Re sum over this lane's registers of a[i] b[i] (complex).
+__device__ __forceinline__ double re_dot4(const v4d& ar, const v4d& ai, const v4d& br, const v4d& bi) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) s += ar[i] * br[i] - ai[i] * bi[i];
+  return s;
+}
+
+// Projector fragment S[al][bd] (zero outside nc x nb).  VOL re-reads it from
+// the cache hierarchy at every use instead of keeping it in registers.
+template <bool VOL>
+__device__ __forceinline__ double2 lr_proj(const double2* P, int al, int bd, int nc, int nb) {
+  double2 v = make_double2(0.0, 0.0);
+  if (al < nc && bd < nb) {
+    if constexpr (VOL) {
+      const volatile double* pv = reinterpret_cast<const volatile double*>(P + al * nb + bd);
+      v.x = pv[0];
+      v.y = pv[1];
+    } else {
+      v = P[al * nb + bd];
+    }
+  }
+  return v;
+}
+
+// One (k-tile, frequency-tile) work item on one wavefront.  VOL: the projector
+// fragments are re-read at every use (fewer live registers next to the running
+// sum of G) instead of being kept in registers across the frequency loop.
+template <int NBP, int KIND, bool VOL>
+__device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile, LRShared& sh, int lane) {
+  constexpr int T = NBP / 16;
+  const int q = lane >> 4, c16 = lane & 15;
+  const int n0 = wtile * a.wt;
+  const int n1 = min(n0 + a.wt, a.nw);
+  const int kk0 = ktile * a.kt;
+  const int kk1 = min(kk0 + a.kt, a.nklist);
+  const double mu = a.mu_ptr ? *a.mu_ptr : a.mu;
+  const int nc = a.nc;
+  const int kc = (nc + 3) >> 2;  // orbital chunks of 4 that hold any correlated orbital
+  const double beta = a.beta;
+  const bool want_s = (KIND == KIND_DENSITY) && (a.mode & MODE_S);
+  const bool want_x = (KIND == KIND_DENSITY) && (a.mode & MODE_GLOC);
+  const bool hasdiag = c16 >= q && ((c16 - q) & 3) == 0;
+  const int idg = (c16 - q) >> 2;
+  int bad = 0, nonfinite = 0;
+
+  for (int kk = kk0; kk < kk1; ++kk) {
+    const int k = a.klist ? a.klist[kk] : kk;
+    const int nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
+    const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
+    const double* eps = a.eps + ob;
+    const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
+    const double wk = a.wk[k];
+    Proj<NBP> pr;  // pa: S[q + 4 j][16 b + c16],  pt: S[c16][16 t + 4 i + q]
+    if constexpr (!VOL) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+          double2 v = lr_proj<false>(P, q + 4 * j, 16 * b + c16, nc, nb);
+          pr.pa_r[j][b] = v.x;
+          pr.pa_i[j][b] = v.y;
+        }
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          double2 v = lr_proj<false>(P, c16, 16 * t + 4 * i + q, nc, nb);
+          pr.pt_r[t][i] = v.x;
+          pr.pt_i[t][i] = v.y;
+        }
+    }
+    // band energies at this lane's rows (ea) and column (eb)
+    double ea[T][4], eb[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      int r = 16 * t + c16;
+      eb[t] = r < nb ? eps[r] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int r2 = 16 * t + 4 * i + q;
+        ea[t][i] = r2 < nb ? eps[r2] : 0.0;
+      }
+    }
+    Mat<NBP> sacc;
+    if (want_s) {
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int b = 0; b < T; ++b) sacc.re[t][b] = sacc.im[t][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+    }
+    double trg = 0.0, trg2 = 0.0;
+
+    for (int n = n0; n < n1; ++n) {
+      const double wn = (double)(2 * n + 1) * M_PI / beta;
+      double2 dcol[T];  // d at band 16 t + c16 (zero for padding)
+#pragma unroll
+      for (int t = 0; t < T; ++t) dcol[t] = 16 * t + c16 < nb ? inv_z_minus(mu, wn, eb[t]) : make_double2(0.0, 0.0);
+      // X = S D S^dag (and X2, X3 for the traces), contracted over the bands
+      v4d xr = {0.0, 0.0, 0.0, 0.0}, xi = xr, x2r = xr, x2i = xr, x3r = xr, x3i = xr;
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (16 * t + 4 * i >= nb) break;  // chunks of padding bands only (uniform)
+          double2 s;
+          if constexpr (VOL)
+            s = lr_proj<true>(P, c16, 16 * t + 4 * i + q, nc, nb);
+          else
+            s = make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
+          const bool valid = 16 * t + 4 * i + q < nb;
+          double2 dd = valid ? inv_z_minus(mu, wn, ea[t][i]) : make_double2(0.0, 0.0);
+          double2 a1 = cmul(s, dd);
+          cmma_cb(xr, xi, a1.x, a1.y, s.x, s.y);
+          if constexpr (KIND == KIND_TRACE) {
+            double2 a2 = cmul(a1, dd);
+            cmma_cb(x2r, x2i, a2.x, a2.y, s.x, s.y);
+            double2 a3 = cmul(a2, dd);
+            cmma_cb(x3r, x3i, a3.x, a3.y, s.x, s.y);
+          }
+        }
+      // Sigma' in both orientations: sa = Sigma'[c16][q + 4 j], sb-regs = Sigma'[q + 4 i][c16]
+      const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)n * nc * nc;
+      double sa_r[4], sa_i[4];
+      v4d sbr, sbi;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int be = q + 4 * j;
+        bool in = c16 < nc && be < nc;
+        double2 v = in ? sg[c16 * nc + be] : make_double2(0.0, 0.0);
+        double2 u = in ? sg[be * nc + c16] : make_double2(0.0, 0.0);
+        if (c16 == be && in) {
+          v.x -= a.e_dc[c16];
+          u.x -= a.e_dc[c16];
+        }
+        sa_r[j] = v.x;
+        sa_i[j] = v.y;
+        sbr[j] = u.x;
+        sbi[j] = u.y;
+      }
+      // Xi = X^-1, Gl = (Xi - Sigma')^-1 = S G S^dag (the padding block stays zero)
+      Mat<16> m;
+      m.re[0][0] = xr;
+      m.im[0][0] = xi;
+      gauss_jordan<16, 1>(m, sh.gj, q, c16, nc, bad);
+      const v4d xir = m.re[0][0], xii = m.im[0][0];
+      m.re[0][0] = xir - sbr;
+      m.im[0][0] = xii - sbi;
+      gauss_jordan<16, 1>(m, sh.gj, q, c16, nc, bad);
+      const v4d glr = m.re[0][0], gli = m.im[0][0];
+      // V = Gl^T Sigma'^T, R^T = Xi^T V
+      v4d vr = {0.0, 0.0, 0.0, 0.0}, vi = vr, rtr = vr, rti = vr;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j >= kc) break;
+        cmma(vr, vi, glr[j], gli[j], sa_r[j], sa_i[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j >= kc) break;
+        cmma(rtr, rti, xir[j], xii[j], vr[j], vi[j]);
+      }
+
+      if constexpr (KIND == KIND_DENSITY) {
+        double chk = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
+        if (!__builtin_isfinite(chk)) nonfinite = 1;
+        if (want_s) {
+#pragma unroll
+          for (int b = 0; b < T; ++b) {
+            if (16 * b >= nb) break;  // tiles of padding bands only (uniform)
+            // Q_b = (R S)_b scaled by d on its columns
+            v4d qr = {0.0, 0.0, 0.0, 0.0}, qi = qr;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              double2 s;
+              if constexpr (VOL)
+                s = lr_proj<true>(P, q + 4 * j, 16 * b + c16, nc, nb);
+              else
+                s = make_double2(pr.pa_r[j][b], pr.pa_i[j][b]);
+              cmma(qr, qi, rtr[j], rti[j], s.x, s.y);
+            }
+            const double2 db = dcol[b];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              double2 v = cmul(make_double2(qr[i], qi[i]), db);
+              qr[i] = v.x;
+              qi[i] = v.y;
+            }
+            // column block b of sum_n G: += (D S^dag)_t Q_b, and D on the diagonal tile
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+              if (16 * t >= nb) break;
+              const double2 dt = dcol[t];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                double2 s;
+                if constexpr (VOL)
+                  s = lr_proj<true>(P, q + 4 * j, 16 * t + c16, nc, nb);
+                else
+                  s = make_double2(pr.pa_r[j][t], pr.pa_i[j][t]);
+                double2 aa = cmul(dt, make_double2(s.x, -s.y));
+                cmma(sacc.re[t][b], sacc.im[t][b], aa.x, aa.y, qr[j], qi[j]);
+              }
+              if (t == b) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                  if (hasdiag && idg == i) {
+                    sacc.re[t][t][i] += db.x;
+                    sacc.im[t][t][i] += db.y;
+                  }
+              }
+            }
+          }
+        }
+        if (want_x) {
+          // lane holds Gl[q + 4 i][c16]; add w_k Gl to this k tile's partial
+          double2* xp = reinterpret_cast<double2*>(a.xpart) + ((int64_t)(a.ktile_base + ktile) * a.nw + n) * 256;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (q + 4 * i < nc && c16 < nc) {
+              double2 v = make_double2(wk * glr[i], wk * gli[i]);
+              if (kk != kk0) {
+                double2 o = xp[i * 64 + lane];
+                v.x += o.x;
+                v.y += o.y;
+              }
+              xp[i * 64 + lane] = v;
+            }
+          }
+        }
+      } else {
+        // tr(R X_j) = sum over lanes of R^T-regs .* X_j-regs; tr(E^2) with E = R X2
+        v4d er = {0.0, 0.0, 0.0, 0.0}, ei = er, etr, eti;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (j >= kc) break;
+          cmma(er, ei, rtr[j], rti[j], x2r[j], x2i[j]);
+        }
+        tile_transpose(er, ei, etr, eti, sh.tp, q, c16);
+        double t2 = re_dot4(rtr, rti, x2r, x2i);
+        double t3 = re_dot4(rtr, rti, x3r, x3i);
+        double ee = re_dot4(er, ei, etr, eti);
+        // sum over bands of Re d and Re d^2: band 16 t + c16, counted on the q = 0 lanes
+        double sd = 0.0, sd2 = 0.0;
+        if (q == 0) {
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            sd += dcol[t].x;
+            sd2 += dcol[t].x * dcol[t].x - dcol[t].y * dcol[t].y;
+          }
+        }
+        trg += sd + t2;
+        trg2 += sd2 + 2.0 * t3 + ee;
+      }
+    }  // frequencies
+
+    if (want_s) {
+      double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int b = 0; b < T; ++b)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            int e = (t * T + b) * 4 + i;
+            sp[e * 64 + lane] = make_double2(sacc.re[t][b][i], sacc.im[t][b][i]);
+          }
+    }
+    if constexpr (KIND == KIND_TRACE) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        trg += __shfl_xor(trg, off);
+        trg2 += __shfl_xor(trg2, off);
+      }
+      if (!__builtin_isfinite(trg) || !__builtin_isfinite(trg2)) nonfinite = 1;
+      if (lane == 0) {
+        a.tpart[((int64_t)wtile * a.nk + k) * 2 + 0] = trg;
+        a.tpart[((int64_t)wtile * a.nk + k) * 2 + 1] = trg2;
+      }
+    }
+  }  // k
+  if (bad) atomicOr(a.err, ERR_SINGULAR);
+  if (nonfinite) atomicOr(a.err, ERR_NONFINITE);
+}
+
+template <int NBP, int KIND, bool VOL, int OCC>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) lr_kernel(DysonArgs a) {
+  __shared__ LRShared sh;
+  lr_tile<NBP, KIND, VOL>(a, blockIdx.x / a.n_wtiles, blockIdx.x % a.n_wtiles, sh, threadIdx.x);
+}
+
+}  // namespace dmft
