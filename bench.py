@@ -42,6 +42,26 @@ def flops_per_eval(nb, nc):
     return 8.0 * (nb ** 3 + 2.0 * nb * nb * nc + 2.0 * nb * nc * nc)
 
 
+def flops_per_eval_lowrank(nb, nc):
+    """Algorithmic FP64 flops of one density-pass evaluation in the low-rank
+    (Woodbury) form: X = S D S^dag (Nb Nc^2 complex MACs), invert X and
+    K = X^-1 - Sigma' (2 Nc^3), R = Sigma' K^-1 X^-1 (2 Nc^3), R S (Nb Nc^2),
+    D S^dag (R S D) (Nb^2 Nc); 8 real flops per complex multiply-add."""
+    return 8.0 * (nb * nb * nc + 2.0 * nb * nc * nc + 4.0 * nc ** 3)
+
+
+def density_kernel(ctx, nb, nc):
+    """(kernel name, algorithmic flops per evaluation) of the density-pass
+    kernel the context will run for this band window."""
+    nbp = (nb + 15) // 16 * 16
+    var = ctx.get_variant(0, nbp)
+    if var >= 0 and var & 8:
+        return "lr_kernel<%d, density> (low-rank, variant %d)" % (nbp, var), flops_per_eval_lowrank(nb, nc)
+    if nbp == 64:
+        return "d64::kernel<density> (variant %d)" % var, flops_per_eval(nb, nc)
+    return "dyson_kernel<%d, density> (variant %d)" % (nbp, var), flops_per_eval(nb, nc)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,15 +166,18 @@ def batched(ctx, steps=2):
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
     evals = sum(l.nk for l in wl.lattices) * wl.sigmas[0].nw
+    from paper_1111_2157_amd.dyson import FORM_LOWRANK
+    lowrank = ctx.batched_form() == FORM_LOWRANK
+    per_eval = flops_per_eval_lowrank if lowrank else flops_per_eval
     flops = 0.0
     for l, s in zip(wl.lattices, wl.sigmas):
-        nb = l.nb.astype(float)
-        flops += s.nw * float(np.sum(8.0 * (nb ** 3 + 2 * nb * nb * l.nc + 2 * nb * l.nc * l.nc)))
+        flops += s.nw * float(np.sum(per_eval(l.nb.astype(float), float(l.nc))))
     del nks, gls
     ctx._b_ws = None
     torch.cuda.empty_cache()
     return {"workload": wl.name, "evals_per_s": evals / sec, "ms_per_pass": sec * 1e3,
-            "tflops": flops / sec / 1e12, "plan_seconds": plan_s, "graph": True}
+            "form": "low-rank" if lowrank else "dense", "tflops": flops / sec / 1e12,
+            "plan_seconds": plan_s, "graph": True}
 
 
 def main():
@@ -181,7 +204,8 @@ def main():
     sec, kms, launches = time_density(ctx, lat, sig, mu, args.steps, args.warmup)
     nk, nw, nb, nc = wl.lattice.nk, sig.nw, wl.lattice.nb_max, wl.lattice.nc
     evals = nk * nw
-    fl = flops_per_eval(nb, nc) * evals
+    kname, fpe = density_kernel(ctx, nb, nc)
+    fl = fpe * evals
     kavg = kms / max(launches, 1) / 1e3
     achieved = fl / kavg / 1e12
     rec = {
@@ -201,8 +225,8 @@ def main():
                    "mu": mu, "outputs": "N(k), G_loc, N_tot/n_corr/<H_KS>", "tail_order": 2},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "dyson_kernel<32, density>", "kernel_ms": kavg * 1e3,
-                     "flop_per_eval": flops_per_eval(nb, nc)},
+                     "kernel": kname, "kernel_ms": kavg * 1e3, "flop_per_eval": fpe,
+                     "dense_flop_per_eval": flops_per_eval(nb, nc)},
         "autotune": tune,
     }
     if not args.no_mu:
@@ -216,8 +240,9 @@ def main():
                 ctx.autotune(l2, s2, w.mu)
             sc, km, ln = time_density(ctx, l2, s2, w.mu, 3 if name != "plain" else 20, 1)
             ev = w.lattice.nk * s2.nw
-            f = flops_per_eval(w.lattice.nb_max, w.lattice.nc) * ev
-            extra[w.name] = {"evals_per_s": ev / sc, "ms_per_pass": sc * 1e3,
+            kn, fp = density_kernel(ctx, w.lattice.nb_max, w.lattice.nc)
+            f = fp * ev
+            extra[w.name] = {"evals_per_s": ev / sc, "ms_per_pass": sc * 1e3, "kernel": kn,
                              "kernel_tflops": f / (km / max(ln, 1) / 1e3) / 1e12}
         rec["extra"] = extra
     if args.batched:

@@ -182,7 +182,9 @@ int find_mu(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, int t
  * iterate's mu from mu_dev (DEVICE [n_iter]) and is safe to capture in a
  * hipGraph.  Per iterate s: nk_out[s] and gloc_out[s] (DEVICE, layouts as in
  * density_matrix; either may be NULL).  lat[s]/sig[s] must stay unchanged
- * between plan and pass. */
+ * between plan and pass.  The plan times the persistent launch for the dense
+ * and the low-rank form of the step (see dmft_variants) and a few frequency-
+ * tile sizes, and keeps the fastest; this runs the kernel several times. */
 int dmft_batched_workspace_size(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
                                 const dmft_sigma* const* sig, size_t* bytes);
 int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
@@ -197,6 +199,15 @@ int dmft_batched_graph_capture(dmft_handle h, const double* mu_dev, double* cons
                                hipStream_t stream);
 int dmft_batched_graph_launch(dmft_handle h, hipStream_t stream);
 
+/* Form of the step used by later batched plans on this handle: DMFT_FORM_AUTO
+ * (default; the plan times both), DMFT_FORM_DENSE or DMFT_FORM_LOWRANK.
+ * Returns DMFT_EINVAL for another value.  dmft_batched_form returns the form
+ * of the current plan (DMFT_FORM_DENSE or DMFT_FORM_LOWRANK), or -1 if there
+ * is none. */
+enum { DMFT_FORM_AUTO = -1, DMFT_FORM_DENSE = 0, DMFT_FORM_LOWRANK = 1 };
+int dmft_batched_set_form(dmft_handle h, int form);
+int dmft_batched_form(dmft_handle h);
+
 /* Autotuner: times every compiled kernel variant that fits this shape on the
  * handle's GPU, after checking that each one reproduces the reference variant,
  * and caches the fastest in the handle (used by all later calls of that
@@ -206,12 +217,23 @@ int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
 
 /* Kernel variants.  kind 0 = density pass (density_matrix, gloc_compute),
  * kind 1 = trace pass (dmft_ntot, find_mu); nbp = padded band-window size
- * (16, 32 or 48).  dmft_variants writes up to max variant codes into out (HOST)
- * and returns their number (the first is the default); dmft_set_variant pins
- * one for later calls on this handle (var = -1 restores the default) and
- * returns DMFT_EINVAL for a code that is not instantiated. */
+ * (16, 32, 48 or 64).  dmft_variants writes up to max variant codes into out
+ * (HOST) and returns their number (the first is the default); dmft_set_variant
+ * pins one for later calls on this handle (var = -1 restores the default) and
+ * returns DMFT_EINVAL for a code that is not instantiated; dmft_get_variant
+ * returns the code later calls of that kind and size will use (the pinned or
+ * autotuned one, else the default), or -1 for a size with no kernel.
+ *
+ * Codes with bit 3 (8) set select the low-rank form of the same step: with
+ * D = diag(1 / (i w_n + mu - E_v)) and X = P D P^dag (nc x nc), the Woodbury
+ * identity gives P G P^dag = (X^-1 - Sigma')^-1 and G = D + D P^dag R P D,
+ * R = Sigma' (X^-1 - Sigma')^-1 X^-1, so only nc x nc matrices are inverted.
+ * It gives the same outputs to rounding and assumes, as the projector
+ * construction of the projection section provides, that the rows of P(k) are
+ * orthonormal; other bits of a code tune registers and occupancy only. */
 int dmft_variants(int kind, int nbp, int* out, int max);
 int dmft_set_variant(dmft_handle h, int kind, int nbp, int var);
+int dmft_get_variant(dmft_handle h, int kind, int nbp);
 
 /* Kernel timing (for roofline reports).  enable = 1 clears the counters and
  * starts recording a pair of hipEvents around every launch of the Dyson kernel

@@ -17,13 +17,14 @@ EXPORTS = [
     "gloc_compute", "density_matrix", "dmft_ntot", "dmft_ntot_vjp", "density_matrix_vjp", "find_mu",
     "dmft_batched_workspace_size", "dmft_batched_plan", "dmft_batched_pass",
     "dmft_batched_graph_capture", "dmft_batched_graph_launch", "dmft_autotune", "dmft_variants",
-    "dmft_set_variant", "dmft_timing",
+    "dmft_set_variant", "dmft_get_variant", "dmft_timing", "dmft_batched_set_form", "dmft_batched_form",
     "dmft_sync_status",
 ]
 
 STATUS = {0: "DMFT_OK", -1: "DMFT_EINVAL", -2: "DMFT_EHIP", -3: "DMFT_ENONFINITE",
           -4: "DMFT_ESINGULAR", -5: "DMFT_ENOCONV", -6: "DMFT_EWORKSPACE", -7: "DMFT_EUNSUPPORTED"}
 NEWTON, BISECT = 0, 1
+FORM_AUTO, FORM_DENSE, FORM_LOWRANK = -1, 0, 1
 
 
 class DmftLattice(C.Structure):
@@ -76,6 +77,9 @@ def load():
         "dmft_autotune": ([P, lp, sp, D, P, S, P, C.c_char_p, S], I),
         "dmft_variants": ([I, I, C.POINTER(I), I], I),
         "dmft_set_variant": ([P, I, I, I], I),
+        "dmft_get_variant": ([P, I, I], I),
+        "dmft_batched_set_form": ([P, I], I),
+        "dmft_batched_form": ([P], I),
         "dmft_timing": ([P, I, C.POINTER(D), C.POINTER(C.c_int64)], I),
         "dmft_sync_status": ([P, P, P], I),
     }

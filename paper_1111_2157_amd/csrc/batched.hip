@@ -9,7 +9,12 @@
 // from the second queue until it is empty; no work-group barrier is executed
 // in phase 2.  Every wavefront reaches the end of both queues, so the grid
 // always drains.  Queue counters are reset by a small kernel before each pass.
+//
+// batched_lr_kernel is the same persistent walk for the low-rank form of the
+// step (lowrank_impl.h), where every band-window size fits one wavefront:
+// single-wavefront work-groups pull items of any size from one queue.
 #include "dyson64_impl.h"
+#include "lowrank_impl.h"
 
 namespace dmft {
 
@@ -73,6 +78,35 @@ hipError_t launch_batched(const void* items, int n_big, int n_small, const Dyson
                           int n_workgroups, hipStream_t s) {
   hipLaunchKernelGGL(batched_kernel, dim3(n_workgroups), dim3(128), 0, s, reinterpret_cast<const BatchItem*>(items),
                      n_big, n_small, args, counters);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(64) batched_lr_kernel(const BatchItem* items, int n_items, const DysonArgs* args,
+                                                        int* counters) {
+  __shared__ LRShared sh;
+  const int lane = threadIdx.x;
+  for (;;) {
+    int it = 0;
+    if (lane == 0) it = atomicAdd(&counters[0], 1);
+    it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
+    if (it >= n_items) break;
+    const BatchItem b = items[it];
+    const DysonArgs a = args[b.args];
+    // nbp: padded size in the low byte, column part of a 64-band item in bit 8
+    const int part = b.nbp >> 8;
+    switch (b.nbp & 255) {
+      case 64: lr_tile<64, KIND_DENSITY, true>(a, b.ktile, b.wtile, part, sh, lane); break;
+      case 48: lr_tile<48, KIND_DENSITY, true>(a, b.ktile, b.wtile, 0, sh, lane); break;
+      case 32: lr_tile<32, KIND_DENSITY, false>(a, b.ktile, b.wtile, 0, sh, lane); break;
+      default: lr_tile<16, KIND_DENSITY, false>(a, b.ktile, b.wtile, 0, sh, lane); break;
+    }
+  }
+}
+
+hipError_t launch_batched_lr(const void* items, int n_items, const DysonArgs* args, int* counters, int n_workgroups,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(batched_lr_kernel, dim3(n_workgroups), dim3(64), 0, s,
+                     reinterpret_cast<const BatchItem*>(items), n_items, args, counters);
   return hipGetLastError();
 }
 

@@ -82,6 +82,8 @@ struct dmft_handle_s {
   int b_tail = 2;
   size_t b_total = 0, b_args = 0, b_items = 0, b_counters = 0, b_mu = 0;
   int b_nbig = 0, b_nsmall = 0, b_nargs = 0, b_wgs = 0;
+  bool b_lowrank = false;                // batched items use the low-rank form
+  int b_form_pref = DMFT_FORM_AUTO;      // form requested for later plans
   void* b_ws = nullptr;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -540,6 +542,11 @@ int dmft_variants(int kind, int nbp, int* out, int max) {
   return n;
 }
 
+int dmft_get_variant(dmft_handle h, int kind, int nbp) {
+  if (!h || (kind != 0 && kind != 1)) return -1;
+  return choose_var(h, kind, nbp);
+}
+
 int dmft_set_variant(dmft_handle h, int kind, int nbp, int var) {
   if (!h) return DMFT_EINVAL;
   char key[32];
@@ -876,7 +883,8 @@ int batched_layout(dmft_handle h, int n_iter, const dmft_lattice* const* lat, co
     o = align_up(o + Ls[s].total);
     for (const Bucket& b : Ls[s].buckets) {
       ++na;
-      ni += b.n_ktiles * Ls[s].n_wtiles;
+      // the low-rank form splits 64-band items into two column parts
+      ni += b.n_ktiles * Ls[s].n_wtiles * (b.nbp == 64 ? 2 : 1);
     }
   }
   *o_args = o;
@@ -902,8 +910,12 @@ int batched_pass_impl(dmft_handle h, const double* mu_dev, double* const* nk_out
   int n_iter = (int)h->iters.size();
   HIPCHK(h, launch_copy_doubles(mu_dev, (double*)(w + h->b_mu), n_iter, stream));
   HIPCHK(h, launch_fill_zero(w + h->b_counters, 2 * sizeof(int), stream));
-  HIPCHK(h, launch_batched(w + h->b_items, h->b_nbig, h->b_nsmall, (const DysonArgs*)(w + h->b_args),
-                           (int*)(w + h->b_counters), h->b_wgs, stream));
+  if (h->b_lowrank)
+    HIPCHK(h, launch_batched_lr(w + h->b_items, h->b_nsmall, (const DysonArgs*)(w + h->b_args),
+                                (int*)(w + h->b_counters), h->b_wgs, stream));
+  else
+    HIPCHK(h, launch_batched(w + h->b_items, h->b_nbig, h->b_nsmall, (const DysonArgs*)(w + h->b_args),
+                             (int*)(w + h->b_counters), h->b_wgs, stream));
   if (kernel_only) return DMFT_OK;
   for (int s = 0; s < n_iter; ++s) {
     const auto& it = h->iters[s];
@@ -919,7 +931,8 @@ int batched_pass_impl(dmft_handle h, const double* mu_dev, double* const* nk_out
 }
 
 int batched_build(dmft_handle h, int n_iter, const dmft_lattice* const* lat, const dmft_sigma* const* sig,
-                  int tail_order, void* ws, size_t ws_bytes, hipStream_t stream, const std::vector<Tile>* tiles) {
+                  int tail_order, void* ws, size_t ws_bytes, hipStream_t stream, const std::vector<Tile>* tiles,
+                  bool lowrank) {
   std::vector<Layout> Ls;
   std::vector<size_t> base;
   size_t total, o_args, o_items, o_cnt, o_mu;
@@ -986,13 +999,22 @@ int batched_build(dmft_handle h, int n_iter, const dmft_lattice* const* lat, con
       int ai = (int)args.size();
       args.push_back(a);
       at += b.klist.size();
+      const double nbp = b.nbp, nc = lat[s]->nc;
       for (int kt = 0; kt < b.n_ktiles; ++kt) {
         int nkt = std::min(L.tile.kt, (int)b.klist.size() - kt * L.tile.kt);
         for (int wt = 0; wt < L.n_wtiles; ++wt) {
           int nwt = std::min(L.tile.wt, sig[s]->nw - wt * L.tile.wt);
-          double c = (double)b.nbp * b.nbp * (b.nbp + 2.0 * lat[s]->nc) * nkt * nwt;
-          Q qq{{ai, b.nbp, kt, wt}, c};
-          (b.nbp == 64 ? big : small).push_back(qq);
+          if (lowrank) {
+            // one queue; 64-band items in two column parts (size in the low
+            // byte of nbp, part in bit 8)
+            int parts = b.nbp == 64 ? 2 : 1;
+            double c = (nbp * nbp * nc / parts + 2.0 * nbp * nc * nc + 4.0 * nc * nc * nc) * nkt * nwt;
+            for (int part = 0; part < parts; ++part) small.push_back(Q{{ai, b.nbp | (part << 8), kt, wt}, c});
+          } else {
+            double c = nbp * nbp * (nbp + 2.0 * nc) * nkt * nwt;
+            Q qq{{ai, b.nbp, kt, wt}, c};
+            (b.nbp == 64 ? big : small).push_back(qq);
+          }
         }
       }
     }
@@ -1019,7 +1041,10 @@ int batched_build(dmft_handle h, int n_iter, const dmft_lattice* const* lat, con
   h->b_nbig = (int)big.size();
   h->b_nsmall = (int)small.size();
   h->b_nargs = (int)args.size();
-  h->b_wgs = 2 * std::max(ncu, 1);
+  h->b_lowrank = lowrank;
+  // dense: two-wavefront work-groups, one per SIMD pair; low-rank: one
+  // wavefront per work-group and per SIMD (the kernel runs one wave per SIMD)
+  h->b_wgs = (lowrank ? 4 : 2) * std::max(ncu, 1);
   h->b_ws = ws;
   return DMFT_OK;
 }
@@ -1053,49 +1078,53 @@ int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
     (void)hipGraphDestroy(h->graph);
     h->graph = nullptr;
   }
-  int r = batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, nullptr);
+  int r = batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, nullptr, false);
   if (r) return r;
-  // Autotune the frequency-tile size of the persistent launch: time the kernel
-  // with a few tile sizes that fit the workspace, keep the fastest plan.
+  // Autotune the form of the step (dense inversion or low-rank) and the
+  // frequency-tile size of the persistent launch: time the kernel for each
+  // candidate that fits the workspace, keep the fastest plan.
   std::vector<Tile> base_tiles;
   for (auto& it : h->iters) base_tiles.push_back(it.lay.tile);
   std::vector<double> mu0(n_iter, 0.0);
   char* w = (char*)ws;
-  double* mu_tmp = (double*)(w + h->b_mu);
-  HIPCHK(h, hipMemcpy(mu_tmp, mu0.data(), sizeof(double) * n_iter, hipMemcpyHostToDevice));
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
   double best = 1e300;
   std::vector<Tile> best_tiles = base_tiles;
-  for (int f : {1, 2, 4}) {
-    std::vector<Tile> cand = base_tiles;
-    for (int s = 0; s < n_iter; ++s) cand[s].wt = std::max(4, base_tiles[s].wt / f);
-    std::vector<Layout> Ls;
-    std::vector<size_t> bs;
-    size_t total, a, b, c, d;
-    int na, ni;
-    r = batched_layout(h, n_iter, lat, sig, Ls, bs, &cand, &total, &a, &b, &c, &d, &na, &ni);
-    if (r) return r;
-    if (total > ws_bytes) continue;
-    r = batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, &cand);
-    if (r) return r;
-    HIPCHK(h, hipMemcpy(w + h->b_mu, mu0.data(), sizeof(double) * n_iter, hipMemcpyHostToDevice));
-    HIPCHK(h, hipEventRecord(e0, stream));
-    r = batched_pass_impl(h, (const double*)(w + h->b_mu), nullptr, nullptr, ws, ws_bytes, stream, true);
-    if (r) return r;
-    HIPCHK(h, hipEventRecord(e1, stream));
-    HIPCHK(h, hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
-      best = ms;
-      best_tiles = cand;
+  bool best_lr = false;
+  for (bool lr : {false, true}) {
+    if (h->b_form_pref != DMFT_FORM_AUTO && lr != (h->b_form_pref == DMFT_FORM_LOWRANK)) continue;
+    for (int f : {1, 2, 4}) {
+      std::vector<Tile> cand = base_tiles;
+      for (int s = 0; s < n_iter; ++s) cand[s].wt = std::max(4, base_tiles[s].wt / f);
+      std::vector<Layout> Ls;
+      std::vector<size_t> bs;
+      size_t total, a, b, c, d;
+      int na, ni;
+      r = batched_layout(h, n_iter, lat, sig, Ls, bs, &cand, &total, &a, &b, &c, &d, &na, &ni);
+      if (r) return r;
+      if (total > ws_bytes) continue;
+      r = batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, &cand, lr);
+      if (r) return r;
+      HIPCHK(h, hipMemcpy(w + h->b_mu, mu0.data(), sizeof(double) * n_iter, hipMemcpyHostToDevice));
+      HIPCHK(h, hipEventRecord(e0, stream));
+      r = batched_pass_impl(h, (const double*)(w + h->b_mu), nullptr, nullptr, ws, ws_bytes, stream, true);
+      if (r) return r;
+      HIPCHK(h, hipEventRecord(e1, stream));
+      HIPCHK(h, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_tiles = cand;
+        best_lr = lr;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, &best_tiles);
+  return batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, &best_tiles, best_lr);
 }
 
 int dmft_batched_pass(dmft_handle h, const double* mu_dev, double* const* nk_out, double* const* gloc_out, void* ws,
@@ -1129,6 +1158,19 @@ int dmft_batched_graph_capture(dmft_handle h, const double* mu_dev, double* cons
   h->graph = g;
   HIPCHK(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
   return dmft_batched_graph_launch(h, stream);
+}
+
+int dmft_batched_set_form(dmft_handle h, int form) {
+  if (!h) return DMFT_EINVAL;
+  if (form != DMFT_FORM_AUTO && form != DMFT_FORM_DENSE && form != DMFT_FORM_LOWRANK)
+    return fail(h, DMFT_EINVAL, "unknown batched form %d", form);
+  h->b_form_pref = form;
+  return DMFT_OK;
+}
+
+int dmft_batched_form(dmft_handle h) {
+  if (!h || h->iters.empty()) return -1;
+  return h->b_lowrank ? DMFT_FORM_LOWRANK : DMFT_FORM_DENSE;
 }
 
 int dmft_batched_graph_launch(dmft_handle h, hipStream_t stream) {

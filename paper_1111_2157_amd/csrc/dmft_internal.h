@@ -106,6 +106,9 @@ struct BatchItemHost {
 };
 hipError_t launch_batched(const void* items, int n_big, int n_small, const DysonArgs* args, int* counters,
                           int n_workgroups, hipStream_t s);
+// The same walk in the low-rank form: every item takes one single-wavefront work-group.
+hipError_t launch_batched_lr(const void* items, int n_items, const DysonArgs* args, int* counters, int n_workgroups,
+                             hipStream_t s);
 hipError_t launch_copy_doubles(const double* src, double* dst, int n, hipStream_t s);
 // Per-k [tr N, d tr N/dmu, mubar_k] from the adjoint partials (tail terms included).
 hipError_t launch_adj_epilogue(const EpilogueArgs& a, const double* nbar, hipStream_t s);

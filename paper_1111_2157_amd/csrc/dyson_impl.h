@@ -237,9 +237,22 @@ struct Proj {
   double pt_r[T][4], pt_i[T][4];  // S[c16][16 t + 4 i + q]
 };
 
+// Returns p unchanged but hides its value from the optimizer, so that loads
+// through the result stay where they are written: they are neither merged
+// with earlier loads of the same address nor hoisted out of a loop.  Unlike
+// volatile accesses, such loads are ordinary cached loads that the compiler
+// may still issue back to back and wait for together.
+template <class T>
+__device__ __forceinline__ const T* fresh(const T* p) {
+  asm volatile("" : "+v"(p));
+  return p;
+}
+
 // Projector fragments are re-read (from L1/L2) where they are used, so that they
-// do not occupy registers during the Gauss-Jordan sweep; the volatile access
-// keeps the compiler from hoisting them out of the frequency loop.
+// do not occupy registers during the Gauss-Jordan sweep.  The volatile access
+// also pins each load to its place in the program order (each one is waited
+// for before the next), which keeps the live ranges short in the kernels that
+// are tightest on registers.
 __device__ __forceinline__ double2 ld_proj(const double2* P, int al, int bd, int nc, int nb) {
   double2 v = make_double2(0.0, 0.0);
   if (al < nc && bd < nb) {

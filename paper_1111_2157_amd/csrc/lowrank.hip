@@ -3,9 +3,7 @@
 //
 // Variant id: bit 3 set (low-rank form), bit 0 = projector fragments re-read
 // at every use (VOL), bit 2 = two wavefronts per SIMD.  Each (size, kind)
-// lists the combinations that compile without register spills, except the
-// 64-band density kernel, whose 64x64 running sum leaves no spill-free choice
-// (its one variant spills 116 bytes per lane).
+// lists the combinations that compile without register spills.
 #include "lowrank_impl.h"
 
 namespace dmft {
@@ -14,6 +12,8 @@ template <int NBP, int KIND, int... VARS>
 struct LRSet {
   template <int VAR>
   static hipError_t one(const DysonArgs& a, dim3 grid, hipStream_t s) {
+    constexpr int parts = (NBP / 16) / lr_col_tiles<NBP, KIND>();
+    grid.x *= parts;
     hipLaunchKernelGGL((lr_kernel<NBP, KIND, (VAR & 1) != 0, (VAR & 4) ? 2 : 1>), grid, dim3(64), 0, s, a);
     return hipGetLastError();
   }
@@ -33,7 +33,7 @@ struct LRSet {
 using LD16 = LRSet<16, KIND_DENSITY, 8, 9>;
 using LD32 = LRSet<32, KIND_DENSITY, 9, 13, 8>;
 using LD48 = LRSet<48, KIND_DENSITY, 9, 8>;
-using LD64 = LRSet<64, KIND_DENSITY, 9>;
+using LD64 = LRSet<64, KIND_DENSITY, 9, 8>;
 using LT16 = LRSet<16, KIND_TRACE, 8, 9>;
 using LT32 = LRSet<32, KIND_TRACE, 12, 13, 8>;
 using LT48 = LRSet<48, KIND_TRACE, 12, 13, 8>;

@@ -103,25 +103,30 @@ __device__ __forceinline__ double re_dot4(const v4d& ar, const v4d& ai, const v4
 // the cache hierarchy at every use instead of keeping it in registers.
 template <bool VOL>
 __device__ __forceinline__ double2 lr_proj(const double2* P, int al, int bd, int nc, int nb) {
-  double2 v = make_double2(0.0, 0.0);
-  if (al < nc && bd < nb) {
-    if constexpr (VOL) {
-      const volatile double* pv = reinterpret_cast<const volatile double*>(P + al * nb + bd);
-      v.x = pv[0];
-      v.y = pv[1];
-    } else {
-      v = P[al * nb + bd];
-    }
-  }
-  return v;
+  if constexpr (VOL) P = fresh(P);
+  return (al < nc && bd < nb) ? P[al * nb + bd] : make_double2(0.0, 0.0);
 }
 
-// One (k-tile, frequency-tile) work item on one wavefront.  VOL: the projector
-// fragments are re-read at every use (fewer live registers next to the running
-// sum of G) instead of being kept in registers across the frequency loop.
-template <int NBP, int KIND, bool VOL>
-__device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile, LRShared& sh, int lane) {
+// Column tiles of sum_n G one work item keeps: all of them, except for 64-band
+// windows, whose 64x64 running sum would not fit next to the rest in
+// registers; those are split into two items of 32 columns each (the nc x nc
+// part of the step is then computed once per item).
+template <int NBP, int KIND>
+constexpr int lr_col_tiles() {
+  return (KIND == KIND_DENSITY && NBP == 64) ? 2 : NBP / 16;
+}
+
+// One (k-tile, frequency-tile, column-part) work item on one wavefront.  VOL:
+// the projector fragments are re-read at every use (fewer live registers next
+// to the running sum of G) instead of being kept in registers across the
+// frequency loop.  Column part `part` covers the column tiles
+// [part CT, (part + 1) CT) of sum_n G; part 0 also writes the G_loc partials.
+template <int NBP, int KIND, bool VOL, int PART>
+__device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int wtile, LRShared& sh, int lane) {
   constexpr int T = NBP / 16;
+  constexpr int CT = lr_col_tiles<NBP, KIND>();
+  constexpr int b0 = PART * CT;
+  constexpr int part = PART;
   const int q = lane >> 4, c16 = lane & 15;
   const int n0 = wtile * a.wt;
   const int n1 = min(n0 + a.wt, a.nw);
@@ -132,7 +137,7 @@ __device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile
   const int kc = (nc + 3) >> 2;  // orbital chunks of 4 that hold any correlated orbital
   const double beta = a.beta;
   const bool want_s = (KIND == KIND_DENSITY) && (a.mode & MODE_S);
-  const bool want_x = (KIND == KIND_DENSITY) && (a.mode & MODE_GLOC);
+  const bool want_x = (KIND == KIND_DENSITY) && (a.mode & MODE_GLOC) && part == 0;
   const bool hasdiag = c16 >= q && ((c16 - q) & 3) == 0;
   const int idg = (c16 - q) >> 2;
   int bad = 0, nonfinite = 0;
@@ -175,12 +180,12 @@ __device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile
         ea[t][i] = r2 < nb ? eps[r2] : 0.0;
       }
     }
-    Mat<NBP> sacc;
+    v4d sre[T][CT], sim[T][CT];  // running sum of G, column tiles b0 .. b0 + CT
     if (want_s) {
 #pragma unroll
       for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int b = 0; b < T; ++b) sacc.re[t][b] = sacc.im[t][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+        for (int c = 0; c < CT; ++c) sre[t][c] = sim[t][c] = (v4d){0.0, 0.0, 0.0, 0.0};
     }
     double trg = 0.0, trg2 = 0.0;
 
@@ -261,7 +266,8 @@ __device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile
         if (!__builtin_isfinite(chk)) nonfinite = 1;
         if (want_s) {
 #pragma unroll
-          for (int b = 0; b < T; ++b) {
+          for (int c = 0; c < CT; ++c) {
+            const int b = b0 + c;
             if (16 * b >= nb) break;  // tiles of padding bands only (uniform)
             // Q_b = (R S)_b scaled by d on its columns
             v4d qr = {0.0, 0.0, 0.0, 0.0}, qi = qr;
@@ -296,14 +302,14 @@ __device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile
                 else
                   s = make_double2(pr.pa_r[j][t], pr.pa_i[j][t]);
                 double2 aa = cmul(dt, make_double2(s.x, -s.y));
-                cmma(sacc.re[t][b], sacc.im[t][b], aa.x, aa.y, qr[j], qi[j]);
+                cmma(sre[t][c], sim[t][c], aa.x, aa.y, qr[j], qi[j]);
               }
               if (t == b) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                   if (hasdiag && idg == i) {
-                    sacc.re[t][t][i] += db.x;
-                    sacc.im[t][t][i] += db.y;
+                    sre[t][c][i] += db.x;
+                    sim[t][c][i] += db.y;
                   }
               }
             }
@@ -356,11 +362,11 @@ __device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile
 #pragma unroll
       for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int b = 0; b < T; ++b)
+        for (int c = 0; c < CT; ++c)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            int e = (t * T + b) * 4 + i;
-            sp[e * 64 + lane] = make_double2(sacc.re[t][b][i], sacc.im[t][b][i]);
+            int e = (t * T + b0 + c) * 4 + i;
+            sp[e * 64 + lane] = make_double2(sre[t][c][i], sim[t][c][i]);
           }
     }
     if constexpr (KIND == KIND_TRACE) {
@@ -380,10 +386,25 @@ __device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile
   if (nonfinite) atomicOr(a.err, ERR_NONFINITE);
 }
 
+template <int NBP, int KIND, bool VOL>
+__device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile, int part, LRShared& sh, int lane) {
+  constexpr int NP = (NBP / 16) / lr_col_tiles<NBP, KIND>();
+  if constexpr (NP > 1) {
+    if (part) {
+      lr_tile_part<NBP, KIND, VOL, 1>(a, ktile, wtile, sh, lane);
+      return;
+    }
+  }
+  lr_tile_part<NBP, KIND, VOL, 0>(a, ktile, wtile, sh, lane);
+}
+
+// Grid: (k tiles x frequency tiles) x column parts, the column part fastest.
 template <int NBP, int KIND, bool VOL, int OCC>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) lr_kernel(DysonArgs a) {
   __shared__ LRShared sh;
-  lr_tile<NBP, KIND, VOL>(a, blockIdx.x / a.n_wtiles, blockIdx.x % a.n_wtiles, sh, threadIdx.x);
+  constexpr int NP = (NBP / 16) / lr_col_tiles<NBP, KIND>();
+  const int item = blockIdx.x / NP, part = blockIdx.x % NP;
+  lr_tile<NBP, KIND, VOL>(a, item / a.n_wtiles, item % a.n_wtiles, part, sh, threadIdx.x);
 }
 
 }  // namespace dmft

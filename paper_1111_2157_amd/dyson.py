@@ -14,9 +14,9 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BISECT, NEWTON, DmftLattice, DmftSigma, check
+from ._lib import BISECT, FORM_AUTO, FORM_DENSE, FORM_LOWRANK, NEWTON, DmftLattice, DmftSigma, check
 
-__all__ = ["Lattice", "SelfEnergy", "Context", "NEWTON", "BISECT"]
+__all__ = ["Lattice", "SelfEnergy", "Context", "NEWTON", "BISECT", "FORM_AUTO", "FORM_DENSE", "FORM_LOWRANK"]
 
 
 def _stream(device):
@@ -225,6 +225,14 @@ class Context:
                                                  C.c_size_t(self._b_ws.numel()), _stream(self.device)))
         return self._b_ws
 
+    def batched_set_form(self, form: int):
+        """Form of the step for later batched plans: FORM_AUTO (timed), FORM_DENSE, FORM_LOWRANK."""
+        check(self.h, self.lib.dmft_batched_set_form(self.h, int(form)))
+
+    def batched_form(self) -> int:
+        """Form of the current batched plan (FORM_DENSE or FORM_LOWRANK), -1 without a plan."""
+        return int(self.lib.dmft_batched_form(self.h))
+
     def _batched_ptrs(self, outs):
         n = len(self._b_ls)
         return (C.c_void_p * n)(*[(o.data_ptr() if o is not None else 0) for o in outs])
@@ -258,6 +266,10 @@ class Context:
 
     def set_variant(self, kind: int, nbp: int, var: int):
         check(self.h, self.lib.dmft_set_variant(self.h, int(kind), int(nbp), int(var)))
+
+    def get_variant(self, kind: int, nbp: int) -> int:
+        """The variant code later calls of this kind and padded size use."""
+        return int(self.lib.dmft_get_variant(self.h, int(kind), int(nbp)))
 
     def timing(self, enable: bool):
         """Returns (summed Dyson-kernel ms, timed launches) recorded so far."""

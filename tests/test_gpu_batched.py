@@ -10,14 +10,23 @@ from gpu_util import assert_gloc_parity, assert_nk_parity
 pytestmark = pytest.mark.gpu
 
 
-def _setup(n_iter=4, nk=10, nw=24):
-    from paper_1111_2157_amd.dyson import Context, Lattice, SelfEnergy
+FORMS = ["dense", "lowrank", "auto"]
+
+
+def _setup(n_iter=4, nk=10, nw=24, form="auto"):
+    from paper_1111_2157_amd.dyson import FORM_AUTO, FORM_DENSE, FORM_LOWRANK, Context, Lattice, SelfEnergy
 
     wl = synth.batched(nk=nk, nb_lo=14, nb_hi=64, nw=nw, n_iter=n_iter)
     ctx = Context(0)
     lats = [Lattice.from_host(l) for l in wl.lattices]
     sigs = [SelfEnergy.from_host(s) for s in wl.sigmas]
+    code = {"dense": FORM_DENSE, "lowrank": FORM_LOWRANK, "auto": FORM_AUTO}[form]
+    ctx.batched_set_form(code)
     ctx.batched_plan(lats, sigs, 2)
+    if form != "auto":
+        assert ctx.batched_form() == code
+    else:
+        assert ctx.batched_form() in (FORM_DENSE, FORM_LOWRANK)
     return wl, ctx, lats, sigs
 
 
@@ -30,10 +39,11 @@ def _split(nk_flat, lat):
     return out
 
 
-def test_batched_pass_matches_oracle():
+@pytest.mark.parametrize("form", FORMS)
+def test_batched_pass_matches_oracle(form):
     import torch
 
-    wl, ctx, lats, sigs = _setup()
+    wl, ctx, lats, sigs = _setup(form=form)
     mus = np.array([0.1, -0.3, 0.25, 0.0][:len(lats)])
     mu_dev = torch.as_tensor(mus, device="cuda")
     nks, gls = ctx.batched_outputs()
@@ -41,17 +51,18 @@ def test_batched_pass_matches_oracle():
     torch.cuda.synchronize()
     ctx.batched_sync_status()
     for s in range(len(lats)):
-        print("iterate", s, flush=True)
+        print("form", form, "iterate", s, flush=True)
         lat, sig = wl.lattices[s], wl.sigmas[s]
         assert_nk_parity(_split(nks[s].cpu().numpy(), lat), lat, sig, mus[s])
         assert_gloc_parity(gls[s].cpu().numpy(), lat, sig, mus[s])
     ctx.close()
 
 
-def test_batched_graph_replays():
+@pytest.mark.parametrize("form", ["dense", "lowrank"])
+def test_batched_graph_replays(form):
     import torch
 
-    wl, ctx, lats, sigs = _setup(n_iter=2, nk=8, nw=20)
+    wl, ctx, lats, sigs = _setup(n_iter=2, nk=8, nw=20, form=form)
     mu_dev = torch.zeros(2, dtype=torch.float64, device="cuda")
     nks, gls = ctx.batched_outputs()
     ctx.batched_graph_capture(mu_dev, nks, gls)
