@@ -109,7 +109,10 @@ class _Pack:
 
 
 def _threads(nthreads):
-    return int(nthreads) if nthreads else int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    """OpenMP threads: the argument, else ORACLE_THREADS, else the host's cores up to 16."""
+    if nthreads:
+        return int(nthreads)
+    return int(os.environ.get("ORACLE_THREADS", min(16, os.cpu_count() or 1)))
 
 
 def density(lat, sig, mu, tail_order=2, klist=None, nthreads=None):
