@@ -13,8 +13,10 @@ struct LRSet {
   template <int VAR>
   static hipError_t one(const DysonArgs& a, dim3 grid, hipStream_t s) {
     constexpr int parts = (NBP / 16) / lr_col_tiles<NBP, KIND>();
+    constexpr bool vol = (VAR & 1) != 0;
+    constexpr int occ = (VAR & 4) ? 2 : 1;
     grid.x *= parts;
-    hipLaunchKernelGGL((lr_kernel<NBP, KIND, (VAR & 1) != 0, (VAR & 4) ? 2 : 1>), grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL((lr_kernel<NBP, KIND, vol, occ>), grid, dim3(64), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t launch(int var, const DysonArgs& a, dim3 grid, hipStream_t s) {
@@ -31,13 +33,13 @@ struct LRSet {
 };
 
 using LD16 = LRSet<16, KIND_DENSITY, 8, 9>;
-using LD32 = LRSet<32, KIND_DENSITY, 9, 13, 8>;
-using LD48 = LRSet<48, KIND_DENSITY, 9, 8>;
-using LD64 = LRSet<64, KIND_DENSITY, 9, 8>;
-using LT16 = LRSet<16, KIND_TRACE, 8, 9>;
-using LT32 = LRSet<32, KIND_TRACE, 12, 13, 8>;
-using LT48 = LRSet<48, KIND_TRACE, 12, 13, 8>;
-using LT64 = LRSet<64, KIND_TRACE, 13, 9, 8>;
+using LD32 = LRSet<32, KIND_DENSITY, 8, 9>;
+using LD48 = LRSet<48, KIND_DENSITY, 8, 9>;
+using LD64 = LRSet<64, KIND_DENSITY, 9>;
+using LT16 = LRSet<16, KIND_TRACE, 12, 13, 8, 9>;
+using LT32 = LRSet<32, KIND_TRACE, 12, 13, 8, 9>;
+using LT48 = LRSet<48, KIND_TRACE, 13, 8, 9>;
+using LT64 = LRSet<64, KIND_TRACE, 13, 8, 9>;
 
 hipError_t launch_lowrank(int nbp, int var, const DysonArgs& a, dim3 grid, hipStream_t s) {
   const bool tr = (a.mode & MODE_TRACE) != 0;

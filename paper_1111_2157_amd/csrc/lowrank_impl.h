@@ -1,4 +1,4 @@
-// Low-rank form of the lattice Dyson step, on the register layout of dyson_impl.h.
+// Low-rank form of the lattice Dyson step (gfx950 / CDNA4).
 //
 // The self-energy enters the band window only through the nc correlated
 // orbitals (the embedding of the DMFT-loop section), so with D = diag(d),
@@ -8,46 +8,50 @@
 //
 //     X   = S D S^dag                      (projected bare propagator)
 //     K   = X^-1 - Sigma'
-//     R   = Sigma' K^-1 X^-1                (= (I - Sigma' X)^-1 Sigma')
+//     Gl  = K^-1                            (= S G S^dag)
+//     R   = Sigma' + Sigma' Gl Sigma'       (= (I - Sigma' X)^-1 Sigma', since Gl X^-1 = I + Gl Sigma')
 //
 // the Woodbury identity gives, exactly,
 //
 //     G           = D + D S^dag R S D
-//     S G S^dag   = K^-1
 //     tr G        = sum_v d_v + tr(R X2)                            X_j = S D^j S^dag
 //     tr G^2      = sum_v d_v^2 + 2 tr(R X3) + tr(R X2 R X2)
 //
 // so the nb^3 inversion becomes rank-nc products on the matrix cores and two
-// nc x nc inversions.  Both are done by the Gauss-Jordan sweep of dyson_impl.h
-// without pivoting, which is safe here for the same reason as for A: the rows
-// of S are orthonormal (the projector construction of the projection section),
-// so the anti-Hermitian part of X, S Im(D) S^dag, is negative definite; that of
-// K = X^-1 - Sigma' is then positive definite for a causal Sigma, and every
-// leading block of either matrix is invertible.
+// nc x nc inversions.  Both are Gauss-Jordan sweeps without pivoting, which is
+// safe for the same reason as for A: the rows of S are orthonormal (the
+// projector construction of the projection section), so the anti-Hermitian
+// part of X, S Im(D) S^dag, is negative definite; that of K = X^-1 - Sigma' is
+// then positive definite for a causal Sigma, and every leading block of either
+// matrix is invertible.
 //
-// Operand bookkeeping (16x16x4 matrix-core instruction): a matrix M used as the
-// A operand is taken from registers holding M^T in the output layout, as the
-// B operand from registers holding M.  Every product below is ordered so that
-// its operands are already in the right form, and no transpose is needed
-// except one (through LDS) in tr(E^2), E = R X2:
-//   X-regs        from  A = S[c16][r] d_r,  B = S[c16][r]  (conjugated)
-//   Xi-regs       Gauss-Jordan of X
-//   K-regs        Xi - Sigma'
-//   Gl-regs       Gauss-Jordan of K                          -> S G S^dag
-//   V  = Gl^T Sigma'^T     (A: Gl-regs,  B: Sigma'[c16][q + 4 j])
-//   R^T = Xi^T V           (A: Xi-regs,  B: V-regs)           -> R^T-regs hold R[c16][q + 4 i]
-//   Q  = (R S) D           (A: R^T-regs, B: S[q + 4 j][16 b + c16])
-//   sum_n G += D + (D S^dag) Q
+// One wavefront walks a (k-tile, frequency-tile) item, four frequencies at a
+// time:
+//   1. X_f = S D_f S^dag for f = 0..3 on the matrix cores (16x16x4 FP64,
+//      contraction over band chunks), staged through LDS;
+//   2. lane 16 g + i takes row i of X_g; both inversions run in this row
+//      layout for the four matrices at once (see rsweep), and Gl_g goes back
+//      through LDS;
+//   3. per frequency, in the output layout of the matrix core: R, then either
+//      sum_n G += D + (D S^dag)(R S D) and the w_k Gl partial of G_loc
+//      (density kind), or the traces (trace kind).
+//
+// Operand bookkeeping of the 16x16x4 instruction: a matrix M used as the A
+// operand comes from registers holding M^T in the output layout (lane
+// 16 q + c16, register i: row q + 4 i, column c16), as the B operand from
+// registers holding M.  The products are ordered so that their operands are
+// already in that form:
+//   X   from  A = S[c16][r] d_r,  B = S[c16][r] (conjugated)
+//   V   = Gl^T Sigma'^T      (A: Gl,           B: Sigma'[c16][q + 4 j])
+//   R^T = Sigma'^T + Sigma'^T V  (A: Sigma'[q + 4 j][c16], B: V)  -> R^T holds R[c16][q + 4 i]
+//   Q   = (R S) D            (A: R^T,          B: S[q + 4 j][16 b + c16])
+//   sum_n G += (D S^dag) Q   (A: d_r conj(S[q + 4 j][r]), B: Q)
+// and tr(E^2), E = R X2, takes one 16x16 transpose through LDS.
 #pragma once
 
 #include "dyson_impl.h"
 
 namespace dmft {
-
-struct LRShared {
-  GJShared<16> gj;
-  double2 tp[16 * 17];  // 16x16 transpose
-};
 
 // 1 / (zr + i zi - e) for real e.
 __device__ __forceinline__ double2 inv_z_minus(double zr, double zi, double e) {
@@ -116,28 +120,68 @@ constexpr int lr_col_tiles() {
   return (KIND == KIND_DENSITY && NBP == 64) ? 2 : NBP / 16;
 }
 
-// One (k-tile, frequency-tile, column-part) work item on one wavefront.  VOL:
-// the projector fragments are re-read at every use (fewer live registers next
-// to the running sum of G) instead of being kept in registers across the
-// frequency loop.  Column part `part` covers the column tiles
-// [part CT, (part + 1) CT) of sum_n G; part 0 also writes the G_loc partials.
+// Inversion stage.  One matrix per wavefront with four elements per lane
+// would leave each Gauss-Jordan step a serial chain of LDS round trip,
+// reciprocal and a few FMAs.  Instead lane 16 g + i holds row i of matrix g
+// in registers, the pivot row of step K is broadcast inside each 16-lane row
+// by DPP (row_newbcast:K), and each step is one pass of independent FMAs over
+// the row.  The update is the in-place Gauss-Jordan step with the pivot row
+// scaled through the multiplier 1 - 1/p and the pivot column and pivot set
+// directly, which avoids the cancellation of a fully uniform update (whose
+// pivot entry p - (p - 1)(p + 1)/p loses about |p|^2 ulps).
+
+struct LRShared {
+  double2 buf[4][16 * 17];  // one 16x16 tile per frequency of the group (rows padded to 17)
+};
+
+// Value of lane K of this lane's 16-lane row.
+template <int K>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + K, 0xf, 0xf, false);
+}
+
+// Gauss-Jordan steps K .. nc-1 on the row held by this lane (row i of its matrix).
+template <int K>
+__device__ __forceinline__ void rsweep(double (&rr)[16], double (&ri)[16], int i, int nc, int& bad) {
+  if constexpr (K < 16) {
+    if (K >= nc) return;
+    const double2 p = make_double2(row_bcast<K>(rr[K]), row_bcast<K>(ri[K]));
+    bad |= (p.x == 0.0 && p.y == 0.0);
+    const double2 ip = crecip(p);
+    const double2 l = cmul(make_double2(rr[K], ri[K]), ip);
+    const bool piv = i == K;
+    const double lr = piv ? 1.0 - ip.x : l.x;
+    const double li = piv ? -ip.y : l.y;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (j == K) continue;
+      const double br = row_bcast<K>(rr[j]), bi = row_bcast<K>(ri[j]);
+      rr[j] = __builtin_fma(-lr, br, __builtin_fma(li, bi, rr[j]));
+      ri[j] = __builtin_fma(-lr, bi, __builtin_fma(-li, br, ri[j]));
+    }
+    rr[K] = piv ? ip.x : -l.x;
+    ri[K] = piv ? ip.y : -l.y;
+    rsweep<K + 1>(rr, ri, i, nc, bad);
+  }
+}
+
 template <int NBP, int KIND, bool VOL, int PART>
 __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int wtile, LRShared& sh, int lane) {
   constexpr int T = NBP / 16;
   constexpr int CT = lr_col_tiles<NBP, KIND>();
   constexpr int b0 = PART * CT;
-  constexpr int part = PART;
   const int q = lane >> 4, c16 = lane & 15;
+  const int g = q, ri_ = c16;  // row-layout coordinates: matrix g, row ri_
   const int n0 = wtile * a.wt;
   const int n1 = min(n0 + a.wt, a.nw);
   const int kk0 = ktile * a.kt;
   const int kk1 = min(kk0 + a.kt, a.nklist);
   const double mu = a.mu_ptr ? *a.mu_ptr : a.mu;
   const int nc = a.nc;
-  const int kc = (nc + 3) >> 2;  // orbital chunks of 4 that hold any correlated orbital
+  const int kc = (nc + 3) >> 2;
   const double beta = a.beta;
   const bool want_s = (KIND == KIND_DENSITY) && (a.mode & MODE_S);
-  const bool want_x = (KIND == KIND_DENSITY) && (a.mode & MODE_GLOC) && part == 0;
+  const bool want_x = (KIND == KIND_DENSITY) && (a.mode & MODE_GLOC) && PART == 0;
   const bool hasdiag = c16 >= q && ((c16 - q) & 3) == 0;
   const int idg = (c16 - q) >> 2;
   int bad = 0, nonfinite = 0;
@@ -149,7 +193,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
     const double* eps = a.eps + ob;
     const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
     const double wk = a.wk[k];
-    Proj<NBP> pr;  // pa: S[q + 4 j][16 b + c16],  pt: S[c16][16 t + 4 i + q]
+    Proj<NBP> pr;
     if constexpr (!VOL) {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
@@ -168,7 +212,6 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
           pr.pt_i[t][i] = v.y;
         }
     }
-    // band energies at this lane's rows (ea) and column (eb)
     double ea[T][4], eb[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
@@ -180,7 +223,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
         ea[t][i] = r2 < nb ? eps[r2] : 0.0;
       }
     }
-    v4d sre[T][CT], sim[T][CT];  // running sum of G, column tiles b0 .. b0 + CT
+    v4d sre[T][CT], sim[T][CT];
     if (want_s) {
 #pragma unroll
       for (int t = 0; t < T; ++t)
@@ -189,173 +232,225 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
     }
     double trg = 0.0, trg2 = 0.0;
 
-    for (int n = n0; n < n1; ++n) {
-      const double wn = (double)(2 * n + 1) * M_PI / beta;
-      double2 dcol[T];  // d at band 16 t + c16 (zero for padding)
+    for (int n = n0; n < n1; n += 4) {
+      // 1. X of the four frequencies n .. n+3 (repeating the last one past n1)
+      //    into LDS, in the output layout of the matrix core
 #pragma unroll
-      for (int t = 0; t < T; ++t) dcol[t] = 16 * t + c16 < nb ? inv_z_minus(mu, wn, eb[t]) : make_double2(0.0, 0.0);
-      // X = S D S^dag (and X2, X3 for the traces), contracted over the bands
-      v4d xr = {0.0, 0.0, 0.0, 0.0}, xi = xr, x2r = xr, x2i = xr, x3r = xr, x3i = xr;
+      for (int f = 0; f < 4; ++f) {
+        const int nf = min(n + f, n1 - 1);
+        const double wn = (double)(2 * nf + 1) * M_PI / beta;
+        v4d xr = {0.0, 0.0, 0.0, 0.0}, xi = xr;
 #pragma unroll
-      for (int t = 0; t < T; ++t)
+        for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          if (16 * t + 4 * i >= nb) break;  // chunks of padding bands only (uniform)
-          double2 s;
-          if constexpr (VOL)
-            s = lr_proj<true>(P, c16, 16 * t + 4 * i + q, nc, nb);
-          else
-            s = make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
-          const bool valid = 16 * t + 4 * i + q < nb;
-          double2 dd = valid ? inv_z_minus(mu, wn, ea[t][i]) : make_double2(0.0, 0.0);
-          double2 a1 = cmul(s, dd);
-          cmma_cb(xr, xi, a1.x, a1.y, s.x, s.y);
-          if constexpr (KIND == KIND_TRACE) {
-            double2 a2 = cmul(a1, dd);
-            cmma_cb(x2r, x2i, a2.x, a2.y, s.x, s.y);
-            double2 a3 = cmul(a2, dd);
-            cmma_cb(x3r, x3i, a3.x, a3.y, s.x, s.y);
+          for (int i = 0; i < 4; ++i) {
+            if (16 * t + 4 * i >= nb) break;
+            double2 s;
+            if constexpr (VOL)
+              s = lr_proj<true>(P, c16, 16 * t + 4 * i + q, nc, nb);
+            else
+              s = make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
+            const bool valid = 16 * t + 4 * i + q < nb;
+            double2 dd = valid ? inv_z_minus(mu, wn, ea[t][i]) : make_double2(0.0, 0.0);
+            double2 a1 = cmul(s, dd);
+            cmma_cb(xr, xi, a1.x, a1.y, s.x, s.y);
+          }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sh.buf[f][(q + 4 * i) * 17 + c16] = make_double2(xr[i], xi[i]);
+      }
+      wave_sync();
+      // 2. row layout: invert X, subtract Sigma', invert K -> Gl, back to LDS
+      {
+        double rr[16], rim[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          double2 v = sh.buf[g][ri_ * 17 + j];
+          rr[j] = v.x;
+          rim[j] = v.y;
+        }
+        rsweep<0>(rr, rim, ri_, nc, bad);
+        const int ng = min(n + g, n1 - 1);
+        const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)ng * nc * nc;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          if (ri_ < nc && j < nc) {
+            double2 v = sg[ri_ * nc + j];
+            if (j == ri_) v.x -= a.e_dc[j];
+            rr[j] -= v.x;
+            rim[j] -= v.y;
           }
         }
-      // Sigma' in both orientations: sa = Sigma'[c16][q + 4 j], sb-regs = Sigma'[q + 4 i][c16]
-      const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)n * nc * nc;
-      double sa_r[4], sa_i[4];
-      v4d sbr, sbi;
+        rsweep<0>(rr, rim, ri_, nc, bad);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int be = q + 4 * j;
-        bool in = c16 < nc && be < nc;
-        double2 v = in ? sg[c16 * nc + be] : make_double2(0.0, 0.0);
-        double2 u = in ? sg[be * nc + c16] : make_double2(0.0, 0.0);
-        if (c16 == be && in) {
-          v.x -= a.e_dc[c16];
-          u.x -= a.e_dc[c16];
+        for (int j = 0; j < 16; ++j) sh.buf[g][ri_ * 17 + j] = make_double2(rr[j], rim[j]);
+      }
+      wave_sync();
+      // 3. per frequency: R, then the running sum / G_loc partial or the traces
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const int nf = n + f;
+        if (nf >= n1) break;
+        const double wn = (double)(2 * nf + 1) * M_PI / beta;
+        double2 dcol[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) dcol[t] = 16 * t + c16 < nb ? inv_z_minus(mu, wn, eb[t]) : make_double2(0.0, 0.0);
+        v4d glr, gli;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          double2 v = sh.buf[f][(q + 4 * i) * 17 + c16];
+          glr[i] = v.x;
+          gli[i] = v.y;
         }
-        sa_r[j] = v.x;
-        sa_i[j] = v.y;
-        sbr[j] = u.x;
-        sbi[j] = u.y;
-      }
-      // Xi = X^-1, Gl = (Xi - Sigma')^-1 = S G S^dag (the padding block stays zero)
-      Mat<16> m;
-      m.re[0][0] = xr;
-      m.im[0][0] = xi;
-      gauss_jordan<16, 1>(m, sh.gj, q, c16, nc, bad);
-      const v4d xir = m.re[0][0], xii = m.im[0][0];
-      m.re[0][0] = xir - sbr;
-      m.im[0][0] = xii - sbi;
-      gauss_jordan<16, 1>(m, sh.gj, q, c16, nc, bad);
-      const v4d glr = m.re[0][0], gli = m.im[0][0];
-      // V = Gl^T Sigma'^T, R^T = Xi^T V
-      v4d vr = {0.0, 0.0, 0.0, 0.0}, vi = vr, rtr = vr, rti = vr;
+        const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)nf * nc * nc;
+        double sa_r[4], sa_i[4];
+        v4d sbr, sbi;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (j >= kc) break;
-        cmma(vr, vi, glr[j], gli[j], sa_r[j], sa_i[j]);
-      }
+        for (int j = 0; j < 4; ++j) {
+          int be = q + 4 * j;
+          bool in = c16 < nc && be < nc;
+          double2 v = in ? sg[c16 * nc + be] : make_double2(0.0, 0.0);
+          double2 u = in ? sg[be * nc + c16] : make_double2(0.0, 0.0);
+          if (c16 == be && in) {
+            v.x -= a.e_dc[c16];
+            u.x -= a.e_dc[c16];
+          }
+          sa_r[j] = v.x;
+          sa_i[j] = v.y;
+          sbr[j] = u.x;
+          sbi[j] = u.y;
+        }
+        // V = Gl^T Sigma'^T, R^T = Sigma'^T + Sigma'^T V
+        v4d vr = {0.0, 0.0, 0.0, 0.0}, vi = vr, rtr, rti;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (j >= kc) break;
-        cmma(rtr, rti, xir[j], xii[j], vr[j], vi[j]);
-      }
+        for (int j = 0; j < 4; ++j) {
+          if (j >= kc) break;
+          cmma(vr, vi, glr[j], gli[j], sa_r[j], sa_i[j]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          rtr[i] = sa_r[i];
+          rti[i] = sa_i[i];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (j >= kc) break;
+          cmma(rtr, rti, sbr[j], sbi[j], vr[j], vi[j]);
+        }
 
-      if constexpr (KIND == KIND_DENSITY) {
-        double chk = 0.0;
+        if constexpr (KIND == KIND_DENSITY) {
+          double chk = 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
-        if (!__builtin_isfinite(chk)) nonfinite = 1;
-        if (want_s) {
+          for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
+          if (!__builtin_isfinite(chk)) nonfinite = 1;
+          if (want_s) {
 #pragma unroll
-          for (int c = 0; c < CT; ++c) {
-            const int b = b0 + c;
-            if (16 * b >= nb) break;  // tiles of padding bands only (uniform)
-            // Q_b = (R S)_b scaled by d on its columns
-            v4d qr = {0.0, 0.0, 0.0, 0.0}, qi = qr;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              double2 s;
-              if constexpr (VOL)
-                s = lr_proj<true>(P, q + 4 * j, 16 * b + c16, nc, nb);
-              else
-                s = make_double2(pr.pa_r[j][b], pr.pa_i[j][b]);
-              cmma(qr, qi, rtr[j], rti[j], s.x, s.y);
-            }
-            const double2 db = dcol[b];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              double2 v = cmul(make_double2(qr[i], qi[i]), db);
-              qr[i] = v.x;
-              qi[i] = v.y;
-            }
-            // column block b of sum_n G: += (D S^dag)_t Q_b, and D on the diagonal tile
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-              if (16 * t >= nb) break;
-              const double2 dt = dcol[t];
+            for (int c = 0; c < CT; ++c) {
+              const int b = b0 + c;
+              if (16 * b >= nb) break;
+              v4d qr = {0.0, 0.0, 0.0, 0.0}, qi = qr;
 #pragma unroll
               for (int j = 0; j < 4; ++j) {
                 if (j >= kc) break;
                 double2 s;
                 if constexpr (VOL)
-                  s = lr_proj<true>(P, q + 4 * j, 16 * t + c16, nc, nb);
+                  s = lr_proj<true>(P, q + 4 * j, 16 * b + c16, nc, nb);
                 else
-                  s = make_double2(pr.pa_r[j][t], pr.pa_i[j][t]);
-                double2 aa = cmul(dt, make_double2(s.x, -s.y));
-                cmma(sre[t][c], sim[t][c], aa.x, aa.y, qr[j], qi[j]);
+                  s = make_double2(pr.pa_r[j][b], pr.pa_i[j][b]);
+                cmma(qr, qi, rtr[j], rti[j], s.x, s.y);
               }
-              if (t == b) {
+              const double2 db = dcol[b];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                  if (hasdiag && idg == i) {
-                    sre[t][c][i] += db.x;
-                    sim[t][c][i] += db.y;
-                  }
+              for (int i = 0; i < 4; ++i) {
+                double2 v = cmul(make_double2(qr[i], qi[i]), db);
+                qr[i] = v.x;
+                qi[i] = v.y;
+              }
+#pragma unroll
+              for (int t = 0; t < T; ++t) {
+                if (16 * t >= nb) break;
+                const double2 dt = dcol[t];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  if (j >= kc) break;
+                  double2 s;
+                  if constexpr (VOL)
+                    s = lr_proj<true>(P, q + 4 * j, 16 * t + c16, nc, nb);
+                  else
+                    s = make_double2(pr.pa_r[j][t], pr.pa_i[j][t]);
+                  double2 aa = cmul(dt, make_double2(s.x, -s.y));
+                  cmma(sre[t][c], sim[t][c], aa.x, aa.y, qr[j], qi[j]);
+                }
+                if (t == b) {
+#pragma unroll
+                  for (int i = 0; i < 4; ++i)
+                    if (hasdiag && idg == i) {
+                      sre[t][c][i] += db.x;
+                      sim[t][c][i] += db.y;
+                    }
+                }
               }
             }
           }
-        }
-        if (want_x) {
-          // lane holds Gl[q + 4 i][c16]; add w_k Gl to this k tile's partial
-          double2* xp = reinterpret_cast<double2*>(a.xpart) + ((int64_t)(a.ktile_base + ktile) * a.nw + n) * 256;
+          if (want_x) {
+            double2* xp = reinterpret_cast<double2*>(a.xpart) + ((int64_t)(a.ktile_base + ktile) * a.nw + nf) * 256;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (q + 4 * i < nc && c16 < nc) {
-              double2 v = make_double2(wk * glr[i], wk * gli[i]);
-              if (kk != kk0) {
-                double2 o = xp[i * 64 + lane];
-                v.x += o.x;
-                v.y += o.y;
+            for (int i = 0; i < 4; ++i) {
+              if (q + 4 * i < nc && c16 < nc) {
+                double2 v = make_double2(wk * glr[i], wk * gli[i]);
+                if (kk != kk0) {
+                  double2 o = xp[i * 64 + lane];
+                  v.x += o.x;
+                  v.y += o.y;
+                }
+                xp[i * 64 + lane] = v;
               }
-              xp[i * 64 + lane] = v;
             }
           }
-        }
-      } else {
-        // tr(R X_j) = sum over lanes of R^T-regs .* X_j-regs; tr(E^2) with E = R X2
-        v4d er = {0.0, 0.0, 0.0, 0.0}, ei = er, etr, eti;
+        } else {
+          // X2 = S D^2 S^dag, X3 = S D^3 S^dag of this frequency
+          v4d x2r = {0.0, 0.0, 0.0, 0.0}, x2i = x2r, x3r = x2r, x3i = x2r;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (j >= kc) break;
-          cmma(er, ei, rtr[j], rti[j], x2r[j], x2i[j]);
-        }
-        tile_transpose(er, ei, etr, eti, sh.tp, q, c16);
-        double t2 = re_dot4(rtr, rti, x2r, x2i);
-        double t3 = re_dot4(rtr, rti, x3r, x3i);
-        double ee = re_dot4(er, ei, etr, eti);
-        // sum over bands of Re d and Re d^2: band 16 t + c16, counted on the q = 0 lanes
-        double sd = 0.0, sd2 = 0.0;
-        if (q == 0) {
+          for (int t = 0; t < T; ++t)
 #pragma unroll
-          for (int t = 0; t < T; ++t) {
-            sd += dcol[t].x;
-            sd2 += dcol[t].x * dcol[t].x - dcol[t].y * dcol[t].y;
+            for (int i = 0; i < 4; ++i) {
+              if (16 * t + 4 * i >= nb) break;
+              double2 s;
+              if constexpr (VOL)
+                s = lr_proj<true>(P, c16, 16 * t + 4 * i + q, nc, nb);
+              else
+                s = make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
+              const bool valid = 16 * t + 4 * i + q < nb;
+              double2 dd = valid ? inv_z_minus(mu, wn, ea[t][i]) : make_double2(0.0, 0.0);
+              double2 a2 = cmul(cmul(s, dd), dd);
+              cmma_cb(x2r, x2i, a2.x, a2.y, s.x, s.y);
+              double2 a3 = cmul(a2, dd);
+              cmma_cb(x3r, x3i, a3.x, a3.y, s.x, s.y);
+            }
+          v4d er = {0.0, 0.0, 0.0, 0.0}, ei = er, etr, eti;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (j >= kc) break;
+            cmma(er, ei, rtr[j], rti[j], x2r[j], x2i[j]);
           }
+          wave_sync();
+          tile_transpose(er, ei, etr, eti, sh.buf[f], q, c16);
+          double t2 = re_dot4(rtr, rti, x2r, x2i);
+          double t3 = re_dot4(rtr, rti, x3r, x3i);
+          double ee = re_dot4(er, ei, etr, eti);
+          double sd = 0.0, sd2 = 0.0;
+          if (q == 0) {
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+              sd += dcol[t].x;
+              sd2 += dcol[t].x * dcol[t].x - dcol[t].y * dcol[t].y;
+            }
+          }
+          trg += sd + t2;
+          trg2 += sd2 + 2.0 * t3 + ee;
         }
-        trg += sd + t2;
-        trg2 += sd2 + 2.0 * t3 + ee;
       }
-    }  // frequencies
+      wave_sync();
+    }  // frequency groups
 
     if (want_s) {
       double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
