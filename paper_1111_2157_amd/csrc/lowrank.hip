@@ -1,9 +1,12 @@
 // Instantiation unit of the low-rank Dyson kernel (lowrank_impl.h), one
 // wavefront per work item for every padded band-window size.
 //
-// Variant id: bit 3 set (low-rank form), bit 0 = projector fragments re-read
-// at every use (VOL), bit 2 = two wavefronts per SIMD.  Each (size, kind)
-// lists the combinations that compile without register spills.
+// Variant id: bit 3 set (low-rank form); projector fragments kept in
+// registers for the whole k-point (bits 0 and 4 clear), re-read at every use
+// (bit 0) or loaded once per four-frequency group at the start of each stage
+// (bit 4); bit 1 = three-product complex arithmetic on the matrix cores;
+// bit 2 = two wavefronts per SIMD.  Each (size, kind) lists the combinations
+// that compile without register spills.
 #include "lowrank_impl.h"
 
 namespace dmft {
@@ -13,10 +16,11 @@ struct LRSet {
   template <int VAR>
   static hipError_t one(const DysonArgs& a, dim3 grid, hipStream_t s) {
     constexpr int parts = (NBP / 16) / lr_col_tiles<NBP, KIND>();
-    constexpr bool vol = (VAR & 1) != 0;
+    constexpr int rl = (VAR & 16) ? 1 : (VAR & 1) ? 2 : 0;
+    constexpr bool m3 = (VAR & 2) != 0;
     constexpr int occ = (VAR & 4) ? 2 : 1;
     grid.x *= parts;
-    hipLaunchKernelGGL((lr_kernel<NBP, KIND, vol, occ>), grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, occ>), grid, dim3(64), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t launch(int var, const DysonArgs& a, dim3 grid, hipStream_t s) {
@@ -32,14 +36,14 @@ struct LRSet {
   }
 };
 
-using LD16 = LRSet<16, KIND_DENSITY, 8, 9>;
-using LD32 = LRSet<32, KIND_DENSITY, 8, 9>;
-using LD48 = LRSet<48, KIND_DENSITY, 8, 9>;
-using LD64 = LRSet<64, KIND_DENSITY, 9>;
-using LT16 = LRSet<16, KIND_TRACE, 12, 13, 8, 9>;
-using LT32 = LRSet<32, KIND_TRACE, 12, 13, 8, 9>;
-using LT48 = LRSet<48, KIND_TRACE, 13, 8, 9>;
-using LT64 = LRSet<64, KIND_TRACE, 13, 8, 9>;
+using LD16 = LRSet<16, KIND_DENSITY, 14, 8, 10, 26, 30>;
+using LD32 = LRSet<32, KIND_DENSITY, 10, 8, 24, 26, 9, 11>;
+using LD48 = LRSet<48, KIND_DENSITY, 8, 24, 26, 9, 11>;
+using LD64 = LRSet<64, KIND_DENSITY, 24, 9, 11>;
+using LT16 = LRSet<16, KIND_TRACE, 14, 12, 13, 15, 28, 30>;
+using LT32 = LRSet<32, KIND_TRACE, 14, 12, 28, 30, 13, 15>;
+using LT48 = LRSet<48, KIND_TRACE, 15, 13, 8, 10, 24, 26>;
+using LT64 = LRSet<64, KIND_TRACE, 13, 9, 11, 8, 10, 24>;
 
 hipError_t launch_lowrank(int nbp, int var, const DysonArgs& a, dim3 grid, hipStream_t s) {
   const bool tr = (a.mode & MODE_TRACE) != 0;

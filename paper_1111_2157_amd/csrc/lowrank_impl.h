@@ -80,6 +80,60 @@ __device__ __forceinline__ void cmma_cb(v4d& dr, v4d& di, double ar, double ai, 
   di = mms(ar, bi, di);
 }
 
+// Complex 16x16 accumulator on the matrix core.  M3 = false: real and
+// imaginary parts, four real products per complex product.  M3 = true: the
+// three-product form P1 = sum ar br, P2 = sum ai bi, P3 = sum (ar + ai)(br + bi),
+// re = P1 - P2, im = P3 - P1 - P2 (a quarter fewer matrix-core products and
+// shorter dependent chains; the imaginary part is exact to rounding relative
+// to |A| |B|, which is what normwise error bounds need).
+template <bool M3>
+struct CAcc;
+
+template <>
+struct CAcc<false> {
+  v4d r, i;
+  __device__ __forceinline__ void zero() { r = i = (v4d){0.0, 0.0, 0.0, 0.0}; }
+  __device__ __forceinline__ void set(const v4d& re, const v4d& im) {
+    r = re;
+    i = im;
+  }
+  __device__ __forceinline__ void mac(double ar, double ai, double br, double bi) { cmma(r, i, ar, ai, br, bi); }
+  __device__ __forceinline__ void mac_cb(double ar, double ai, double br, double bi) { cmma_cb(r, i, ar, ai, br, bi); }
+  __device__ __forceinline__ v4d re() const { return r; }
+  __device__ __forceinline__ v4d im() const { return i; }
+  __device__ __forceinline__ void add(int reg, double x, double y) {
+    r[reg] += x;
+    i[reg] += y;
+  }
+};
+
+template <>
+struct CAcc<true> {
+  v4d p1, p2, p3;
+  __device__ __forceinline__ void zero() { p1 = p2 = p3 = (v4d){0.0, 0.0, 0.0, 0.0}; }
+  __device__ __forceinline__ void set(const v4d& re, const v4d& im) {
+    p1 = re;
+    p2 = (v4d){0.0, 0.0, 0.0, 0.0};
+    p3 = re + im;
+  }
+  __device__ __forceinline__ void mac(double ar, double ai, double br, double bi) {
+    p1 = mma(ar, br, p1);
+    p2 = mma(ai, bi, p2);
+    p3 = mma(ar + ai, br + bi, p3);
+  }
+  __device__ __forceinline__ void mac_cb(double ar, double ai, double br, double bi) {
+    p1 = mma(ar, br, p1);
+    p2 = mms(ai, bi, p2);
+    p3 = mma(ar + ai, br - bi, p3);
+  }
+  __device__ __forceinline__ v4d re() const { return p1 - p2; }
+  __device__ __forceinline__ v4d im() const { return p3 - p1 - p2; }
+  __device__ __forceinline__ void add(int reg, double x, double y) {
+    p1[reg] += x;
+    p3[reg] += x + y;
+  }
+};
+
 // 16x16 output-layout tile transposed through LDS: out register i holds in[c16][q + 4 i].
 __device__ __forceinline__ void tile_transpose(const v4d& inr, const v4d& ini, v4d& outr, v4d& outi, double2* buf,
                                                int q, int c16) {
@@ -103,12 +157,35 @@ __device__ __forceinline__ double re_dot4(const v4d& ar, const v4d& ai, const v4
   return s;
 }
 
-// Projector fragment S[al][bd] (zero outside nc x nb).  VOL re-reads it from
-// the cache hierarchy at every use instead of keeping it in registers.
-template <bool VOL>
+// Projector fragment S[al][bd] (zero outside nc x nb).
 __device__ __forceinline__ double2 lr_proj(const double2* P, int al, int bd, int nc, int nb) {
-  if constexpr (VOL) P = fresh(P);
   return (al < nc && bd < nb) ? P[al * nb + bd] : make_double2(0.0, 0.0);
+}
+
+// The two projector fragment sets of a lane: pa = S[q + 4 j][16 b + c16]
+// (B operand of R S, A operand of D S^dag) and pt = S[c16][16 t + 4 i + q]
+// (both operands of S D S^dag).
+template <int NBP>
+__device__ __forceinline__ void lr_load_pa(Proj<NBP>& pr, const double2* P, int nc, int nb, int q, int c16) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int b = 0; b < NBP / 16; ++b) {
+      double2 v = lr_proj(P, q + 4 * j, 16 * b + c16, nc, nb);
+      pr.pa_r[j][b] = v.x;
+      pr.pa_i[j][b] = v.y;
+    }
+}
+template <int NBP>
+__device__ __forceinline__ void lr_load_pt(Proj<NBP>& pr, const double2* P, int nc, int nb, int q, int c16) {
+#pragma unroll
+  for (int t = 0; t < NBP / 16; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double2 v = lr_proj(P, c16, 16 * t + 4 * i + q, nc, nb);
+      pr.pt_r[t][i] = v.x;
+      pr.pt_i[t][i] = v.y;
+    }
 }
 
 // Column tiles of sum_n G one work item keeps: all of them, except for 64-band
@@ -165,7 +242,7 @@ __device__ __forceinline__ void rsweep(double (&rr)[16], double (&ri)[16], int i
   }
 }
 
-template <int NBP, int KIND, bool VOL, int PART>
+template <int NBP, int KIND, int RL, bool M3, int PART>
 __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int wtile, LRShared& sh, int lane) {
   constexpr int T = NBP / 16;
   constexpr int CT = lr_col_tiles<NBP, KIND>();
@@ -193,24 +270,14 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
     const double* eps = a.eps + ob;
     const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
     const double wk = a.wk[k];
+    // projector fragments: RL = 0 kept in registers for the whole k; RL = 1
+    // loaded per group of four frequencies at the start of the stage that
+    // uses them, so that they do not occupy registers in the other stages;
+    // RL = 2 re-read at every use (fewest live registers)
     Proj<NBP> pr;
-    if constexpr (!VOL) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int b = 0; b < T; ++b) {
-          double2 v = lr_proj<false>(P, q + 4 * j, 16 * b + c16, nc, nb);
-          pr.pa_r[j][b] = v.x;
-          pr.pa_i[j][b] = v.y;
-        }
-#pragma unroll
-      for (int t = 0; t < T; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          double2 v = lr_proj<false>(P, c16, 16 * t + 4 * i + q, nc, nb);
-          pr.pt_r[t][i] = v.x;
-          pr.pt_i[t][i] = v.y;
-        }
+    if constexpr (RL == 0) {
+      lr_load_pa<NBP>(pr, P, nc, nb, q, c16);
+      lr_load_pt<NBP>(pr, P, nc, nb, q, c16);
     }
     double ea[T][4], eb[T];
 #pragma unroll
@@ -223,38 +290,40 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
         ea[t][i] = r2 < nb ? eps[r2] : 0.0;
       }
     }
-    v4d sre[T][CT], sim[T][CT];
+    // running sum of G, column tiles b0 .. b0 + CT; the three-product form
+    // needs three accumulators per tile, so it is used here only up to four tiles
+    CAcc<M3 && T * CT <= 4> sacc[T][CT];
     if (want_s) {
 #pragma unroll
       for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) sre[t][c] = sim[t][c] = (v4d){0.0, 0.0, 0.0, 0.0};
+        for (int c = 0; c < CT; ++c) sacc[t][c].zero();
     }
     double trg = 0.0, trg2 = 0.0;
 
     for (int n = n0; n < n1; n += 4) {
       // 1. X of the four frequencies n .. n+3 (repeating the last one past n1)
       //    into LDS, in the output layout of the matrix core
+      if constexpr (RL == 1) lr_load_pt<NBP>(pr, fresh(P), nc, nb, q, c16);
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         const int nf = min(n + f, n1 - 1);
         const double wn = (double)(2 * nf + 1) * M_PI / beta;
-        v4d xr = {0.0, 0.0, 0.0, 0.0}, xi = xr;
+        CAcc<M3> x;
+        x.zero();
 #pragma unroll
         for (int t = 0; t < T; ++t)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             if (16 * t + 4 * i >= nb) break;
-            double2 s;
-            if constexpr (VOL)
-              s = lr_proj<true>(P, c16, 16 * t + 4 * i + q, nc, nb);
-            else
-              s = make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
+            const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
+                                      : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
             const bool valid = 16 * t + 4 * i + q < nb;
             double2 dd = valid ? inv_z_minus(mu, wn, ea[t][i]) : make_double2(0.0, 0.0);
             double2 a1 = cmul(s, dd);
-            cmma_cb(xr, xi, a1.x, a1.y, s.x, s.y);
+            x.mac_cb(a1.x, a1.y, s.x, s.y);
           }
+        const v4d xr = x.re(), xi = x.im();
 #pragma unroll
         for (int i = 0; i < 4; ++i) sh.buf[f][(q + 4 * i) * 17 + c16] = make_double2(xr[i], xi[i]);
       }
@@ -286,6 +355,12 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
       }
       wave_sync();
       // 3. per frequency: R, then the running sum / G_loc partial or the traces
+      if constexpr (RL == 1) {
+        if constexpr (KIND == KIND_DENSITY)
+          lr_load_pa<NBP>(pr, fresh(P), nc, nb, q, c16);
+        else
+          lr_load_pt<NBP>(pr, fresh(P), nc, nb, q, c16);
+      }
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         const int nf = n + f;
@@ -320,22 +395,22 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
           sbi[j] = u.y;
         }
         // V = Gl^T Sigma'^T, R^T = Sigma'^T + Sigma'^T V
-        v4d vr = {0.0, 0.0, 0.0, 0.0}, vi = vr, rtr, rti;
+        CAcc<M3> va;
+        va.zero();
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (j >= kc) break;
-          cmma(vr, vi, glr[j], gli[j], sa_r[j], sa_i[j]);
+          va.mac(glr[j], gli[j], sa_r[j], sa_i[j]);
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          rtr[i] = sa_r[i];
-          rti[i] = sa_i[i];
-        }
+        const v4d vr = va.re(), vi = va.im();
+        CAcc<M3> ra;
+        ra.set((v4d){sa_r[0], sa_r[1], sa_r[2], sa_r[3]}, (v4d){sa_i[0], sa_i[1], sa_i[2], sa_i[3]});
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (j >= kc) break;
-          cmma(rtr, rti, sbr[j], sbi[j], vr[j], vi[j]);
+          ra.mac(sbr[j], sbi[j], vr[j], vi[j]);
         }
+        const v4d rtr = ra.re(), rti = ra.im();
 
         if constexpr (KIND == KIND_DENSITY) {
           double chk = 0.0;
@@ -347,17 +422,16 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
             for (int c = 0; c < CT; ++c) {
               const int b = b0 + c;
               if (16 * b >= nb) break;
-              v4d qr = {0.0, 0.0, 0.0, 0.0}, qi = qr;
+              CAcc<M3> qa;
+              qa.zero();
 #pragma unroll
               for (int j = 0; j < 4; ++j) {
                 if (j >= kc) break;
-                double2 s;
-                if constexpr (VOL)
-                  s = lr_proj<true>(P, q + 4 * j, 16 * b + c16, nc, nb);
-                else
-                  s = make_double2(pr.pa_r[j][b], pr.pa_i[j][b]);
-                cmma(qr, qi, rtr[j], rti[j], s.x, s.y);
+                const double2 s = RL == 2 ? lr_proj(fresh(P), q + 4 * j, 16 * b + c16, nc, nb)
+                                          : make_double2(pr.pa_r[j][b], pr.pa_i[j][b]);
+                qa.mac(rtr[j], rti[j], s.x, s.y);
               }
+              v4d qr = qa.re(), qi = qa.im();
               const double2 db = dcol[b];
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
@@ -372,21 +446,15 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                   if (j >= kc) break;
-                  double2 s;
-                  if constexpr (VOL)
-                    s = lr_proj<true>(P, q + 4 * j, 16 * t + c16, nc, nb);
-                  else
-                    s = make_double2(pr.pa_r[j][t], pr.pa_i[j][t]);
+                  const double2 s = RL == 2 ? lr_proj(fresh(P), q + 4 * j, 16 * t + c16, nc, nb)
+                                            : make_double2(pr.pa_r[j][t], pr.pa_i[j][t]);
                   double2 aa = cmul(dt, make_double2(s.x, -s.y));
-                  cmma(sre[t][c], sim[t][c], aa.x, aa.y, qr[j], qi[j]);
+                  sacc[t][c].mac(aa.x, aa.y, qr[j], qi[j]);
                 }
                 if (t == b) {
 #pragma unroll
                   for (int i = 0; i < 4; ++i)
-                    if (hasdiag && idg == i) {
-                      sre[t][c][i] += db.x;
-                      sim[t][c][i] += db.y;
-                    }
+                    if (hasdiag && idg == i) sacc[t][c].add(i, db.x, db.y);
                 }
               }
             }
@@ -408,30 +476,33 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
           }
         } else {
           // X2 = S D^2 S^dag, X3 = S D^3 S^dag of this frequency
-          v4d x2r = {0.0, 0.0, 0.0, 0.0}, x2i = x2r, x3r = x2r, x3i = x2r;
+          CAcc<M3> x2a, x3a;
+          x2a.zero();
+          x3a.zero();
 #pragma unroll
           for (int t = 0; t < T; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               if (16 * t + 4 * i >= nb) break;
-              double2 s;
-              if constexpr (VOL)
-                s = lr_proj<true>(P, c16, 16 * t + 4 * i + q, nc, nb);
-              else
-                s = make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
+              const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
+                                      : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
               const bool valid = 16 * t + 4 * i + q < nb;
               double2 dd = valid ? inv_z_minus(mu, wn, ea[t][i]) : make_double2(0.0, 0.0);
               double2 a2 = cmul(cmul(s, dd), dd);
-              cmma_cb(x2r, x2i, a2.x, a2.y, s.x, s.y);
+              x2a.mac_cb(a2.x, a2.y, s.x, s.y);
               double2 a3 = cmul(a2, dd);
-              cmma_cb(x3r, x3i, a3.x, a3.y, s.x, s.y);
+              x3a.mac_cb(a3.x, a3.y, s.x, s.y);
             }
-          v4d er = {0.0, 0.0, 0.0, 0.0}, ei = er, etr, eti;
+          const v4d x2r = x2a.re(), x2i = x2a.im(), x3r = x3a.re(), x3i = x3a.im();
+          CAcc<M3> ea_;
+          ea_.zero();
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             if (j >= kc) break;
-            cmma(er, ei, rtr[j], rti[j], x2r[j], x2i[j]);
+            ea_.mac(rtr[j], rti[j], x2r[j], x2i[j]);
           }
+          const v4d er = ea_.re(), ei = ea_.im();
+          v4d etr, eti;
           wave_sync();
           tile_transpose(er, ei, etr, eti, sh.buf[f], q, c16);
           double t2 = re_dot4(rtr, rti, x2r, x2i);
@@ -461,7 +532,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             int e = (t * T + b0 + c) * 4 + i;
-            sp[e * 64 + lane] = make_double2(sre[t][c][i], sim[t][c][i]);
+            sp[e * 64 + lane] = make_double2(sacc[t][c].re()[i], sacc[t][c].im()[i]);
           }
     }
     if constexpr (KIND == KIND_TRACE) {
@@ -481,25 +552,25 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   if (nonfinite) atomicOr(a.err, ERR_NONFINITE);
 }
 
-template <int NBP, int KIND, bool VOL>
+template <int NBP, int KIND, int RL, bool M3>
 __device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile, int part, LRShared& sh, int lane) {
   constexpr int NP = (NBP / 16) / lr_col_tiles<NBP, KIND>();
   if constexpr (NP > 1) {
     if (part) {
-      lr_tile_part<NBP, KIND, VOL, 1>(a, ktile, wtile, sh, lane);
+      lr_tile_part<NBP, KIND, RL, M3, 1>(a, ktile, wtile, sh, lane);
       return;
     }
   }
-  lr_tile_part<NBP, KIND, VOL, 0>(a, ktile, wtile, sh, lane);
+  lr_tile_part<NBP, KIND, RL, M3, 0>(a, ktile, wtile, sh, lane);
 }
 
 // Grid: (k tiles x frequency tiles) x column parts, the column part fastest.
-template <int NBP, int KIND, bool VOL, int OCC>
+template <int NBP, int KIND, int RL, bool M3, int OCC>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) lr_kernel(DysonArgs a) {
   __shared__ LRShared sh;
   constexpr int NP = (NBP / 16) / lr_col_tiles<NBP, KIND>();
   const int item = blockIdx.x / NP, part = blockIdx.x % NP;
-  lr_tile<NBP, KIND, VOL>(a, item / a.n_wtiles, item % a.n_wtiles, part, sh, threadIdx.x);
+  lr_tile<NBP, KIND, RL, M3>(a, item / a.n_wtiles, item % a.n_wtiles, part, sh, threadIdx.x);
 }
 
 }  // namespace dmft
