@@ -95,10 +95,10 @@ __global__ void __launch_bounds__(64) batched_lr_kernel(const BatchItem* items, 
     // nbp: padded size in the low byte, column part of a 64-band item in bit 8
     const int part = b.nbp >> 8;
     switch (b.nbp & 255) {
-      case 64: lr_tile<64, KIND_DENSITY, 2, false>(a, b.ktile, b.wtile, part, sh, lane); break;
-      case 48: lr_tile<48, KIND_DENSITY, 2, false>(a, b.ktile, b.wtile, 0, sh, lane); break;
-      case 32: lr_tile<32, KIND_DENSITY, 0, false>(a, b.ktile, b.wtile, 0, sh, lane); break;
-      default: lr_tile<16, KIND_DENSITY, 0, false>(a, b.ktile, b.wtile, 0, sh, lane); break;
+      case 64: lr_tile<64, KIND_DENSITY, 2, false, 16>(a, b.ktile, b.wtile, part, sh, lane); break;
+      case 48: lr_tile<48, KIND_DENSITY, 2, false, 16>(a, b.ktile, b.wtile, 0, sh, lane); break;
+      case 32: lr_tile<32, KIND_DENSITY, 0, false, 16>(a, b.ktile, b.wtile, 0, sh, lane); break;
+      default: lr_tile<16, KIND_DENSITY, 0, false, 16>(a, b.ktile, b.wtile, 0, sh, lane); break;
     }
   }
 }

@@ -217,10 +217,11 @@ __device__ __forceinline__ double row_bcast(double v) {
   return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + K, 0xf, 0xf, false);
 }
 
-// Gauss-Jordan steps K .. nc-1 on the row held by this lane (row i of its matrix).
-template <int K>
-__device__ __forceinline__ void rsweep(double (&rr)[16], double (&ri)[16], int i, int nc, int& bad) {
-  if constexpr (K < 16) {
+// Gauss-Jordan steps K .. nc-1 on the row held by this lane (row i of its
+// matrix); NC columns are kept (nc <= NC; the others are zero throughout).
+template <int K, int NC>
+__device__ __forceinline__ void rsweep(double (&rr)[NC], double (&ri)[NC], int i, int nc, int& bad) {
+  if constexpr (K < NC) {
     if (K >= nc) return;
     const double2 p = make_double2(row_bcast<K>(rr[K]), row_bcast<K>(ri[K]));
     bad |= (p.x == 0.0 && p.y == 0.0);
@@ -230,7 +231,7 @@ __device__ __forceinline__ void rsweep(double (&rr)[16], double (&ri)[16], int i
     const double lr = piv ? 1.0 - ip.x : l.x;
     const double li = piv ? -ip.y : l.y;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < NC; ++j) {
       if (j == K) continue;
       const double br = row_bcast<K>(rr[j]), bi = row_bcast<K>(ri[j]);
       rr[j] = __builtin_fma(-lr, br, __builtin_fma(li, bi, rr[j]));
@@ -238,11 +239,11 @@ __device__ __forceinline__ void rsweep(double (&rr)[16], double (&ri)[16], int i
     }
     rr[K] = piv ? ip.x : -l.x;
     ri[K] = piv ? ip.y : -l.y;
-    rsweep<K + 1>(rr, ri, i, nc, bad);
+    rsweep<K + 1, NC>(rr, ri, i, nc, bad);
   }
 }
 
-template <int NBP, int KIND, int RL, bool M3, int PART>
+template <int NBP, int KIND, int RL, bool M3, int NC, int PART>
 __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int wtile, LRShared& sh, int lane) {
   constexpr int T = NBP / 16;
   constexpr int CT = lr_col_tiles<NBP, KIND>();
@@ -330,18 +331,18 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
       wave_sync();
       // 2. row layout: invert X, subtract Sigma', invert K -> Gl, back to LDS
       {
-        double rr[16], rim[16];
+        double rr[NC], rim[NC];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
+        for (int j = 0; j < NC; ++j) {
           double2 v = sh.buf[g][ri_ * 17 + j];
           rr[j] = v.x;
           rim[j] = v.y;
         }
-        rsweep<0>(rr, rim, ri_, nc, bad);
+        rsweep<0, NC>(rr, rim, ri_, nc, bad);
         const int ng = min(n + g, n1 - 1);
         const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)ng * nc * nc;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
+        for (int j = 0; j < NC; ++j) {
           if (ri_ < nc && j < nc) {
             double2 v = sg[ri_ * nc + j];
             if (j == ri_) v.x -= a.e_dc[j];
@@ -349,9 +350,9 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
             rim[j] -= v.y;
           }
         }
-        rsweep<0>(rr, rim, ri_, nc, bad);
+        rsweep<0, NC>(rr, rim, ri_, nc, bad);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) sh.buf[g][ri_ * 17 + j] = make_double2(rr[j], rim[j]);
+        for (int j = 0; j < NC; ++j) sh.buf[g][ri_ * 17 + j] = make_double2(rr[j], rim[j]);
       }
       wave_sync();
       // 3. per frequency: R, then the running sum / G_loc partial or the traces
@@ -552,25 +553,63 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   if (nonfinite) atomicOr(a.err, ERR_NONFINITE);
 }
 
-template <int NBP, int KIND, int RL, bool M3>
+// NC: columns kept in the row-layout inversions, nc rounded up to 4, 8, 12 or 16.
+template <int NBP, int KIND, int RL, bool M3, int NC>
 __device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile, int part, LRShared& sh, int lane) {
   constexpr int NP = (NBP / 16) / lr_col_tiles<NBP, KIND>();
   if constexpr (NP > 1) {
     if (part) {
-      lr_tile_part<NBP, KIND, RL, M3, 1>(a, ktile, wtile, sh, lane);
+      lr_tile_part<NBP, KIND, RL, M3, NC, 1>(a, ktile, wtile, sh, lane);
       return;
     }
   }
-  lr_tile_part<NBP, KIND, RL, M3, 0>(a, ktile, wtile, sh, lane);
+  lr_tile_part<NBP, KIND, RL, M3, NC, 0>(a, ktile, wtile, sh, lane);
 }
 
 // Grid: (k tiles x frequency tiles) x column parts, the column part fastest.
-template <int NBP, int KIND, int RL, bool M3, int OCC>
+template <int NBP, int KIND, int RL, bool M3, int NC, int OCC>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) lr_kernel(DysonArgs a) {
   __shared__ LRShared sh;
   constexpr int NP = (NBP / 16) / lr_col_tiles<NBP, KIND>();
   const int item = blockIdx.x / NP, part = blockIdx.x % NP;
-  lr_tile<NBP, KIND, RL, M3>(a, item / a.n_wtiles, item % a.n_wtiles, part, sh, threadIdx.x);
+  lr_tile<NBP, KIND, RL, M3, NC>(a, item / a.n_wtiles, item % a.n_wtiles, part, sh, threadIdx.x);
 }
+
+// Variant id of the low-rank kernel: bit 3 set; projector fragments kept in
+// registers for the whole k-point (bits 0 and 4 clear), re-read at every use
+// (bit 0) or loaded once per four-frequency group at the start of each stage
+// (bit 4); bit 1 = three-product complex arithmetic on the matrix cores;
+// bit 2 = two wavefronts per SIMD.  An LRSet lists the variants one
+// instantiation unit compiles for one size and kind.
+template <int NBP, int KIND, int... VARS>
+struct LRSet {
+  template <int VAR>
+  static hipError_t one(const DysonArgs& a, dim3 grid, hipStream_t s) {
+    constexpr int parts = (NBP / 16) / lr_col_tiles<NBP, KIND>();
+    constexpr int rl = (VAR & 16) ? 1 : (VAR & 1) ? 2 : 0;
+    constexpr bool m3 = (VAR & 2) != 0;
+    constexpr int occ = (VAR & 4) ? 2 : 1;
+    grid.x *= parts;
+    // columns of the row-layout inversions: nc rounded up to 8, 12 or 16
+    if (a.nc <= 8)
+      hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 8, occ>), grid, dim3(64), 0, s, a);
+    else if (a.nc <= 12)
+      hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 12, occ>), grid, dim3(64), 0, s, a);
+    else
+      hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 16, occ>), grid, dim3(64), 0, s, a);
+    return hipGetLastError();
+  }
+  static hipError_t launch(int var, const DysonArgs& a, dim3 grid, hipStream_t s) {
+    hipError_t r = hipErrorInvalidValue;
+    bool hit = ((var == VARS ? (r = one<VARS>(a, grid, s), true) : false) || ...);
+    (void)hit;
+    return r;
+  }
+  static int list(int* out, int max) {
+    int n = 0;
+    ((n < max ? (out[n++] = VARS, 0) : 0), ...);
+    return n;
+  }
+};
 
 }  // namespace dmft
