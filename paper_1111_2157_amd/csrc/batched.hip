@@ -81,6 +81,22 @@ hipError_t launch_batched(const void* items, int n_big, int n_small, const Dyson
   return hipGetLastError();
 }
 
+// One low-rank work item of the batched queue, per padded size.  All paths
+// share one kernel's register allocation; these choices were the fastest
+// measured (the 48-band path with per-stage projector loads spills 20 bytes
+// per lane in this kernel and is still about 9% faster than the spill-free
+// per-use reloads).
+template <int NC>
+__device__ __forceinline__ void lr_batched_item(const DysonArgs& a, const BatchItem& b, int part, LRShared& sh,
+                                                int lane) {
+  switch (b.nbp & 255) {
+    case 64: lr_tile<64, KIND_DENSITY, 2, true, NC>(a, b.ktile, b.wtile, part, sh, lane); break;
+    case 48: lr_tile<48, KIND_DENSITY, 1, false, NC>(a, b.ktile, b.wtile, 0, sh, lane); break;
+    case 32: lr_tile<32, KIND_DENSITY, 0, true, NC>(a, b.ktile, b.wtile, 0, sh, lane); break;
+    default: lr_tile<16, KIND_DENSITY, 0, true, NC>(a, b.ktile, b.wtile, 0, sh, lane); break;
+  }
+}
+
 __global__ void __launch_bounds__(64) batched_lr_kernel(const BatchItem* items, int n_items, const DysonArgs* args,
                                                         int* counters) {
   __shared__ LRShared sh;
@@ -92,14 +108,13 @@ __global__ void __launch_bounds__(64) batched_lr_kernel(const BatchItem* items, 
     if (it >= n_items) break;
     const BatchItem b = items[it];
     const DysonArgs a = args[b.args];
-    // nbp: padded size in the low byte, column part of a 64-band item in bit 8
-    const int part = b.nbp >> 8;
-    switch (b.nbp & 255) {
-      case 64: lr_tile<64, KIND_DENSITY, 2, false, 16>(a, b.ktile, b.wtile, part, sh, lane); break;
-      case 48: lr_tile<48, KIND_DENSITY, 2, false, 16>(a, b.ktile, b.wtile, 0, sh, lane); break;
-      case 32: lr_tile<32, KIND_DENSITY, 0, false, 16>(a, b.ktile, b.wtile, 0, sh, lane); break;
-      default: lr_tile<16, KIND_DENSITY, 0, false, 16>(a, b.ktile, b.wtile, 0, sh, lane); break;
-    }
+    // nbp: padded size in the low byte, column part of a 64-band item in bit 8,
+    // bit 9 set when nc <= 8 (row-layout inversions over 8 columns, else 16)
+    const int part = (b.nbp >> 8) & 1;
+    if (b.nbp & 512)
+      lr_batched_item<8>(a, b, part, sh, lane);
+    else
+      lr_batched_item<16>(a, b, part, sh, lane);
   }
 }
 
