@@ -73,7 +73,24 @@ def parse():
     ap.add_argument("--extra", action="store_true", help="also time the other workloads")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (use the default variants)")
     ap.add_argument("--batched", action="store_true", help="also time the batched workload (8 iterates, graph)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device-to-device three times (reference for the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device copy of known size: under rocprofv3 --pmc FETCH_SIZE /
+    WRITE_SIZE it gives the factors that turn those counters into bytes."""
+    import torch
+
+    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_per_copy": x.numel() * 8, "copies": 3}}), flush=True)
 
 
 def time_density(ctx, lat, sig, mu, steps, warmup, tail=2):
@@ -186,6 +203,9 @@ def main():
         print("bench.py: this build runs on one GPU only; the path shards over k across GPUs "
               "by design, but multi-GPU runs are not part of it (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
 
     from paper_1111_2157_amd import synth

@@ -294,6 +294,12 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
     // running sum of G, column tiles b0 .. b0 + CT; the three-product form
     // needs three accumulators per tile, so it is used here only up to four tiles
     CAcc<M3 && T * CT <= 4> sacc[T][CT];
+    // sum over frequencies of d at band 16 t + c16: the D term of sum_n G,
+    // added to the diagonal once per k so that the running sum above is
+    // touched only by the matrix cores inside the frequency loop
+    double2 dsum[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) dsum[t] = make_double2(0.0, 0.0);
     if (want_s) {
 #pragma unroll
       for (int t = 0; t < T; ++t)
@@ -370,6 +376,13 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
         double2 dcol[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) dcol[t] = 16 * t + c16 < nb ? inv_z_minus(mu, wn, eb[t]) : make_double2(0.0, 0.0);
+        if (want_s) {
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            dsum[t].x += dcol[t].x;
+            dsum[t].y += dcol[t].y;
+          }
+        }
         v4d glr, gli;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -452,11 +465,6 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
                   double2 aa = cmul(dt, make_double2(s.x, -s.y));
                   sacc[t][c].mac(aa.x, aa.y, qr[j], qi[j]);
                 }
-                if (t == b) {
-#pragma unroll
-                  for (int i = 0; i < 4; ++i)
-                    if (hasdiag && idg == i) sacc[t][c].add(i, db.x, db.y);
-                }
               }
             }
           }
@@ -533,7 +541,12 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             int e = (t * T + b0 + c) * 4 + i;
-            sp[e * 64 + lane] = make_double2(sacc[t][c].re()[i], sacc[t][c].im()[i]);
+            double2 v = make_double2(sacc[t][c].re()[i], sacc[t][c].im()[i]);
+            if (t == b0 + c && hasdiag && idg == i) {
+              v.x += dsum[t].x;
+              v.y += dsum[t].y;
+            }
+            sp[e * 64 + lane] = v;
           }
     }
     if constexpr (KIND == KIND_TRACE) {
