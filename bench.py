@@ -34,6 +34,38 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
 
+# HBM traffic of the timed kernel per launch, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, scaled by 2 and 1 as a plain 1 GiB copy reads
+# under --copy-calibration), recorded in profiles/lr_kernel_d-shell.md.  It is
+# valid only for the kernel sources it was measured on (their SHA-256), the same
+# workload and the same tuned variant; otherwise "traffic" is null.
+TRAFFIC = {
+    ("d-shell-Nk512-Nb32-Nc10-Nw1024", 32, 10): {
+        "fetch_bytes": 336799.5 * 2 * 1024,
+        "write_bytes": 851968.0 * 1024,
+        "sources_sha256": "0d422f9c4bc939777b778980148f1ae6e53d976ef9c76c299f6b54097793a07b",
+        "profile": "profiles/lr_kernel_d-shell.md",
+    },
+}
+TRAFFIC_SOURCES = ["paper_1111_2157_amd/csrc/lowrank_impl.h", "paper_1111_2157_amd/csrc/dyson_impl.h",
+                   "paper_1111_2157_amd/csrc/dmft_internal.h", "paper_1111_2157_amd/csrc/lowrank_32.hip"]
+
+
+def measured_traffic(workload, nbp, var):
+    """Counter-measured HBM bytes per launch of this kernel, or None."""
+    import hashlib
+
+    rec = TRAFFIC.get((workload, nbp, var))
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for p in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec
+
 
 def flops_per_eval(nb, nc):
     """Algorithmic FP64 flops of one (k, i w_n) evaluation in the dense form:
@@ -225,6 +257,8 @@ def main():
     nk, nw, nb, nc = wl.lattice.nk, sig.nw, wl.lattice.nb_max, wl.lattice.nc
     evals = nk * nw
     kname, fpe = density_kernel(ctx, nb, nc)
+    nbp = (nb + 15) // 16 * 16
+    traffic = measured_traffic(wl.name, nbp, ctx.get_variant(0, nbp))
     fl = fpe * evals
     kavg = kms / max(launches, 1) / 1e3
     achieved = fl / kavg / 1e12
@@ -244,7 +278,11 @@ def main():
         "config": {"workload": wl.name, "nk": nk, "nb": nb, "nc": nc, "nw": nw, "beta": sig.beta,
                    "mu": mu, "outputs": "N(k), G_loc, N_tot/n_corr/<H_KS>", "tail_order": 2},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": (traffic["fetch_bytes"] + traffic["write_bytes"]) if traffic else None,
+                     "traffic_unit": "bytes per launch (HBM, counters)",
+                     "traffic_gbps": ((traffic["fetch_bytes"] + traffic["write_bytes"]) / kavg / 1e9) if traffic else None,
+                     "traffic_profile": traffic["profile"] if traffic else None,
                      "kernel": kname, "kernel_ms": kavg * 1e3, "flop_per_eval": fpe,
                      "dense_flop_per_eval": flops_per_eval(nb, nc)},
         "autotune": tune,
