@@ -144,13 +144,28 @@ def time_density(ctx, lat, sig, mu, steps, warmup, tail=2):
     return (t1 - t0) / steps, kms, launches
 
 
+def host_cpu():
+    """Model name of the host CPU (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(wl, mu, target_s):
+    """The FP64 oracle on this host's cores (OpenMP over k, at most 16 threads
+    unless ORACLE_THREADS says otherwise) on a bounded k-sample of the same
+    workload, plus a single-thread rate on a smaller sample."""
     import numpy as np
 
     import oracle
 
     lat, sig = wl.lattice, wl.sigma
-    cores = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    cores = int(os.environ.get("ORACLE_THREADS", min(16, os.cpu_count() or 1)))
     # calibrate on a few k-points, then size the sample to ~target_s
     t0 = time.perf_counter()
     oracle.density(lat, sig, mu, 2, klist=list(range(cores)), nthreads=cores)
@@ -161,9 +176,54 @@ def cpu_baseline(wl, mu, target_s):
     oracle.density(lat, sig, mu, 2, klist=ks, nthreads=cores)
     t = time.perf_counter() - t0
     evals = nsel * sig.nw
+    # single thread: as many k-points as fit in about a quarter of the target
+    t0 = time.perf_counter()
+    oracle.density(lat, sig, mu, 2, klist=[0], nthreads=1)
+    t1 = time.perf_counter() - t0
+    n1 = int(max(1, min(lat.nk, (target_s / 4) / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.density(lat, sig, mu, 2, klist=list(range(n1)), nthreads=1)
+    t1 = time.perf_counter() - t0
     return {"value": evals / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": "N(k) of the first %d of %d k-points over all %d frequencies (%d evals, %.1f s)"
-                      % (nsel, lat.nk, sig.nw, evals, t)}
+                      % (nsel, lat.nk, sig.nw, evals, t),
+            "single_thread": {"value": n1 * sig.nw / t1, "unit": "evals/s",
+                              "sample": "first %d k-points, %.1f s" % (n1, t1)},
+            "host_cpu": host_cpu()}
+
+
+def adjoint_pass(ctx, tune=True):
+    """Forward + fused scalar adjoint (N_tot, dN/dmu, dN/dSigma in one pass) on
+    the differentiation workload."""
+    import torch
+
+    from paper_1111_2157_amd import synth
+    from paper_1111_2157_amd.dyson import Lattice, SelfEnergy
+
+    wl = synth.differentiation()
+    lat, sig = Lattice.from_host(wl.lattice), SelfEnergy.from_host(wl.sigma)
+    mu = -0.8
+    ctx.dmft_ntot_vjp(lat, sig, mu)  # warm-up
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.dmft_ntot_vjp(lat, sig, mu)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    nb, nc = wl.lattice.nb_max, wl.lattice.nc
+    nbp = (nb + 15) // 16 * 16
+    evals = wl.lattice.nk * wl.sigma.nw
+    var = ctx.get_variant(2, nbp)
+    lowrank = var >= 0 and bool(var & 8)
+    # dense form: forward (embed + invert + project) plus the adjoint's extra work;
+    # low-rank form: X, X2, X3 (3 Nb Nc^2), two inversions, R, R X2 and the four
+    # Nc x Nc products of S G^2 S^dag (9 Nc^3)
+    dense_fl = 8.0 * (nb ** 3 + 2 * nb * nb * nc + 2 * nb * nc * nc) + 8.0 * (nb * nb * nc + nb * nc * nc + nb * nb)
+    fl = 8.0 * (3 * nb * nc * nc + 9 * nc ** 3) if lowrank else dense_fl
+    return {"workload": wl.name, "evals_per_s": evals / sec, "ms_per_pass": sec * 1e3,
+            "form": "low-rank" if lowrank else "dense", "variant": var, "flop_per_eval": fl,
+            "tflops": fl * evals / sec / 1e12, "tflops_dense_count": dense_fl * evals / sec / 1e12}
 
 
 def mu_search(ctx, tune=True):
@@ -302,6 +362,7 @@ def main():
             f = fp * ev
             extra[w.name] = {"evals_per_s": ev / sc, "ms_per_pass": sc * 1e3, "kernel": kn,
                              "kernel_tflops": f / (km / max(ln, 1) / 1e3) / 1e12}
+        extra["adjoint (N_tot, dN/dmu, dN/dSigma)"] = adjoint_pass(ctx)
         rec["extra"] = extra
     if args.batched:
         rec["batched"] = batched(ctx)

@@ -154,7 +154,11 @@ int density_matrix_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma*
  *   sigma_bar: DEVICE [nw][nc][nc] complex
  *              dN_tot/dSigma(i w_n) = (2/beta) [ sum_k w_k S_k G_kn^2 S_k^dag ]^dag
  *              in PyTorch's complex convention, or NULL.  Equal to
- *              density_matrix_vjp with nk_bar_k = w_k I and no gloc_bar. */
+ *              density_matrix_vjp with nk_bar_k = w_k I and no gloc_bar.
+ * Kernel kind 2 (see dmft_variants): in the low-rank form the per-(k, n)
+ * quantities come from S G^2 S^dag = (I + Gl Sigma') X2 (I + Sigma' Gl) with
+ * X2 = S D^2 S^dag and Gl = S G S^dag; that form covers band windows up to 64,
+ * the dense adjoint kernel (code 0) windows up to 48 (DMFT_EUNSUPPORTED above). */
 int dmft_ntot_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu,
                   int tail_order, double* sigma_bar, double* out, void* ws, size_t ws_bytes,
                   hipStream_t stream);
@@ -208,15 +212,18 @@ enum { DMFT_FORM_AUTO = -1, DMFT_FORM_DENSE = 0, DMFT_FORM_LOWRANK = 1 };
 int dmft_batched_set_form(dmft_handle h, int form);
 int dmft_batched_form(dmft_handle h);
 
-/* Autotuner: times every compiled kernel variant that fits this shape on the
- * handle's GPU, after checking that each one reproduces the reference variant,
- * and caches the fastest in the handle (used by all later calls of that
- * shape).  best_out (HOST, may be NULL) receives a short description. */
+/* Autotuner: times every compiled kernel variant of the three kinds (density
+ * pass, trace pass, fused scalar adjoint) that fits this shape on the
+ * handle's GPU, with a few frequency-tile sizes, after checking that each one
+ * reproduces the reference variant to 1e-11, and caches the fastest in the
+ * handle (used by all later calls of that shape).  best_out (HOST, may be
+ * NULL) receives a short description. */
 int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu,
                   void* ws, size_t ws_bytes, hipStream_t stream, char* best_out, size_t best_len);
 
 /* Kernel variants.  kind 0 = density pass (density_matrix, gloc_compute),
- * kind 1 = trace pass (dmft_ntot, find_mu); nbp = padded band-window size
+ * kind 1 = trace pass (dmft_ntot, find_mu), kind 2 = fused scalar adjoint
+ * (dmft_ntot_vjp; code 0 there is the dense adjoint kernel); nbp = padded band-window size
  * (16, 32, 48 or 64).  dmft_variants writes up to max variant codes into out
  * (HOST) and returns their number (the first is the default); dmft_set_variant
  * pins one for later calls on this handle (var = -1 restores the default) and

@@ -161,6 +161,10 @@ Tile choose_tile(const dmft_handle h, int kind, int nk, int nw, int nbp) {
   return it != h->tune.end() ? it->second : heuristic_tile(nk, nw);
 }
 
+const char* kind_name(int kind) {
+  return kind == KIND_DENSITY ? "density" : kind == KIND_TRACE ? "trace" : "adjoint";
+}
+
 int choose_var(const dmft_handle h, int kind, int nbp) {
   char key[32];
   snprintf(key, sizeof key, "%d/%d", kind, nbp);
@@ -343,7 +347,13 @@ int run_dyson(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, con
       }
       HIPCHK(h, hipEventRecord(ev.first, s));
     }
-    if (adj.gen >= 0) {
+    if (adj.gen == 0 && (choose_var(h, KIND_ADJOINT, b.nbp) & 8)) {
+      // fused scalar adjoint in the low-rank form (same partials as the dense kernel)
+      DysonArgs aa = a;
+      aa.mode = MODE_ADJ;
+      HIPCHK(h, launch_dyson(b.nbp, choose_var(h, KIND_ADJOINT, b.nbp), aa, b.n_ktiles, s));
+    } else if (adj.gen >= 0) {
+      if (b.nbp > 48) return fail(h, DMFT_EUNSUPPORTED, "the dense adjoint supports band windows up to 48");
       HIPCHK(h, launch_adjoint(b.nbp, adj.gen, a, adj.nbar, L.ragged ? (const int64_t*)(ws + L.meta_offn) : nullptr,
                                adj.gbar, (double*)(ws + L.xpart), (double*)(ws + L.tpart), b.n_ktiles, s));
     } else {
@@ -534,8 +544,37 @@ int dmft_ntot(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, dou
   return ntot_impl(h, lat, sig, L, (char*)ws, mu, nullptr, tail_order, out, stream);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Fused scalar adjoint of N_tot on a prepared layout: out = [N_tot, dN/dmu]
+// (device, may be NULL), sigma_bar = dN/dSigma (device [nw][nc][nc], may be NULL).
+int ntot_vjp_impl(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, const Layout& L, char* w, double mu,
+                  int tail_order, double* sigma_bar, double* out, hipStream_t stream) {
+  AdjReq adj;
+  adj.gen = 0;
+  int r = run_dyson(h, lat, sig, L, w, mu, nullptr, 0, stream, adj);
+  if (r) return r;
+  EpilogueArgs e = epilogue_args(lat, sig, L, w, mu, nullptr, tail_order);
+  if (out) {
+    HIPCHK(h, launch_adj_epilogue(e, nullptr, stream));
+    // per-k values are [tr N, d tr N/dmu, mubar_k]: reduce all three, return the first two
+    HIPCHK(h, launch_scalar_reduce_mask(lat->nk, lat->wk, e.kscal, 3, 4, (double*)(w + L.out2), stream));
+    HIPCHK(h, hipMemcpyAsync(out, w + L.out2, 2 * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  }
+  if (sigma_bar)
+    HIPCHK(h, launch_sigma_bar_reduce(L.n_ktiles_total, sig->nw, lat->nc, (const double*)(w + L.xpart),
+                                      2.0 / sig->beta, 1, sigma_bar, stream));
+  return DMFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int dmft_variants(int kind, int nbp, int* out, int max) {
-  if (kind != 0 && kind != 1) return 0;
+  if (kind < 0 || kind > 2) return 0;
   int v[16];
   int n = dyson_variants(nbp, kind, v, 16);
   for (int i = 0; i < n && i < max && out; ++i) out[i] = v[i];
@@ -543,7 +582,7 @@ int dmft_variants(int kind, int nbp, int* out, int max) {
 }
 
 int dmft_get_variant(dmft_handle h, int kind, int nbp) {
-  if (!h || (kind != 0 && kind != 1)) return -1;
+  if (!h || kind < 0 || kind > 2) return -1;
   return choose_var(h, kind, nbp);
 }
 
@@ -594,23 +633,7 @@ int dmft_ntot_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
   Layout L;
   int r = prepare(h, lat, sig, ws, ws_bytes, L, KIND_ADJOINT, stream);
   if (r) return r;
-  if (L.nbp_max > 48) return fail(h, DMFT_EUNSUPPORTED, "the adjoint supports band windows up to 48");
-  char* w = (char*)ws;
-  AdjReq adj;
-  adj.gen = 0;
-  r = run_dyson(h, lat, sig, L, w, mu, nullptr, 0, stream, adj);
-  if (r) return r;
-  EpilogueArgs e = epilogue_args(lat, sig, L, w, mu, nullptr, tail_order);
-  if (out) {
-    HIPCHK(h, launch_adj_epilogue(e, nullptr, stream));
-    // per-k values are [tr N, d tr N/dmu, mubar_k]: reduce all three, return the first two
-    HIPCHK(h, launch_scalar_reduce_mask(lat->nk, lat->wk, e.kscal, 3, 4, (double*)(w + L.out2), stream));
-    HIPCHK(h, hipMemcpyAsync(out, w + L.out2, 2 * sizeof(double), hipMemcpyDeviceToDevice, stream));
-  }
-  if (sigma_bar)
-    HIPCHK(h, launch_sigma_bar_reduce(L.n_ktiles_total, sig->nw, lat->nc, (const double*)(w + L.xpart),
-                                      2.0 / sig->beta, 1, sigma_bar, stream));
-  return DMFT_OK;
+  return ntot_vjp_impl(h, lat, sig, L, (char*)ws, mu, tail_order, sigma_bar, out, stream);
 }
 
 int density_matrix_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu, int tail_order,
@@ -755,7 +778,7 @@ int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
-  for (int kind : {KIND_DENSITY, KIND_TRACE}) {
+  for (int kind : {KIND_DENSITY, KIND_TRACE, KIND_ADJOINT}) {
     Layout L0;
     r = make_layout(h, lat, sig, L0, kind);
     if (r) return r;
@@ -773,7 +796,8 @@ int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
       for (auto& u : tiles) dup |= (u.wt == t.wt && u.kt == t.kt);
       if (!dup) tiles.push_back(t);
     }
-    size_t nres = kind == KIND_DENSITY ? (size_t)nw * nc * nc * 2 + 3 : 2;
+    size_t nres = kind == KIND_DENSITY ? (size_t)nw * nc * nc * 2 + 3
+                  : kind == KIND_ADJOINT ? (size_t)nw * nc * nc * 2 + 2 : 2;
     std::vector<double> ref(nres), got(nres);
     bool have_ref = false;
     double best_ms = 1e300;
@@ -795,6 +819,7 @@ int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
           if (kind == KIND_DENSITY)
             return density_impl(h, lat, sig, L, w, mu, nullptr, 2, nullptr, out, out + (size_t)nw * nc * nc * 2,
                                 stream);
+          if (kind == KIND_ADJOINT) return ntot_vjp_impl(h, lat, sig, L, w, mu, 2, out + 2, out, stream);
           return ntot_impl(h, lat, sig, L, w, mu, nullptr, 2, out, stream);
         };
         r = run();
@@ -822,8 +847,8 @@ int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
         }
         have_ref = true;
         char line[160];
-        snprintf(line, sizeof line, "%s nbp=%d var=%d kt=%d wt=%d: %.3f ms%s\n",
-                 kind == KIND_DENSITY ? "density" : "trace", nbp, vars[vi], t.kt, t.wt, ms, ok ? "" : " (rejected)");
+        snprintf(line, sizeof line, "%s nbp=%d var=%d kt=%d wt=%d: %.3f ms%s\n", kind_name(kind), nbp, vars[vi], t.kt,
+                 t.wt, ms, ok ? "" : " (rejected)");
         report += line;
         if (ok && ms < best_ms) {
           best_ms = ms;
@@ -835,8 +860,8 @@ int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
     h->tvar[key] = best_var;
     h->tune[tile_key(kind, nbp, nk, nw)] = best_tile;
     char line[160];
-    snprintf(line, sizeof line, "best %s: var=%d kt=%d wt=%d %.3f ms\n", kind == KIND_DENSITY ? "density" : "trace",
-             best_var, best_tile.kt, best_tile.wt, best_ms);
+    snprintf(line, sizeof line, "best %s: var=%d kt=%d wt=%d %.3f ms\n", kind_name(kind), best_var, best_tile.kt,
+             best_tile.wt, best_ms);
     report += line;
   }
   (void)hipEventDestroy(e0);

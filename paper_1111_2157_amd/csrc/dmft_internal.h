@@ -14,6 +14,8 @@ enum : int {
   MODE_S = 1,      // accumulate sum_n G_kn into per-(frequency tile, k) partials
   MODE_GLOC = 2,   // accumulate w_k S G S^dag into per-(k tile, n) partials
   MODE_TRACE = 4,  // accumulate sum_n Re tr G and sum_n Re tr G^2 per (frequency tile, k)
+  MODE_ADJ = 8,    // low-rank fused scalar adjoint: MODE_TRACE's sums (stride 3 in tpart) and
+                   // w_k S G^2 S^dag per (k tile, n) in xpart
 };
 
 // Error bits raised on the device.

@@ -20,9 +20,17 @@ int variants_32(int kind, int* out, int max);
 int variants_48(int kind, int* out, int max);
 hipError_t launch_lowrank(int nbp, int var, const DysonArgs& a, dim3 grid, hipStream_t s);
 int lowrank_variants(int nbp, int kind, int* out, int max);
+bool dyson_supported(int nbp);
 
 // Dense variants first (the first one is the default), then the low-rank ones.
+// Kind 2 (fused scalar adjoint): the low-rank variants first, then code 0 for
+// the dense adjoint kernel, which exists up to 48 bands.
 int dyson_variants(int nbp, int kind, int* out, int max) {
+  if (kind == 2) {
+    int n = lowrank_variants(nbp, kind, out, max);
+    if (nbp <= 48 && dyson_supported(nbp) && n < max) out[n++] = 0;
+    return n;
+  }
   int n = 0;
   switch (nbp) {
     case 16: n = variants_16(kind, out, max); break;

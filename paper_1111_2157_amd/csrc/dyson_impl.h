@@ -289,7 +289,8 @@ __device__ __forceinline__ void load_pt(Proj<NBP>& pr, const double2* P, int nc,
     }
 }
 
-enum { KIND_DENSITY = 0, KIND_TRACE = 1 };
+// KIND_ADJ (fused scalar adjoint of N_tot) exists in the low-rank form only.
+enum { KIND_DENSITY = 0, KIND_TRACE = 1, KIND_ADJ = 2 };
 
 template <int NBP, int KIND, int SLDS>
 struct KernelShared {

@@ -34,7 +34,11 @@
 //      through LDS;
 //   3. per frequency, in the output layout of the matrix core: R, then either
 //      sum_n G += D + (D S^dag)(R S D) and the w_k Gl partial of G_loc
-//      (density kind), or the traces (trace kind).
+//      (density kind), or the traces (trace kind), or the traces and
+//      w_k S G^2 S^dag (adjoint kind: the fused scalar adjoint of N_tot,
+//      dN/dSigma_n = (2/beta) [sum_k w_k S G^2 S^dag]^dag), with
+//      S G = (I + X R) S D, G S^dag = D S^dag (I + R X) and I + X R = Gl X^-1 = I + Gl Sigma':
+//          S G^2 S^dag = (I + Gl Sigma') X2 (I + Sigma' Gl).
 //
 // Operand bookkeeping of the 16x16x4 instruction: a matrix M used as the A
 // operand comes from registers holding M^T in the output layout (lane
@@ -383,12 +387,17 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
             dsum[t].y += dcol[t].y;
           }
         }
-        v4d glr, gli;
+        v4d glr, gli, gltr, glti;  // Gl and (adjoint kind) Gl^T in the output layout
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           double2 v = sh.buf[f][(q + 4 * i) * 17 + c16];
           glr[i] = v.x;
           gli[i] = v.y;
+          if constexpr (KIND == KIND_ADJ) {
+            double2 u = sh.buf[f][c16 * 17 + q + 4 * i];
+            gltr[i] = u.x;
+            glti[i] = u.y;
+          }
         }
         const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)nf * nc * nc;
         double sa_r[4], sa_i[4];
@@ -527,6 +536,62 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
           }
           trg += sd + t2;
           trg2 += sd2 + 2.0 * t3 + ee;
+          if constexpr (KIND == KIND_ADJ) {
+            // M = S G^2 S^dag = (I + Gl Sigma') X2 (I + Sigma' Gl), as
+            // Rr = I + Sigma' Gl, Y = X2 Rr, M = Y + Gl (Sigma' Y)
+            CAcc<M3> rra;
+            {
+              v4d id = {0.0, 0.0, 0.0, 0.0}, z = id;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) id[i] = (hasdiag && idg == i) ? 1.0 : 0.0;
+              rra.set(id, z);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              rra.mac(sa_r[j], sa_i[j], glr[j], gli[j]);
+            }
+            const v4d rrr = rra.re(), rri = rra.im();
+            v4d x2tr, x2ti;
+            tile_transpose(x2r, x2i, x2tr, x2ti, sh.buf[f], q, c16);
+            CAcc<M3> ya;
+            ya.zero();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              ya.mac(x2tr[j], x2ti[j], rrr[j], rri[j]);
+            }
+            const v4d yr = ya.re(), yi = ya.im();
+            CAcc<M3> za;
+            za.zero();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              za.mac(sa_r[j], sa_i[j], yr[j], yi[j]);
+            }
+            const v4d zr = za.re(), zi = za.im();
+            CAcc<M3> ma;
+            ma.set(yr, yi);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              ma.mac(gltr[j], glti[j], zr[j], zi[j]);
+            }
+            const v4d mr = ma.re(), mi = ma.im();
+            double2* mp = reinterpret_cast<double2*>(a.xpart) + ((int64_t)(a.ktile_base + ktile) * a.nw + nf) * 256;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              if (q + 4 * i < nc && c16 < nc) {
+                double2 v = make_double2(wk * mr[i], wk * mi[i]);
+                if (kk != kk0) {
+                  double2 o = mp[i * 64 + lane];
+                  v.x += o.x;
+                  v.y += o.y;
+                }
+                mp[i * 64 + lane] = v;
+              }
+            }
+          }
         }
       }
       wave_sync();
@@ -549,7 +614,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
             sp[e * 64 + lane] = v;
           }
     }
-    if constexpr (KIND == KIND_TRACE) {
+    if constexpr (KIND != KIND_DENSITY) {
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
         trg += __shfl_xor(trg, off);
@@ -557,8 +622,12 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
       }
       if (!__builtin_isfinite(trg) || !__builtin_isfinite(trg2)) nonfinite = 1;
       if (lane == 0) {
-        a.tpart[((int64_t)wtile * a.nk + k) * 2 + 0] = trg;
-        a.tpart[((int64_t)wtile * a.nk + k) * 2 + 1] = trg2;
+        // trace kind: [Re tr G, Re tr G^2]; adjoint kind: the same and a zero mubar share
+        constexpr int stride = KIND == KIND_ADJ ? 3 : 2;
+        double* tp = a.tpart + ((int64_t)wtile * a.nk + k) * stride;
+        tp[0] = trg;
+        tp[1] = trg2;
+        if constexpr (KIND == KIND_ADJ) tp[2] = 0.0;
       }
     }
   }  // k

@@ -144,3 +144,56 @@ def test_autograd_matches_oracle_gradient(ctx):
     ref, mref = oracle.vjp(lat, sig, 0.1, nbar=nbar, gbar=gbar)
     assert relerr(sigma.grad.cpu().numpy(), ref) <= 1e-10
     assert abs(float(mu.grad) - mref) <= 1e-10 * max(1.0, abs(mref))
+
+
+ADJ_VARIANT_CASES = [(16, lambda: synth.plain(nk=6, nw=40), -1.5), (32, lambda: synth.d_shell(nk=6, nw=32), 0.2),
+                     (48, lambda: synth.differentiation(nk=4, nw=24), -0.5),
+                     (64, lambda: synth.f_shell(nk=3, nb=64, nw=20), 0.0)]
+
+
+@pytest.mark.parametrize("nbp,maker,mu", ADJ_VARIANT_CASES)
+def test_every_adjoint_variant_matches_oracle(nbp, maker, mu):
+    """Kind 2 (fused scalar adjoint): the low-rank variants and, up to 48
+    bands, the dense adjoint kernel (code 0), each against the oracle."""
+    from paper_1111_2157_amd.dyson import Context, Lattice, SelfEnergy
+
+    wl = maker()
+    lat, sig = wl.lattice, wl.sigma
+    n, d = oracle.trace(lat, sig, mu)
+    nbar = [lat.wk[k] * np.eye(lat.nb[k]) for k in range(lat.nk)]
+    ref, _ = oracle.vjp(lat, sig, mu, nbar=nbar)
+    c = Context(0)
+    dl, ds = Lattice.from_host(lat), SelfEnergy.from_host(sig)
+    vars_ = c.variants(2, nbp)
+    assert any(v & 8 for v in vars_) and ((0 in vars_) == (nbp <= 48))
+    for var in vars_:
+        print("adjoint variant", nbp, var, flush=True)
+        c.set_variant(2, nbp, var)
+        out, sb = c.dmft_ntot_vjp(dl, ds, mu)
+        out, sb = out.cpu().numpy(), sb.cpu().numpy()
+        c.sync_status()
+        assert abs(out[0] - n) <= 1e-10 * abs(n), var
+        assert abs(out[1] - d) <= 1e-10 * abs(d), var
+        for nn in range(sig.nw):
+            assert relerr(sb[nn], ref[nn]) <= 1e-10, (var, nn)
+    c.close()
+
+
+def test_lowrank_adjoint_ragged_up_to_64(ctx):
+    """Ragged windows 14..64 (the dense adjoint stops at 48)."""
+    from paper_1111_2157_amd.dyson import Lattice, SelfEnergy
+
+    wl = synth.batched(nk=8, nb_lo=14, nb_hi=64, nw=24, n_iter=2)
+    for s in range(2):
+        lat, sig = wl.lattices[s], wl.sigmas[s]
+        assert lat.nb.max() > 48
+        out, sb = ctx.dmft_ntot_vjp(Lattice.from_host(lat), SelfEnergy.from_host(sig), 0.1)
+        out, sb = out.cpu().numpy(), sb.cpu().numpy()
+        ctx.sync_status()
+        n, d = oracle.trace(lat, sig, 0.1)
+        assert abs(out[0] - n) <= 1e-10 * abs(n)
+        assert abs(out[1] - d) <= 1e-10 * abs(d)
+        nbar = [lat.wk[k] * np.eye(lat.nb[k]) for k in range(lat.nk)]
+        ref, _ = oracle.vjp(lat, sig, 0.1, nbar=nbar)
+        for nn in range(sig.nw):
+            assert relerr(sb[nn], ref[nn]) <= 1e-10, (s, nn)
