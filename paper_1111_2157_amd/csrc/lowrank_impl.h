@@ -377,6 +377,16 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
         const int nf = n + f;
         if (nf >= n1) break;
         const double wn = (double)(2 * nf + 1) * M_PI / beta;
+        // the k-tile partial this frequency adds to (G_loc, or S G^2 S^dag for
+        // the adjoint kind): read here, so that its latency overlaps the
+        // products below (the compiler cannot move it above the previous
+        // frequency's stores)
+        double2* part = reinterpret_cast<double2*>(a.xpart) + ((int64_t)(a.ktile_base + ktile) * a.nw + nf) * 256;
+        const bool part_rmw = kk != kk0 && ((KIND == KIND_DENSITY && want_x) || KIND == KIND_ADJ);
+        double2 prev[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          prev[i] = (part_rmw && q + 4 * i < nc && c16 < nc) ? part[i * 64 + lane] : make_double2(0.0, 0.0);
         double2 dcol[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) dcol[t] = 16 * t + c16 < nb ? inv_z_minus(mu, wn, eb[t]) : make_double2(0.0, 0.0);
@@ -478,19 +488,10 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
             }
           }
           if (want_x) {
-            double2* xp = reinterpret_cast<double2*>(a.xpart) + ((int64_t)(a.ktile_base + ktile) * a.nw + nf) * 256;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              if (q + 4 * i < nc && c16 < nc) {
-                double2 v = make_double2(wk * glr[i], wk * gli[i]);
-                if (kk != kk0) {
-                  double2 o = xp[i * 64 + lane];
-                  v.x += o.x;
-                  v.y += o.y;
-                }
-                xp[i * 64 + lane] = v;
-              }
-            }
+            for (int i = 0; i < 4; ++i)
+              if (q + 4 * i < nc && c16 < nc)
+                part[i * 64 + lane] = make_double2(wk * glr[i] + prev[i].x, wk * gli[i] + prev[i].y);
           }
         } else {
           // X2 = S D^2 S^dag, X3 = S D^3 S^dag of this frequency
@@ -578,19 +579,10 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
               ma.mac(gltr[j], glti[j], zr[j], zi[j]);
             }
             const v4d mr = ma.re(), mi = ma.im();
-            double2* mp = reinterpret_cast<double2*>(a.xpart) + ((int64_t)(a.ktile_base + ktile) * a.nw + nf) * 256;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              if (q + 4 * i < nc && c16 < nc) {
-                double2 v = make_double2(wk * mr[i], wk * mi[i]);
-                if (kk != kk0) {
-                  double2 o = mp[i * 64 + lane];
-                  v.x += o.x;
-                  v.y += o.y;
-                }
-                mp[i * 64 + lane] = v;
-              }
-            }
+            for (int i = 0; i < 4; ++i)
+              if (q + 4 * i < nc && c16 < nc)
+                part[i * 64 + lane] = make_double2(wk * mr[i] + prev[i].x, wk * mi[i] + prev[i].y);
           }
         }
       }
