@@ -124,6 +124,22 @@ int density_matrix(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig
                    int tail_order, double* nk, double* gloc, double* scalars, void* ws,
                    size_t ws_bytes, hipStream_t stream);
 
+/* DMFT self-consistency step that consumes G_loc (Sec. 3.2.2 eq. dmftloop2,
+ * the impurity level of eq. H_imp):
+ *   e_imp: DEVICE [nc][nc] complex, written (may be NULL):
+ *          E_imp = sum_k w_k S_k diag(E_k) S_k^dag - diag(V_DC);
+ *   delta: DEVICE [nw][nc][nc] complex, written:
+ *          Delta(i w_n) = i w_n + mu - E_imp - Sigma(i w_n) - G_loc(i w_n)^-1;
+ *   gloc:  DEVICE [nw][nc][nc] complex, read: G_loc at the same mu, as written
+ *          by gloc_compute or density_matrix.
+ * G_loc^-1 is a Gauss-Jordan sweep without pivoting (the anti-Hermitian part
+ * of G_loc(i w_n) is negative definite for w_n > 0); a zero pivot sets
+ * DMFT_ESINGULAR and non-finite output DMFT_ENONFINITE in the error word
+ * (dmft_sync_status).  ws as for density_matrix. */
+int dmft_hybridization(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu,
+                       const double* gloc, double* delta, double* e_imp, void* ws, size_t ws_bytes,
+                       hipStream_t stream);
+
 /* Trace-only pass of the mu search (Sec. 3.3 eq. fix_mu) with its adjoint:
  * out: DEVICE [2] = { N_tot(mu), dN_tot/dmu }, where
  *   dN_tot/dmu = sum_k w_k [ (beta/4) nb_k - (2/beta) sum_n (Re tr G_kn^2 + nb_k / w_n^2) ]

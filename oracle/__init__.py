@@ -203,3 +203,34 @@ def green(lat, sig, mu, k, n):
     if _load().orc_green(*pk.refs, float(mu), int(k), int(n), _ptr(g)):
         raise ZeroDivisionError("singular")
     return g
+
+
+def impurity_level(lat, sig):
+    """E_imp = sum_k w_k S_k diag(E_k) S_k^dag - diag(V_DC) (nc x nc): the level
+    of the correlated orbitals in the impurity model of Sec. 3.2.2 (eq. H_imp),
+    with V_DC entering as it does in the lattice resolvent (eq. dmftloop1)."""
+    nc = int(lat.nc)
+    e = np.zeros((nc, nc), np.complex128)
+    for k in range(int(lat.nk)):
+        p = lat.proj_k(k)
+        eps = lat.eps_k(k)
+        for a in range(nc):
+            for b in range(nc):
+                e[a, b] += lat.wk[k] * np.sum(p[a] * eps * np.conj(p[b]))
+    return e - np.diag(np.asarray(sig.e_dc, np.float64))
+
+
+def hybridization(lat, sig, mu, nlist=None, nthreads=None):
+    """Hybridization function of the DMFT self-consistency (Sec. 3.2.2 eq.
+    dmftloop2), Delta(i w_n) = i w_n + mu - E_imp - Sigma(i w_n) - G_loc(i w_n)^-1,
+    for the n in ``nlist`` (default: all).  Returns (delta [len, nc, nc], E_imp).
+    G_loc is the oracle's own; its inverse is the oracle's pivoting elimination."""
+    ns = list(range(int(sig.nw))) if nlist is None else list(nlist)
+    g = gloc(lat, sig, mu, ns, nthreads=nthreads)
+    eimp = impurity_level(lat, sig)
+    nc = int(lat.nc)
+    out = np.zeros((len(ns), nc, nc), np.complex128)
+    for i, n in enumerate(ns):
+        w = (2.0 * n + 1.0) * np.pi / float(sig.beta)
+        out[i] = (1j * w + mu) * np.eye(nc) - eimp - np.asarray(sig.sigma[n]) - invert(g[i])
+    return out, eimp

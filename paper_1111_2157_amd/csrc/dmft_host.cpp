@@ -521,6 +521,22 @@ int gloc_compute(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, 
   return density_impl(h, lat, sig, L, (char*)ws, mu, nullptr, 2, nullptr, gloc, nullptr, stream);
 }
 
+int dmft_hybridization(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu, const double* gloc,
+                       double* delta, double* e_imp, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!gloc || !delta) return fail(h, DMFT_EINVAL, "gloc and delta are required");
+  if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
+  Layout L;
+  int r = prepare(h, lat, sig, ws, ws_bytes, L, KIND_DENSITY, stream);
+  if (r) return r;
+  char* w = (char*)ws;
+  double* eimp = e_imp ? e_imp : (double*)(w + L.tune_a);  // scratch when not requested
+  HIPCHK(h, launch_self_consistency(lat->nk, lat->nc, sig->nw, L.ragged ? 0 : lat->nb_max,
+                                    (const int32_t*)(w + L.meta_nb), (const int64_t*)(w + L.meta_offb), lat->eps,
+                                    lat->wk, lat->proj, sig->e_dc, sig->beta, mu, gloc, sig->sigma, eimp, delta,
+                                    (int*)(w + L.err), stream));
+  return DMFT_OK;
+}
+
 int density_matrix(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu, int tail_order,
                    double* nk, double* gloc, double* scalars, void* ws, size_t ws_bytes,
                    hipStream_t stream) {

@@ -134,6 +134,18 @@ class Context:
                                             _ptr(ws), nws, _stream(self.device)))
         return gloc
 
+    def hybridization(self, lat: Lattice, sig: SelfEnergy, mu: float, gloc: torch.Tensor):
+        """DMFT self-consistency step: (Delta [nw, nc, nc], E_imp [nc, nc]) from
+        G_loc (as returned by gloc_compute / density_matrix at the same mu)."""
+        delta = torch.empty((sig.nw, lat.nc, lat.nc), dtype=torch.complex128, device=self.device)
+        eimp = torch.empty((lat.nc, lat.nc), dtype=torch.complex128, device=self.device)
+        gloc = gloc.contiguous()
+        ws, nws = self._call_ws(lat, sig)
+        ls, ss = lat.struct(), sig.struct()
+        check(self.h, self.lib.dmft_hybridization(self.h, C.byref(ls), C.byref(ss), float(mu), _ptr(gloc), _ptr(delta),
+                                                  _ptr(eimp), _ptr(ws), nws, _stream(self.device)))
+        return delta, eimp
+
     def density_matrix(self, lat: Lattice, sig: SelfEnergy, mu: float, tail_order: int = 2, nk=True,
                        gloc=True, scalars=True):
         """Returns (nk_flat or None, gloc or None, scalars or None); nk_flat holds

@@ -455,3 +455,62 @@ def test_bisection_hits_target():
     assert passes < 60
     # the exact (pole-route) electron count at this mu differs only by the truncation
     assert abs(pole.exact_ntot(lat, sig, mu) - n0) < 5e-3
+
+
+# ----------------------------------------------------------------------------- DMFT self-consistency step
+
+
+def test_hybridization_vanishes_for_decoupled_orbitals():
+    """Correlated orbitals that are k-independent band eigenstates (S selects
+    nc bands whose energies do not depend on k): the lattice is the impurity
+    with no bath, so Delta(i w) = 0 and E_imp = diag(E_c) - V_DC exactly."""
+    rng = np.random.default_rng(7)
+    nk, nb, nc, nw, beta = 5, 6, 2, 32, 8.0
+    ec = np.array([-0.7, 0.4])
+    eps = np.concatenate([np.concatenate([ec, rng.uniform(-3, 3, nb - nc)]) for _ in range(nk)])
+    proj_k = np.zeros((nc, nb), np.complex128)
+    proj_k[0, 0] = np.exp(0.3j)
+    proj_k[1, 1] = np.exp(-1.1j)
+    proj = np.concatenate([proj_k.ravel() for _ in range(nk)])
+    lat = synth.Lattice(nk, nc, np.full(nk, nb, np.int32), eps, np.full(nk, 1.0 / nk), proj)
+    w = wgrid(nw, beta)
+    sigma = np.stack([np.diag([1.5 / (1j * x - 0.8), 0.9 / (1j * x + 0.3)]) + 0.2 for x in w])
+    sig = synth.SelfEnergy(nw, beta, sigma, None, np.array([0.25, 0.1]))
+    delta, eimp = oracle.hybridization(lat, sig, 0.3)
+    assert np.abs(eimp - (np.diag(ec) - np.diag(sig.e_dc))).max() < 1e-14
+    assert np.abs(delta).max() < 1e-12
+
+
+def test_hybridization_first_moment():
+    """i w Delta(i w) -> Delta_1 = sum_k w_k S H^2 S^dag - (sum_k w_k S H S^dag)^2
+    (H = diag(E_k)), independent of Sigma and mu, with an O(1/w) remainder."""
+    wl = small_plain(nk=4, nb=6, nc=2, nw=20000, beta=10.0)
+    lat, sig = wl.lattice, wl.sigma
+    nc = lat.nc
+    m1 = np.zeros((nc, nc), np.complex128)
+    m2 = np.zeros((nc, nc), np.complex128)
+    for k in range(lat.nk):
+        p, e = lat.proj_k(k), lat.eps_k(k)
+        m1 += lat.wk[k] * (p * e) @ p.conj().T
+        m2 += lat.wk[k] * (p * e * e) @ p.conj().T
+    d1 = m2 - m1 @ m1
+    assert np.all(np.linalg.eigvalsh(d1) > 0)  # a bath is present
+    errs = []
+    for n in (1999, 19999):
+        w = (2 * n + 1) * np.pi / sig.beta
+        delta, _ = oracle.hybridization(lat, sig, -0.4, [n])
+        errs.append((w, np.abs(1j * w * delta[0] - d1).max() / np.abs(d1).max()))
+    assert errs[1][1] < 2e-2
+    # the remainder falls as 1/w
+    ratio = (errs[0][1] * errs[0][0]) / (errs[1][1] * errs[1][0])
+    assert 0.8 < ratio < 1.25
+
+
+def test_hybridization_is_causal():
+    """The anti-Hermitian part of Delta(i w_n) is negative semidefinite for w_n > 0."""
+    wl = small_dshell()
+    lat, sig = wl.lattice, wl.sigma
+    delta, _ = oracle.hybridization(lat, sig, 0.2)
+    for d in delta:
+        ah = (d - d.conj().T) / 2j
+        assert np.linalg.eigvalsh(ah).max() < 1e-12 * max(1.0, np.abs(d).max())
