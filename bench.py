@@ -226,6 +226,41 @@ def adjoint_pass(ctx, tune=True):
             "tflops": fl * evals / sec / 1e12, "tflops_dense_count": dense_fl * evals / sec / 1e12}
 
 
+def self_consistency(ctx):
+    """The DMFT self-consistency step (E_imp and Delta from G_loc) on the d-shell
+    and f-shell workloads: microseconds per call from events on the stream it
+    runs on, and the rate of its algorithmic HBM bytes (read G_loc and Sigma,
+    write Delta: 3 Nw Nc^2 complex; read the projectors and band energies
+    once for E_imp)."""
+    import torch
+
+    from paper_1111_2157_amd import synth
+    from paper_1111_2157_amd.dyson import Lattice, SelfEnergy
+
+    out = {}
+    for w in (synth.d_shell(), synth.f_shell()):
+        lat, sig = Lattice.from_host(w.lattice), SelfEnergy.from_host(w.sigma)
+        gl = ctx.gloc_compute(lat, sig, w.mu)
+        ctx.hybridization(lat, sig, w.mu, gl)
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        reps = 50
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ctx.hybridization(lat, sig, w.mu, gl)
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        nk, nc, nw = w.lattice.nk, w.lattice.nc, sig.nw
+        nbs = int(w.lattice.nb.astype(np.int64).sum())
+        nbytes = 3 * nw * nc * nc * 16 + nbs * (nc * 16 + 8) + nk * 8
+        out[w.name] = {"us_per_call": us, "algorithmic_bytes": nbytes, "gbps": nbytes / us / 1e3}
+        del gl
+    return out
+
+
 def mu_search(ctx, tune=True):
     import torch
 
@@ -363,6 +398,7 @@ def main():
             extra[w.name] = {"evals_per_s": ev / sc, "ms_per_pass": sc * 1e3, "kernel": kn,
                              "kernel_tflops": f / (km / max(ln, 1) / 1e3) / 1e12}
         extra["adjoint (N_tot, dN/dmu, dN/dSigma)"] = adjoint_pass(ctx)
+        extra["self-consistency (E_imp, Delta)"] = self_consistency(ctx)
         rec["extra"] = extra
     if args.batched:
         rec["batched"] = batched(ctx)

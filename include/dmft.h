@@ -65,7 +65,7 @@ typedef enum dmft_status {
   DMFT_EHIP = -2,         /* a HIP runtime call failed                          */
   DMFT_ENONFINITE = -3,   /* a non-finite value reached a pivot or a trace      */
   DMFT_ESINGULAR = -4,    /* a Gauss-Jordan pivot vanished (non-causal Sigma)   */
-  DMFT_ENOCONV = -5,      /* mu search: no bracket or max_iter reached          */
+  DMFT_ENOCONV = -5,      /* mu search or eigensolver did not converge          */
   DMFT_EWORKSPACE = -6,   /* workspace NULL, misaligned or smaller than needed  */
   DMFT_EUNSUPPORTED = -7  /* shape outside the compiled kernel variants         */
 } dmft_status;
@@ -268,6 +268,86 @@ int dmft_timing(dmft_handle h, int enable, double* kernel_ms, int64_t* launches)
 
 /* Synchronise `stream` and report the error word kept in ws (then clear it). */
 int dmft_sync_status(dmft_handle h, void* ws, hipStream_t stream);
+
+
+/* ------------------------------------------------------------------------
+ * Pole-expansion route (Sec. 3.3 eqs. pseudo_H_k, rho_LDA+DMFT_componet_final
+ * and fix_mu; Sec. 3.5.2 eqs. DOS and PDOS).  For a self-energy in the pole
+ * form of Sec. 3.2.4 eq. se_pole,
+ *   Sigma(i w) = Sigma_inf + sum_i V_i^dag V_i / (i w - p_i)   (V_i a row over alpha),
+ * the band-window resolvent is the physical block of (i w - H_ps(k))^-1 with
+ *   H_ps(k) = [[ diag(E_k) + P^dag (Sigma_inf - diag(V_DC)) P,  -(V P)^dag ],
+ *              [ -(V P),                                       diag(p)    ]]
+ * (m_k = nb_k + np rows).  With H_ps = Psi diag(E^ps) Psi^dag and u_l the first
+ * nb_k entries of column l of Psi (<phi_n|psi_l>):
+ *   N(k) = sum_l u_l u_l^dag n_F(E^ps_l - mu),  N_tot = sum_k w_k sum_l |u_l|^2 n_F(E^ps_l - mu).
+ * The eigensystems do not depend on mu: one dmft_pole_eig serves every later
+ * density, mu search and DOS at any mu.  Limit: nb_max + np <= 64.
+ *
+ * Per-k outputs use the padded stride mp = nb_max + np; for k with m_k < mp the
+ * entries m_k .. mp-1 are zero (eigenvalue 0 with weight 0, zero vectors).
+ * All calls are stream-ordered; the workspace layout is shared by all of them
+ * (size from dmft_pole_workspace_size with the largest DOS grid used). */
+typedef struct dmft_poles {
+  int32_t np;              /* number of poles, 0 .. 64 - nb_max                    */
+  double beta;             /* inverse temperature (1/eV)                           */
+  const double* p;         /* DEVICE [np] real pole positions p_i                  */
+  const double* v;         /* DEVICE [np][nc] complex pole vectors V_i             */
+  const double* sigma_inf; /* DEVICE [nc][nc] complex Sigma(inf), or NULL for zero */
+  const double* e_dc;      /* DEVICE [nc] real V_DC^alpha                          */
+} dmft_poles;
+
+/* Workspace bytes for the pole-route calls, with DOS grids up to ne_max points. */
+int dmft_pole_workspace_size(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, int ne_max,
+                             size_t* bytes);
+
+/* Eigensystems of H_ps(k) for every k (batched Jacobi, one work-group per k).
+ *   evals: DEVICE [nk][mp] real, ascending per k (ties by index);
+ *   evecs: DEVICE [nk][nb_max][mp] complex, row n = band, column l = eigenvector
+ *          (the physical part u_l; the pole components are not returned);
+ *   wphys: DEVICE [nk][mp] = |u_l|^2;
+ *   worb:  DEVICE [nk][mp][nc] = |P_alpha u_l|^2 (for the PDOS), or NULL.
+ * A k whose iteration does not converge within 30 sweeps raises DMFT_ENOCONV,
+ * non-finite input DMFT_ENONFINITE, in the error word (dmft_sync_status). */
+int dmft_pole_eig(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, double* evals, double* evecs,
+                  double* wphys, double* worb, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Jacobi sweeps each k took in the last dmft_pole_eig on ws (HOST [nk]); synchronises. */
+int dmft_pole_sweeps(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, const void* ws, int32_t* out,
+                     hipStream_t stream);
+
+/* N(k) = sum_l u_l u_l^dag f(E^ps_l - mu) from dmft_pole_eig's output, with
+ * f = n_F (nw_trunc = 0, the paper's exact sum) or, for nw_trunc > 0, the
+ * weight the positive-frequency Matsubara sum truncated at nw_trunc
+ * frequencies with the analytic 1/(iw) and 1/(iw)^2 tails gives one level,
+ *   f(x) = 1/2 - beta x / 4 + (2/beta) sum_{n<nw_trunc} x^3 / (w_n^2 (w_n^2 + x^2)),
+ * which makes the result equal density_matrix's N(k) at nw = nw_trunc.
+ *   nk:      DEVICE, N(k) layout of density_matrix, or NULL;
+ *   scalars: DEVICE [3] = { N_tot, n_corr, <H_KS> } as in density_matrix, or NULL. */
+int dmft_pole_density(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, double mu, int nw_trunc,
+                      const double* evals, const double* evecs, double* nk, double* scalars, void* ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* mu with N_tot(mu) = n_target (Sec. 3.3 eq. fix_mu) from the eigenvalues and
+ * weights alone: the whole search runs in one work-group on the device
+ * (safeguarded Newton with dN/dmu = sum_k w_k sum_l |u_l|^2 beta n_F (1 - n_F),
+ * or bisection), starting at the middle of [mu_lo, mu_hi]; N(mu) is increasing.
+ * Stops at |N - n_target| <= tol_n; DMFT_ENOCONV after max_iter evaluations.
+ * mu_out, passes_out (evaluations of N) and n_out are HOST; synchronises. */
+int dmft_pole_find_mu(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, const double* evals,
+                      const double* wphys, double n_target, double tol_n, int method, double mu_lo, double mu_hi,
+                      int max_iter, double* mu_out, int* passes_out, double* n_out, void* ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/* DOS and PDOS on ne energies e_i = e_min + i (e_max - e_min) / (ne - 1)
+ * (Sec. 3.5.2 eqs. DOS and PDOS, k-sum with the weights w_k), with the
+ * Lorentzian of half-width eta > 0 for the eta -> 0+ limit:
+ *   D(e)   = sum_k w_k sum_l |u_l|^2 (eta/pi) / ((e + mu - E^ps_l)^2 + eta^2),
+ *   D_a(e) = the same with |P_alpha u_l|^2.
+ *   dos:  DEVICE [ne];  pdos: DEVICE [ne][nc] or NULL (needs worb). */
+int dmft_pole_dos(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, const double* evals,
+                  const double* wphys, const double* worb, double mu, double eta, double e_min, double e_max, int ne,
+                  double* dos, double* pdos, void* ws, size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

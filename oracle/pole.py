@@ -10,8 +10,8 @@ enlarged Hermitian "pseudo-Hamiltonian".  Written relative to the chemical
 potential (mu enters the physical block only, because Sigma(i w) does not move
 with mu):
 
-    Htil_k = [[ M1_k,        W_k^dag        ],
-              [ W_k,   diag(p_i) (poles)    ]],
+    Htil_k = [[ M1_k,        -W_k^dag       ],
+              [ -W_k,  diag(p_i) (poles)    ]],
     M1_k   = diag(E_k) - mu + S_k^dag (Sigma_inf - diag(V_DC)) S_k,
     W_k    = rows V_i S_k  (one row per pole),
 
@@ -19,7 +19,9 @@ with mu):
     N_k      = sum_l u_l u_l^dag n_F(lam_l)                    (exact, no frequency sum)
 
 with Htil_k = U diag(lam) U^dag and u_l the physical (band-window) part of
-column l of U.  The eigen-decomposition is numpy's ``eigh`` (a library
+column l of U.  Htil_k is the paper's H_ps(k) shifted by -mu in the physical
+block, with the paper's sign of the coupling (the sign does not change the
+physical block of any function of it).  The eigen-decomposition is numpy's ``eigh`` (a library
 routine).  This route shares nothing with the Matsubara-sum oracle in
 ``dmft_oracle.c``; the tests use it to pin that oracle.
 
@@ -71,8 +73,8 @@ def pseudo_hamiltonian(eps_k, proj_k, sigma_inf, e_dc, poles, mu):
     h[:nb, :nb] = m1
     for i, (p, v) in enumerate(poles):
         row = np.asarray(v, np.complex128) @ proj_k        # V_i S_k : 1 x nb
-        h[nb + i, :nb] = row
-        h[:nb, nb + i] = row.conj()
+        h[nb + i, :nb] = -row
+        h[:nb, nb + i] = -row.conj()
         h[nb + i, nb + i] = p
     return h
 
@@ -109,3 +111,70 @@ def exact_ntot(lat, sig, mu):
         n = exact_density(lat.eps_k(k), lat.proj_k(k), sig.sigma_inf, sig.e_dc, sig.poles, mu, sig.beta)
         tot += lat.wk[k] * np.trace(n).real
     return tot
+
+
+# --------------------------------------------------------------------------
+# Eigensystems, chemical potential and DOS / PDOS of the pole route
+# (Sec. 3.3 eqs. pseudo_H_k and fix_mu; Sec. 3.5.2 eqs. DOS and PDOS).
+
+def pseudo_h(eps_k, proj_k, sigma_inf, e_dc, poles):
+    """The paper's H_ps(k) (no chemical potential): its eigenvalues are E^ps_l(k).
+    Here the pole positions are absolute energies, as eq. rho_LDA+DMFT_componet_final
+    has them (occupations n_F(E^ps - mu)); the Matsubara-axis self-energy at a
+    chemical potential mu then has its poles at p_i - mu, which is what the
+    functions above take."""
+    return pseudo_hamiltonian(eps_k, proj_k, sigma_inf, e_dc, poles, 0.0)
+
+
+def eigensystem(lat, sig, k):
+    """(E^ps ascending [m], u = <phi_n|psi_l> [nb, m], |u_l|^2 [m], |S_alpha u_l|^2 [m, nc]) for one k."""
+    p = lat.proj_k(k)
+    lam, vec = np.linalg.eigh(pseudo_h(lat.eps_k(k), p, sig.sigma_inf, sig.e_dc, sig.poles))
+    u = vec[:p.shape[1], :]
+    return lam, u, (np.abs(u) ** 2).sum(axis=0), (np.abs(p @ u) ** 2).T
+
+
+def pole_ntot_and_slope(eigs, wk, mu, beta):
+    """N_tot(mu) = sum_k w_k sum_l |u_l|^2 n_F(E^ps_l - mu) (eq. fix_mu) and its mu-derivative,
+    from a list of per-k (E^ps, |u|^2)."""
+    n = d = 0.0
+    for (lam, w), wkk in zip(eigs, wk):
+        f = fermi(lam - mu, beta)
+        n += wkk * np.sum(w * f)
+        d += wkk * np.sum(w * beta * f * (1.0 - f))
+    return n, d
+
+
+def pole_find_mu_bisect(lat, sig, n_target, tol, lo, hi, max_iter=200):
+    """Plain bisection on N_tot(mu) of the pole route; returns (mu, evaluations, N)."""
+    eigs = []
+    for k in range(lat.nk):
+        lam, _, w, _ = eigensystem(lat, sig, k)
+        eigs.append((lam, w))
+    mu = n = 0.0
+    for it in range(max_iter):
+        mu = 0.5 * (lo + hi)
+        n, _ = pole_ntot_and_slope(eigs, lat.wk, mu, sig.beta)
+        if abs(n - n_target) <= tol:
+            return mu, it + 1, n
+        if n < n_target:
+            lo = mu
+        else:
+            hi = mu
+    raise RuntimeError("no convergence")
+
+
+def dos(lat, sig, mu, eta, energies):
+    """D(e) and D_alpha(e) (eqs. DOS, PDOS) with the eta -> 0+ limit taken at a finite
+    Lorentzian half-width eta: -(1/pi) Im 1/(x + i eta) = (eta/pi) / (x^2 + eta^2),
+    x = e + mu - E^ps_l, k-sum with the weights w_k.  Returns ([ne], [ne, nc])."""
+    e = np.asarray(energies, np.float64)
+    d = np.zeros(e.shape)
+    pd = np.zeros(e.shape + (int(lat.nc),))
+    for k in range(lat.nk):
+        lam, _, w, wo = eigensystem(lat, sig, k)
+        x = e[:, None] + mu - lam[None, :]
+        lor = (eta / np.pi) / (x * x + eta * eta)
+        d += lat.wk[k] * lor @ w
+        pd += lat.wk[k] * lor @ wo
+    return d, pd

@@ -18,7 +18,8 @@ EXPORTS = [
     "dmft_batched_workspace_size", "dmft_batched_plan", "dmft_batched_pass",
     "dmft_batched_graph_capture", "dmft_batched_graph_launch", "dmft_autotune", "dmft_variants",
     "dmft_set_variant", "dmft_get_variant", "dmft_timing", "dmft_batched_set_form", "dmft_batched_form",
-    "dmft_hybridization",
+    "dmft_hybridization", "dmft_pole_workspace_size", "dmft_pole_eig", "dmft_pole_sweeps",
+    "dmft_pole_density", "dmft_pole_find_mu", "dmft_pole_dos",
     "dmft_sync_status",
 ]
 
@@ -35,6 +36,11 @@ class DmftLattice(C.Structure):
 
 class DmftSigma(C.Structure):
     _fields_ = [("nw", C.c_int32), ("beta", C.c_double), ("sigma", C.c_void_p),
+                ("sigma_inf", C.c_void_p), ("e_dc", C.c_void_p)]
+
+
+class DmftPoles(C.Structure):
+    _fields_ = [("np", C.c_int32), ("beta", C.c_double), ("p", C.c_void_p), ("v", C.c_void_p),
                 ("sigma_inf", C.c_void_p), ("e_dc", C.c_void_p)]
 
 
@@ -57,7 +63,7 @@ def load():
         raise RuntimeError("libdmft.so is not built (run paper_1111_2157_amd.build.build())")
     lib = C.CDLL(LIB_PATH)
     P, I, D, S = C.c_void_p, C.c_int, C.c_double, C.c_size_t
-    lp, sp = C.POINTER(DmftLattice), C.POINTER(DmftSigma)
+    lp, sp, pp = C.POINTER(DmftLattice), C.POINTER(DmftSigma), C.POINTER(DmftPoles)
     sig = {
         "dmft_create": ([C.POINTER(P), I], I),
         "dmft_destroy": ([P], I),
@@ -77,6 +83,13 @@ def load():
         "dmft_batched_graph_launch": ([P, P], I),
         "dmft_autotune": ([P, lp, sp, D, P, S, P, C.c_char_p, S], I),
         "dmft_variants": ([I, I, C.POINTER(I), I], I),
+        "dmft_pole_workspace_size": ([P, lp, pp, I, C.POINTER(S)], I),
+        "dmft_pole_eig": ([P, lp, pp, P, P, P, P, P, S, P], I),
+        "dmft_pole_sweeps": ([P, lp, pp, P, P, P], I),
+        "dmft_pole_density": ([P, lp, pp, D, I, P, P, P, P, P, S, P], I),
+        "dmft_pole_find_mu": ([P, lp, pp, P, P, D, D, I, D, D, I, C.POINTER(D), C.POINTER(I), C.POINTER(D),
+                               P, S, P], I),
+        "dmft_pole_dos": ([P, lp, pp, P, P, P, D, D, D, D, I, P, P, P, S, P], I),
         "dmft_set_variant": ([P, I, I, I], I),
         "dmft_get_variant": ([P, I, I], I),
         "dmft_batched_set_form": ([P, I], I),

@@ -116,9 +116,9 @@ int fail(dmft_handle h, int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(h, DMFT_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-int check_shapes(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig) {
+int check_lattice(dmft_handle h, const dmft_lattice* lat) {
   if (!h) return DMFT_EINVAL;
-  if (!lat || !sig) return fail(h, DMFT_EINVAL, "lattice or sigma is NULL");
+  if (!lat) return fail(h, DMFT_EINVAL, "lattice is NULL");
   if (lat->nk < 1) return fail(h, DMFT_EINVAL, "nk must be >= 1 (got %d)", lat->nk);
   if (lat->nc < 1 || lat->nc > 16) return fail(h, DMFT_EINVAL, "nc must be in 1..16 (got %d)", lat->nc);
   if (lat->nb_max < lat->nc || lat->nb_max > 64)
@@ -129,6 +129,13 @@ int check_shapes(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig) 
       if (lat->nb[k] < lat->nc || lat->nb[k] > lat->nb_max)
         return fail(h, DMFT_EINVAL, "nb[%d] = %d outside nc..nb_max", k, lat->nb[k]);
   }
+  return DMFT_OK;
+}
+
+int check_shapes(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig) {
+  int r = check_lattice(h, lat);
+  if (r) return r;
+  if (!sig) return fail(h, DMFT_EINVAL, "sigma is NULL");
   if (sig->nw < 1) return fail(h, DMFT_EINVAL, "nw must be >= 1 (got %d)", sig->nw);
   if (!(sig->beta > 0) || !std::isfinite(sig->beta))
     return fail(h, DMFT_EINVAL, "beta must be positive and finite");
@@ -691,6 +698,7 @@ int dmft_sync_status(dmft_handle h, void* ws, hipStream_t stream) {
   HIPCHK(h, hipMemcpy(ws, &zero, sizeof(int), hipMemcpyHostToDevice));
   if (err & ERR_NONFINITE) return fail(h, DMFT_ENONFINITE, "device flagged a non-finite value");
   if (err & ERR_SINGULAR) return fail(h, DMFT_ESINGULAR, "device flagged a vanishing pivot");
+  if (err & ERR_NOCONV) return fail(h, DMFT_ENOCONV, "an eigensolver did not converge");
   return DMFT_OK;
 }
 
@@ -1220,6 +1228,239 @@ int dmft_batched_graph_launch(dmft_handle h, hipStream_t stream) {
   if (!h) return DMFT_EINVAL;
   if (!h->gexec) return fail(h, DMFT_EINVAL, "no captured graph");
   HIPCHK(h, hipGraphLaunch(h->gexec, stream));
+  return DMFT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Pole-expansion route (Sec. 3.3 eqs. pseudo_H_k, rho_LDA+DMFT_componet_final,
+// fix_mu; Sec. 3.5.2 eqs. DOS, PDOS).
+
+namespace {
+
+struct PoleLayout {
+  size_t err = 0, res = 0, meta_nb = 0, meta_offb = 0, meta_offn = 0, kscal = 0, sweeps = 0, part = 0, total = 0;
+  int mp = 0;
+  bool ragged = false;
+};
+
+int check_poles(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol) {
+  int r = check_lattice(h, lat);
+  if (r) return r;
+  if (!pol) return fail(h, DMFT_EINVAL, "poles is NULL");
+  if (pol->np < 0) return fail(h, DMFT_EINVAL, "np must be >= 0 (got %d)", pol->np);
+  if (pol->np > 0 && (!pol->p || !pol->v)) return fail(h, DMFT_EINVAL, "p and v must be set when np > 0");
+  if (!pol->e_dc) return fail(h, DMFT_EINVAL, "e_dc must be set");
+  if (!(pol->beta > 0) || !std::isfinite(pol->beta)) return fail(h, DMFT_EINVAL, "beta must be positive and finite");
+  if (lat->nb_max + pol->np > 64)
+    return fail(h, DMFT_EUNSUPPORTED, "nb_max + np = %d exceeds 64", lat->nb_max + pol->np);
+  return DMFT_OK;
+}
+
+void pole_layout(const dmft_lattice* lat, const dmft_poles* pol, int ne, PoleLayout& P) {
+  const int nk = lat->nk;
+  P.mp = lat->nb_max + pol->np;
+  P.ragged = lat->nb != nullptr;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  P.err = take(16);
+  P.res = take(8 * sizeof(double));
+  P.meta_nb = take(sizeof(int32_t) * nk);
+  P.meta_offb = take(sizeof(int64_t) * (nk + 1));
+  P.meta_offn = take(sizeof(int64_t) * (nk + 1));
+  P.kscal = take(sizeof(double) * 3 * nk);
+  P.sweeps = take(sizeof(int32_t) * nk);
+  P.part = take(sizeof(double) * (size_t)pole_dos_kslices(nk, P.mp) * std::max(ne, 1) * (1 + lat->nc));
+  P.total = o;
+}
+
+int pole_prepare(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, int ne, void* ws, size_t ws_bytes,
+                 PoleLayout& P, hipStream_t s) {
+  int r = check_poles(h, lat, pol);
+  if (r) return r;
+  pole_layout(lat, pol, ne, P);
+  if (!ws) return fail(h, DMFT_EWORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % kAlign) return fail(h, DMFT_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < P.total) return fail(h, DMFT_EWORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, P.total);
+  HIPCHK(h, hipSetDevice(h->device));
+  if (!P.ragged) return DMFT_OK;  // uniform windows need no per-k metadata
+  const size_t nk = lat->nk;
+  const size_t need = sizeof(int32_t) * nk + sizeof(int64_t) * (nk + 1) * 2;
+  if (h->staged) HIPCHK(h, hipEventSynchronize(h->staged));
+  if (need > h->pinned_bytes) {
+    if (h->pinned) HIPCHK(h, hipHostFree(h->pinned));
+    h->pinned = nullptr;
+    HIPCHK(h, hipHostMalloc(&h->pinned, need, hipHostMallocDefault));
+    h->pinned_bytes = need;
+  }
+  int32_t* nbv = (int32_t*)h->pinned;
+  int64_t* offb = (int64_t*)(nbv + nk);
+  int64_t* offn = offb + nk + 1;
+  offb[0] = offn[0] = 0;
+  for (size_t k = 0; k < nk; ++k) {
+    nbv[k] = lat->nb[k];
+    offb[k + 1] = offb[k] + lat->nb[k];
+    offn[k + 1] = offn[k] + (int64_t)lat->nb[k] * lat->nb[k];
+  }
+  char* w = (char*)ws;
+  HIPCHK(h, hipMemcpyAsync(w + P.meta_nb, nbv, sizeof(int32_t) * nk, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(w + P.meta_offb, offb, sizeof(int64_t) * (nk + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(w + P.meta_offn, offn, sizeof(int64_t) * (nk + 1), hipMemcpyHostToDevice, s));
+  if (!h->staged) HIPCHK(h, hipEventCreateWithFlags(&h->staged, hipEventDisableTiming));
+  HIPCHK(h, hipEventRecord(h->staged, s));
+  return DMFT_OK;
+}
+
+PoleArgs pole_args(const dmft_lattice* lat, const dmft_poles* pol, const PoleLayout& P, char* w) {
+  PoleArgs a{};
+  a.nk = lat->nk;
+  a.nc = lat->nc;
+  a.np = pol->np;
+  a.mp = P.mp;
+  a.nb_max = lat->nb_max;
+  a.nb_uniform = P.ragged ? 0 : lat->nb_max;
+  a.nb = (const int32_t*)(w + P.meta_nb);
+  a.off_b = (const int64_t*)(w + P.meta_offb);
+  a.off_n = (const int64_t*)(w + P.meta_offn);
+  a.eps = lat->eps;
+  a.wk = lat->wk;
+  a.proj = lat->proj;
+  a.p = pol->p;
+  a.v = pol->v;
+  a.sigma_inf = pol->sigma_inf;
+  a.e_dc = pol->e_dc;
+  a.beta = pol->beta;
+  a.sweeps = (int*)(w + P.sweeps);
+  a.err = (int*)(w + P.err);
+  a.max_sweeps = 30;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dmft_pole_workspace_size(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, int ne_max,
+                             size_t* bytes) {
+  if (!bytes) return fail(h, DMFT_EINVAL, "bytes is NULL");
+  int r = check_poles(h, lat, pol);
+  if (r) return r;
+  if (ne_max < 0) return fail(h, DMFT_EINVAL, "ne_max must be >= 0");
+  PoleLayout P;
+  pole_layout(lat, pol, ne_max, P);
+  *bytes = P.total;
+  return DMFT_OK;
+}
+
+int dmft_pole_eig(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, double* evals, double* evecs,
+                  double* wphys, double* worb, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!evals || !evecs || !wphys) return fail(h, DMFT_EINVAL, "evals, evecs and wphys are required");
+  PoleLayout P;
+  int r = pole_prepare(h, lat, pol, 0, ws, ws_bytes, P, stream);
+  if (r) return r;
+  const size_t lds = pole_eig_lds_bytes(lat->nb_max, pol->np);
+  int lim = 0, optin = 0;
+  HIPCHK(h, hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, h->device) != hipSuccess) optin = 0;
+  lim = std::max(lim, optin);
+  if (lds + 8192 > (size_t)lim)
+    return fail(h, DMFT_EUNSUPPORTED, "eigensolver needs %zu B of LDS, the device allows %d", lds + 8192, lim);
+  PoleArgs a = pole_args(lat, pol, P, (char*)ws);
+  a.evals = evals;
+  a.evecs = evecs;
+  a.wphys = wphys;
+  a.worb = worb;
+  HIPCHK(h, launch_pole_eig(a, lds, stream));
+  return DMFT_OK;
+}
+
+int dmft_pole_sweeps(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, const void* ws, int32_t* out,
+                     hipStream_t stream) {
+  if (!out || !ws) return fail(h, DMFT_EINVAL, "out and ws are required");
+  int r = check_poles(h, lat, pol);
+  if (r) return r;
+  PoleLayout P;
+  pole_layout(lat, pol, 0, P);
+  HIPCHK(h, hipMemcpyAsync(out, (const char*)ws + P.sweeps, sizeof(int32_t) * lat->nk, hipMemcpyDeviceToHost,
+                           stream));
+  HIPCHK(h, hipStreamSynchronize(stream));
+  return DMFT_OK;
+}
+
+int dmft_pole_density(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, double mu, int nw_trunc,
+                      const double* evals, const double* evecs, double* nk, double* scalars, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  if (!evals || !evecs) return fail(h, DMFT_EINVAL, "evals and evecs are required");
+  if (!nk && !scalars) return fail(h, DMFT_EINVAL, "no output requested");
+  if (nw_trunc < 0) return fail(h, DMFT_EINVAL, "nw_trunc must be >= 0");
+  if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
+  PoleLayout P;
+  int r = pole_prepare(h, lat, pol, 0, ws, ws_bytes, P, stream);
+  if (r) return r;
+  char* w = (char*)ws;
+  PoleArgs a = pole_args(lat, pol, P, w);
+  a.evals = const_cast<double*>(evals);
+  a.evecs = const_cast<double*>(evecs);
+  double* kscal = (double*)(w + P.kscal);
+  HIPCHK(h, launch_pole_density(a, mu, nw_trunc, nk, kscal, stream));
+  if (scalars) HIPCHK(h, launch_scalar_reduce_mask(lat->nk, lat->wk, kscal, 3, 0, scalars, stream));
+  return DMFT_OK;
+}
+
+int dmft_pole_find_mu(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, const double* evals,
+                      const double* wphys, double n_target, double tol_n, int method, double mu_lo, double mu_hi,
+                      int max_iter, double* mu_out, int* passes_out, double* n_out, void* ws, size_t ws_bytes,
+                      hipStream_t stream) {
+  if (!evals || !wphys) return fail(h, DMFT_EINVAL, "evals and wphys are required");
+  if (method != DMFT_NEWTON && method != DMFT_BISECT) return fail(h, DMFT_EINVAL, "unknown method");
+  if (!(mu_lo < mu_hi) || !std::isfinite(mu_lo) || !std::isfinite(mu_hi))
+    return fail(h, DMFT_EINVAL, "need finite mu_lo < mu_hi");
+  if (!(tol_n > 0) || max_iter < 1) return fail(h, DMFT_EINVAL, "need tol_n > 0 and max_iter >= 1");
+  if (!std::isfinite(n_target)) return fail(h, DMFT_EINVAL, "n_target is not finite");
+  PoleLayout P;
+  int r = pole_prepare(h, lat, pol, 0, ws, ws_bytes, P, stream);
+  if (r) return r;
+  char* w = (char*)ws;
+  PoleArgs a = pole_args(lat, pol, P, w);
+  a.evals = const_cast<double*>(evals);
+  a.wphys = const_cast<double*>(wphys);
+  double* res = (double*)(w + P.res);
+  HIPCHK(h, launch_pole_find_mu(a, n_target, tol_n, method, mu_lo, mu_hi, 0.5 * (mu_lo + mu_hi), max_iter, res,
+                                stream));
+  double host[4];
+  HIPCHK(h, hipMemcpyAsync(host, res, sizeof host, hipMemcpyDeviceToHost, stream));
+  HIPCHK(h, hipStreamSynchronize(stream));
+  if (mu_out) *mu_out = host[0];
+  if (n_out) *n_out = host[1];
+  if (passes_out) *passes_out = (int)host[2];
+  if (host[3] != 0.0)
+    return fail(h, DMFT_ENOCONV, "no convergence after %d passes (N=%g)", (int)host[2], host[1]);
+  return DMFT_OK;
+}
+
+int dmft_pole_dos(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, const double* evals,
+                  const double* wphys, const double* worb, double mu, double eta, double e_min, double e_max, int ne,
+                  double* dos, double* pdos, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!evals || !wphys || !dos) return fail(h, DMFT_EINVAL, "evals, wphys and dos are required");
+  if (pdos && !worb) return fail(h, DMFT_EINVAL, "pdos needs worb");
+  if (ne < 1) return fail(h, DMFT_EINVAL, "ne must be >= 1");
+  if (!(eta > 0) || !std::isfinite(eta)) return fail(h, DMFT_EINVAL, "eta must be positive and finite");
+  if (!std::isfinite(e_min) || !std::isfinite(e_max) || e_max < e_min || !std::isfinite(mu))
+    return fail(h, DMFT_EINVAL, "need finite mu and e_min <= e_max");
+  PoleLayout P;
+  int r = pole_prepare(h, lat, pol, ne, ws, ws_bytes, P, stream);
+  if (r) return r;
+  char* w = (char*)ws;
+  PoleArgs a = pole_args(lat, pol, P, w);
+  a.evals = const_cast<double*>(evals);
+  a.wphys = const_cast<double*>(wphys);
+  a.worb = pdos ? const_cast<double*>(worb) : nullptr;
+  HIPCHK(h, launch_pole_dos(a, mu, eta, e_min, e_max, ne, (double*)(w + P.part), dos, pdos, stream));
   return DMFT_OK;
 }
 

@@ -19,7 +19,7 @@ enum : int {
 };
 
 // Error bits raised on the device.
-enum : int { ERR_SINGULAR = 1, ERR_NONFINITE = 2 };
+enum : int { ERR_SINGULAR = 1, ERR_NONFINITE = 2, ERR_NOCONV = 4 };
 
 // Everything one launch of the Dyson kernel needs.  Pointers are device
 // pointers.  A launch covers the k-points klist[0 .. nklist) (all with
@@ -122,5 +122,47 @@ hipError_t launch_adj_epilogue(const EpilogueArgs& a, const double* nbar, hipStr
 // out[j] = sum_k weight_j(k) kvals[k][j], weight = w_k, or 1 where bit j of unit_mask is set.
 hipError_t launch_scalar_reduce_mask(int nk, const double* wk, const double* kvals, int nvals, int unit_mask,
                                      double* out, hipStream_t s);
+
+
+// Pole-expansion route (pseudo-Hamiltonian eigensystems).  Pointers are device
+// pointers; mp = nb_max + np is the padded stride of the per-k outputs.
+struct PoleArgs {
+  int nk, nc, np, mp, nb_max;
+  int nb_uniform;              // > 0: every k has this many bands and nb/off_b are unused
+  const int32_t* nb;
+  const int64_t* off_b;
+  const int64_t* off_n;        // [nk+1] prefix sums of nb^2 (N(k) output layout)
+  const double* eps;
+  const double* wk;
+  const double* proj;          // complex [nc][nb_k] per k
+  const double* p;             // [np] pole positions
+  const double* v;             // complex [np][nc] pole vectors
+  const double* sigma_inf;     // complex [nc][nc] or null
+  const double* e_dc;          // [nc]
+  double beta;
+  double* evals;               // [nk][mp]
+  double* evecs;               // complex [nk][nb_max][mp]
+  double* wphys;               // [nk][mp]
+  double* worb;                // [nk][mp][nc] or null
+  int* sweeps;                 // [nk] Jacobi sweeps taken
+  int* err;
+  int max_sweeps;
+};
+// Dynamic LDS bytes of the eigensolver for one k with nb bands.
+size_t pole_eig_lds_bytes(int nb, int np);
+hipError_t launch_pole_eig(const PoleArgs& a, size_t lds_bytes, hipStream_t s);
+// N(k) = sum_l u_l u_l^dag f(lam_l - mu) with f = n_F (nw_trunc = 0) or the
+// truncated Matsubara weight f_Nw; per-k [tr N, tr S N S^dag, sum_v E_v N_vv] into kscal.
+hipError_t launch_pole_density(const PoleArgs& a, double mu, int nw_trunc, double* nk_out, double* kscal,
+                               hipStream_t s);
+// Safeguarded Newton (method 0) or bisection (1) for sum_k w_k sum_l w_l n_F(lam_l - mu) = n_target,
+// one work-group; res = [mu, N(mu), passes, status (0 converged, 1 not)].
+hipError_t launch_pole_find_mu(const PoleArgs& a, double n_target, double tol, int method, double lo, double hi,
+                               double mu0, int max_iter, double* res, hipStream_t s);
+// Lorentzian-broadened DOS and PDOS on ne energies in [e_min, e_max]; part holds
+// [kslices][ne][1 + nc] partial sums.
+int pole_dos_kslices(int nk, int mp);
+hipError_t launch_pole_dos(const PoleArgs& a, double mu, double eta, double e_min, double e_max, int ne,
+                           double* part, double* dos, double* pdos, hipStream_t s);
 
 }  // namespace dmft

@@ -1,0 +1,539 @@
+// Pole-expansion route of the lattice step (Sec. 3.3 eqs. pseudo_H_k,
+// rho_LDA+DMFT_componet_final and fix_mu; Sec. 3.5.2 eqs. DOS and PDOS).
+//
+// When Sigma has the pole form of Sec. 3.2.4 eq. se_pole,
+//     Sigma(i w) = Sigma_inf + sum_i V_i^dag V_i / (i w - p_i),
+// the band-window resolvent is the physical block of (i w - H_ps)^-1 with
+//     H_ps(k) = [[ diag(E_k) + S^dag (Sigma_inf - V_DC) S,  -(V S)^dag ],
+//                [ -(V S),                                  diag(p)    ]]
+// (one row of V S per pole), so with H_ps = Psi diag(E^ps) Psi^dag and
+// u_l = <phi|psi_l> the physical part of eigenvector l:
+//     N(k)   = sum_l u_l u_l^dag n_F(E^ps_l - mu)            (no frequency sum)
+//     N_tot  = sum_k w_k sum_l |u_l|^2 n_F(E^ps_l - mu)
+//     D(e)   = sum_k w_k sum_l |u_l|^2 L(e + mu - E^ps_l),   L(x) = (eta/pi) / (x^2 + eta^2)
+//     D_a(e) = sum_k w_k sum_l |S_a u_l|^2 L(e + mu - E^ps_l).
+// The eigensystems do not depend on mu, so once they are known every further
+// N(mu) costs O(Nk (Nb + np)).
+//
+// Eigensolver: one work-group per k, the matrix and the physical rows of the
+// eigenvectors resident in LDS, cyclic two-sided Jacobi for complex Hermitian
+// matrices in the round-robin (tournament) order: in each of the m-1 steps of
+// a sweep the m/2 disjoint index pairs rotate at once.  A step is one pass
+// over the 2x2 blocks of the matrix, A <- U^dag A U with U block-diagonal in
+// the step's pairing, computed for the upper blocks and mirrored, plus the
+// same column rotation of the eigenvector rows.  A pair rotates when
+// |a_pq| > 1e-17 ||A||_F; the sweep that rotates nothing ends the iteration.
+// The rotation for a pair: with a_pq = r e^{i phi}, zeta = (a_qq - a_pp) / 2r,
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2),
+// sigma = t c e^{i phi}, U = [[c, sigma], [-conj(sigma), c]] zeroes a_pq and
+// moves the diagonal to a_pp - t r, a_qq + t r (the phase-reduced form of the
+// real symmetric 2x2 Jacobi rotation).
+#include <math.h>
+
+#include "dmft_internal.h"
+
+namespace dmft {
+namespace {
+
+constexpr int kEigThreads = 256;
+constexpr int kMaxM = 64;         // largest pseudo-Hamiltonian (nb + np)
+constexpr int kDosThreads = 256;
+constexpr int kDosChunk = 512;    // eigenpairs per slice of the DOS sum
+constexpr int kMaxSlices = 128;
+
+__device__ __forceinline__ double2 pz(double r, double i) { return make_double2(r, i); }
+__device__ __forceinline__ double2 pconj(double2 a) { return pz(a.x, -a.y); }
+__device__ __forceinline__ double2 padd(double2 a, double2 b) { return pz(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 psub(double2 a, double2 b) { return pz(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 pscal(double s, double2 a) { return pz(s * a.x, s * a.y); }
+__device__ __forceinline__ double2 pmul(double2 a, double2 b) {
+  return pz(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 pfma(double2 a, double2 b, double2 c) {  // c + a b
+  return pz(__builtin_fma(a.x, b.x, __builtin_fma(-a.y, b.y, c.x)), __builtin_fma(a.x, b.y, __builtin_fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double pabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// Fixed-order sum over a block of NT threads (NT a power of two).
+template <int NT>
+__device__ __forceinline__ double pole_block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// n_F(x) = 1 / (exp(beta x) + 1) without overflow.
+__device__ __forceinline__ double fermi(double x, double beta) {
+  const double y = beta * x;
+  if (y > 0.0) {
+    const double e = exp(-y);
+    return e / (1.0 + e);
+  }
+  return 1.0 / (1.0 + exp(y));
+}
+
+// Weight of one level at x in the positive-frequency Matsubara sum truncated at
+// nw frequencies with the analytic 1/(iw) and 1/(iw)^2 tails (the density of the
+// frequency-sum route at that nw): 1/2 - beta x / 4 + (2/beta) sum_n x^3 / (w_n^2 (w_n^2 + x^2)).
+__device__ double truncated_weight(double x, double beta, int nw) {
+  const double x2 = x * x, x3 = x2 * x;
+  double s = 0.0;
+  for (int n = 0; n < nw; ++n) {
+    const double w = (double)(2 * n + 1) * M_PI / beta;
+    const double w2 = w * w;
+    s += x3 / (w2 * (w2 + x2));
+  }
+  return 0.5 - beta * x / 4.0 + 2.0 * s / beta;
+}
+
+__device__ __forceinline__ void k_window(const PoleArgs& a, int k, int& nb, int64_t& ob) {
+  nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
+  ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
+}
+
+__global__ void __launch_bounds__(kEigThreads) pole_eig_kernel(PoleArgs a) {
+  extern __shared__ double2 lds[];
+  __shared__ double s_c[kMaxM / 2], s_sr[kMaxM / 2], s_si[kMaxM / 2], s_dp[kMaxM / 2], s_dq[kMaxM / 2];
+  __shared__ int s_p[kMaxM / 2], s_q[kMaxM / 2], s_rot[kMaxM / 2], s_inv[kMaxM];
+  __shared__ double s_lam[kMaxM];
+  __shared__ double red[kEigThreads];
+  const int k = blockIdx.x, t = threadIdx.x;
+  int nb;
+  int64_t ob;
+  k_window(a, k, nb, ob);
+  const int nc = a.nc, np = a.np;
+  const int m = nb + np, mq = m + (m & 1), P = mq >> 1;
+  const int lda = mq + 1, ldv = nb + 1;
+  double2* A = lds;              // mq x lda
+  double2* VT = lds + mq * lda;  // mq x ldv: row l = physical components of eigenvector l
+  const double2* S = reinterpret_cast<const double2*>(a.proj) + ob * nc;
+  const double* E = a.eps + ob;
+  const double2* SI = reinterpret_cast<const double2*>(a.sigma_inf);
+  const double2* V = reinterpret_cast<const double2*>(a.v);
+
+  // T = (Sigma_inf - V_DC) S, nc x nb, staged in the eigenvector area
+  for (int idx = t; idx < nc * nb; idx += kEigThreads) {
+    const int al = idx / nb, j = idx - al * nb;
+    double2 acc = pscal(-a.e_dc[al], S[al * nb + j]);
+    if (SI)
+      for (int be = 0; be < nc; ++be) acc = pfma(SI[al * nc + be], S[be * nb + j], acc);
+    VT[idx] = acc;
+  }
+  __syncthreads();
+  // physical block diag(E) + S^dag T (upper triangle, mirrored)
+  for (int idx = t; idx < nb * nb; idx += kEigThreads) {
+    const int i = idx / nb, j = idx - i * nb;
+    if (i > j) continue;
+    double2 acc = pz(0.0, 0.0);
+    for (int al = 0; al < nc; ++al) acc = pfma(pconj(S[al * nb + i]), VT[al * nb + j], acc);
+    if (i == j) acc = pz(E[i] + acc.x, 0.0);
+    A[i * lda + j] = acc;
+    A[j * lda + i] = pconj(acc);
+  }
+  // coupling rows -V_i S and the pole block diag(p)
+  for (int idx = t; idx < np * nb; idx += kEigThreads) {
+    const int i = idx / nb, j = idx - i * nb;
+    double2 acc = pz(0.0, 0.0);
+    for (int al = 0; al < nc; ++al) acc = pfma(V[i * nc + al], S[al * nb + j], acc);
+    A[(nb + i) * lda + j] = pz(-acc.x, -acc.y);
+    A[j * lda + nb + i] = pz(-acc.x, acc.y);
+  }
+  for (int idx = t; idx < np * np; idx += kEigThreads) {
+    const int i = idx / np, j = idx - i * np;
+    A[(nb + i) * lda + nb + j] = pz(i == j ? a.p[i] : 0.0, 0.0);
+  }
+  if (m & 1)  // odd size: one decoupled zero row/column completes the pairing
+    for (int j = t; j < mq; j += kEigThreads) {
+      A[m * lda + j] = pz(0.0, 0.0);
+      A[j * lda + m] = pz(0.0, 0.0);
+    }
+  __syncthreads();
+  for (int idx = t; idx < mq * nb; idx += kEigThreads) {
+    const int l = idx / nb, i = idx - l * nb;
+    VT[l * ldv + i] = pz(l == i ? 1.0 : 0.0, 0.0);
+  }
+  double ss = 0.0;
+  for (int idx = t; idx < mq * mq; idx += kEigThreads) {
+    const int i = idx / mq, j = idx - i * mq;
+    ss += pabs2(A[i * lda + j]);
+  }
+  const double tol = 1e-17 * sqrt(pole_block_sum<kEigThreads>(ss, red));
+
+  int sweep = 0, converged = 0;
+  while (sweep < a.max_sweeps) {
+    ++sweep;
+    int any = 0;
+    for (int s = 0; s < mq - 1; ++s) {
+      int rot = 0;
+      if (t < P) {
+        // round-robin: position 0 holds index 0, position j >= 1 index 1 + (j - 1 + s) mod (mq - 1);
+        // pair t joins positions t and mq - 1 - t
+        const int p = t == 0 ? 0 : 1 + (t - 1 + s) % (mq - 1);
+        const int q = 1 + (mq - 2 - t + s) % (mq - 1);
+        const double2 apq = A[p * lda + q];
+        const double app = A[p * lda + p].x, aqq = A[q * lda + q].x;
+        const double r = sqrt(pabs2(apq));
+        double c = 1.0, sr = 0.0, si = 0.0, dp = app, dq = aqq;
+        if (r > tol) {
+          const double z = (aqq - app) / (2.0 * r);
+          const double tt = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          const double sn = tt * c / r;
+          sr = sn * apq.x;
+          si = sn * apq.y;
+          dp = app - tt * r;
+          dq = aqq + tt * r;
+          rot = 1;
+        }
+        s_p[t] = p;
+        s_q[t] = q;
+        s_c[t] = c;
+        s_sr[t] = sr;
+        s_si[t] = si;
+        s_dp[t] = dp;
+        s_dq[t] = dq;
+        s_rot[t] = rot;
+      }
+      if (!__syncthreads_or(rot)) continue;
+      any = 1;
+      // A <- U^dag A U, one 2x2 block (pair I rows, pair J columns) per item, I <= J
+      for (int b = t; b < P * P; b += kEigThreads) {
+        const int I = b / P, J = b - I * P;
+        if (I > J || !(s_rot[I] | s_rot[J])) continue;
+        const int p1 = s_p[I], q1 = s_q[I];
+        if (I == J) {
+          A[p1 * lda + p1] = pz(s_dp[I], 0.0);
+          A[q1 * lda + q1] = pz(s_dq[I], 0.0);
+          A[p1 * lda + q1] = pz(0.0, 0.0);
+          A[q1 * lda + p1] = pz(0.0, 0.0);
+          continue;
+        }
+        const int p2 = s_p[J], q2 = s_q[J];
+        const double c1 = s_c[I], c2 = s_c[J];
+        const double2 g1 = pz(s_sr[I], s_si[I]), g2 = pz(s_sr[J], s_si[J]);
+        const double2 x11 = A[p1 * lda + p2], x12 = A[p1 * lda + q2];
+        const double2 x21 = A[q1 * lda + p2], x22 = A[q1 * lda + q2];
+        // rows: p' = c p - g q, q' = conj(g) p + c q
+        const double2 y11 = psub(pscal(c1, x11), pmul(g1, x21));
+        const double2 y12 = psub(pscal(c1, x12), pmul(g1, x22));
+        const double2 y21 = padd(pmul(pconj(g1), x11), pscal(c1, x21));
+        const double2 y22 = padd(pmul(pconj(g1), x12), pscal(c1, x22));
+        // columns: p' = c p - conj(g) q, q' = g p + c q
+        const double2 z11 = psub(pscal(c2, y11), pmul(pconj(g2), y12));
+        const double2 z12 = padd(pmul(g2, y11), pscal(c2, y12));
+        const double2 z21 = psub(pscal(c2, y21), pmul(pconj(g2), y22));
+        const double2 z22 = padd(pmul(g2, y21), pscal(c2, y22));
+        A[p1 * lda + p2] = z11;
+        A[p1 * lda + q2] = z12;
+        A[q1 * lda + p2] = z21;
+        A[q1 * lda + q2] = z22;
+        A[p2 * lda + p1] = pconj(z11);
+        A[q2 * lda + p1] = pconj(z12);
+        A[p2 * lda + q1] = pconj(z21);
+        A[q2 * lda + q1] = pconj(z22);
+      }
+      // eigenvector columns (rows of VT): p' = c p - conj(g) q, q' = g p + c q
+      for (int b = t; b < P * nb; b += kEigThreads) {
+        const int J = b / nb, i = b - J * nb;
+        if (!s_rot[J]) continue;
+        const int p = s_p[J], q = s_q[J];
+        const double c = s_c[J];
+        const double2 g = pz(s_sr[J], s_si[J]);
+        const double2 vp = VT[p * ldv + i], vq = VT[q * ldv + i];
+        VT[p * ldv + i] = psub(pscal(c, vp), pmul(pconj(g), vq));
+        VT[q * ldv + i] = padd(pmul(g, vp), pscal(c, vq));
+      }
+      __syncthreads();
+    }
+    if (!any) {
+      converged = 1;
+      break;
+    }
+  }
+
+  // eigenvalues in ascending order (ties by index)
+  if (t < m) s_lam[t] = A[t * lda + t].x;
+  if (t < kMaxM) s_inv[t] = t < m ? t : 0;
+  __syncthreads();
+  if (t < m) {
+    const double lt = s_lam[t];
+    int r = 0;
+    for (int j = 0; j < m; ++j) {
+      const double lj = s_lam[j];
+      r += (lj < lt) || (lj == lt && j < t);
+    }
+    s_inv[r] = t;  // r <= m - 1
+  }
+  __syncthreads();
+  const int64_t kb = (int64_t)k * a.mp;
+  int nonfinite = !isfinite(tol);
+  for (int r = t; r < a.mp; r += kEigThreads) {
+    double lam = 0.0, w = 0.0;
+    if (r < m) {
+      const int l = s_inv[r];
+      lam = s_lam[l];
+      for (int i = 0; i < nb; ++i) w += pabs2(VT[l * ldv + i]);
+      nonfinite |= !isfinite(lam);
+    }
+    a.evals[kb + r] = lam;
+    a.wphys[kb + r] = w;
+  }
+  double2* U = reinterpret_cast<double2*>(a.evecs) + (int64_t)k * a.nb_max * a.mp;
+  for (int idx = t; idx < a.nb_max * a.mp; idx += kEigThreads) {
+    const int i = idx / a.mp, r = idx - i * a.mp;
+    U[idx] = (i < nb && r < m) ? VT[s_inv[r] * ldv + i] : pz(0.0, 0.0);
+  }
+  if (a.worb)
+    for (int idx = t; idx < a.mp * nc; idx += kEigThreads) {
+      const int r = idx / nc, al = idx - r * nc;
+      double w = 0.0;
+      if (r < m) {
+        const int l = s_inv[r];
+        double2 acc = pz(0.0, 0.0);
+        for (int v = 0; v < nb; ++v) acc = pfma(S[al * nb + v], VT[l * ldv + v], acc);
+        w = pabs2(acc);
+      }
+      a.worb[(kb + r) * nc + al] = w;
+    }
+  if (t == 0) {
+    a.sweeps[k] = sweep;
+    if (!converged) atomicOr(a.err, ERR_NOCONV);
+  }
+  if (nonfinite) atomicOr(a.err, ERR_NONFINITE);
+}
+
+__global__ void __launch_bounds__(256) pole_density_kernel(PoleArgs a, double mu, int nw_trunc, double* nk_out,
+                                                           double* kscal) {
+  extern __shared__ double2 lds[];
+  __shared__ double s_f[kMaxM];
+  __shared__ double red[256];
+  const int k = blockIdx.x, t = threadIdx.x;
+  int nb;
+  int64_t ob;
+  k_window(a, k, nb, ob);
+  const int nc = a.nc, m = nb + a.np, ldu = m + 1;
+  double2* Us = lds;  // nb x ldu
+  const double2* U = reinterpret_cast<const double2*>(a.evecs) + (int64_t)k * a.nb_max * a.mp;
+  for (int idx = t; idx < nb * m; idx += 256) {
+    const int i = idx / m, l = idx - i * m;
+    Us[i * ldu + l] = U[i * a.mp + l];
+  }
+  if (t < m) {
+    const double x = a.evals[(int64_t)k * a.mp + t] - mu;
+    s_f[t] = nw_trunc > 0 ? truncated_weight(x, a.beta, nw_trunc) : fermi(x, a.beta);
+  }
+  __syncthreads();
+  const double* E = a.eps + ob;
+  const int64_t on = a.nb_uniform > 0 ? (int64_t)k * nb * nb : a.off_n[k];
+  double2* N = nk_out ? reinterpret_cast<double2*>(nk_out) + on : nullptr;
+  double tr = 0.0, hks = 0.0, ncor = 0.0;
+  for (int idx = t; idx < nb * nb; idx += 256) {
+    const int i = idx / nb, j = idx - i * nb;
+    double2 acc = pz(0.0, 0.0);
+    for (int l = 0; l < m; ++l) acc = pfma(pscal(s_f[l], Us[i * ldu + l]), pconj(Us[j * ldu + l]), acc);
+    if (N) N[idx] = acc;
+    if (i == j) {
+      tr += acc.x;
+      hks += E[i] * acc.x;
+    }
+  }
+  const double2* S = reinterpret_cast<const double2*>(a.proj) + ob * nc;
+  for (int idx = t; idx < nc * m; idx += 256) {
+    const int al = idx / m, l = idx - al * m;
+    double2 acc = pz(0.0, 0.0);
+    for (int v = 0; v < nb; ++v) acc = pfma(S[al * nb + v], Us[v * ldu + l], acc);
+    ncor += s_f[l] * pabs2(acc);
+  }
+  tr = pole_block_sum<256>(tr, red);
+  ncor = pole_block_sum<256>(ncor, red);
+  hks = pole_block_sum<256>(hks, red);
+  if (t == 0) {
+    kscal[3 * k + 0] = tr;
+    kscal[3 * k + 1] = ncor;
+    kscal[3 * k + 2] = hks;
+  }
+}
+
+__global__ void __launch_bounds__(1024) pole_mu_kernel(PoleArgs a, double n_target, double tol, int method,
+                                                       double lo, double hi, double mu0, int max_iter, double* res) {
+  __shared__ double red[1024];
+  const int64_t total = (int64_t)a.nk * a.mp;
+  auto eval = [&](double mu, double& nv, double& dv) {
+    double sn = 0.0, sd = 0.0;
+    for (int64_t idx = threadIdx.x; idx < total; idx += 1024) {
+      const int kk = (int)(idx / a.mp);
+      const double w = a.wk[kk] * a.wphys[idx];
+      const double f = fermi(a.evals[idx] - mu, a.beta);
+      sn += w * f;
+      sd += w * a.beta * f * (1.0 - f);
+    }
+    nv = pole_block_sum<1024>(sn, red);
+    dv = pole_block_sum<1024>(sd, red);
+  };
+  int passes = 0, converged = 0;
+  double mu = 0.0, nv = 0.0, dv = 0.0;
+  if (method == 1) {
+    for (int it = 0; it < max_iter; ++it) {
+      mu = 0.5 * (lo + hi);
+      eval(mu, nv, dv);
+      ++passes;
+      if (fabs(nv - n_target) <= tol) {
+        converged = 1;
+        break;
+      }
+      if (nv < n_target) lo = mu;
+      else hi = mu;
+    }
+  } else {
+    // Newton kept inside the bracket; bisect when the step leaves it or the
+    // residual does not fall fast enough
+    mu = fmin(fmax(mu0, lo), hi);
+    double prev_res = INFINITY, prev_dx = hi - lo;
+    for (int it = 0; it < max_iter; ++it) {
+      eval(mu, nv, dv);
+      ++passes;
+      const double r = nv - n_target;
+      if (fabs(r) <= tol) {
+        converged = 1;
+        break;
+      }
+      if (r < 0) lo = mu;
+      else hi = mu;
+      double next = 0.0;
+      bool ok = dv > 0.0 && isfinite(dv);
+      if (ok) {
+        next = mu - r / dv;
+        if (!(next > lo && next < hi)) ok = false;
+        if (fabs(r) > 0.5 * prev_res && fabs(next - mu) > 0.5 * prev_dx) ok = false;
+      }
+      if (!ok) next = 0.5 * (lo + hi);
+      prev_dx = fabs(next - mu);
+      prev_res = fabs(r);
+      mu = next;
+    }
+  }
+  if (threadIdx.x == 0) {
+    res[0] = mu;
+    res[1] = nv;
+    res[2] = (double)passes;
+    res[3] = converged ? 0.0 : 1.0;
+  }
+}
+
+__global__ void __launch_bounds__(kDosThreads) pole_dos_kernel(PoleArgs a, double mu, double eta, double e_min,
+                                                               double de, int ne, int nslices, double* part) {
+  __shared__ double s_lam[kDosThreads], s_w[kDosThreads], s_wo[kDosThreads * 16];
+  const int t = threadIdx.x, e = blockIdx.x * kDosThreads + t, slice = blockIdx.y;
+  const int nc = a.nc;
+  const int64_t total = (int64_t)a.nk * a.mp;
+  const int64_t per = (total + nslices - 1) / nslices;
+  const int64_t s0 = (int64_t)slice * per, s1 = s0 + per < total ? s0 + per : total;
+  const double ee = e_min + (double)e * de + mu;
+  const double scale = eta / M_PI, eta2 = eta * eta;
+  double d = 0.0, pd[16];
+#pragma unroll
+  for (int al = 0; al < 16; ++al) pd[al] = 0.0;
+  for (int64_t c0 = s0; c0 < s1; c0 += kDosThreads) {
+    __syncthreads();
+    const int64_t idx = c0 + t;
+    if (idx < s1) {
+      const double w = a.wk[idx / a.mp];
+      s_lam[t] = a.evals[idx];
+      s_w[t] = w * a.wphys[idx];
+      for (int al = 0; al < nc; ++al) s_wo[t * 16 + al] = a.worb ? w * a.worb[idx * nc + al] : 0.0;
+    }
+    __syncthreads();
+    const int cnt = (int)(s1 - c0 < kDosThreads ? s1 - c0 : kDosThreads);
+    for (int j = 0; j < cnt; ++j) {
+      const double x = ee - s_lam[j];
+      const double L = scale / (x * x + eta2);
+      d += s_w[j] * L;
+#pragma unroll
+      for (int al = 0; al < 16; ++al)
+        if (al < nc) pd[al] += s_wo[j * 16 + al] * L;
+    }
+  }
+  if (e < ne) {
+    double* o = part + ((int64_t)slice * ne + e) * (1 + nc);
+    o[0] = d;
+#pragma unroll
+    for (int al = 0; al < 16; ++al)
+      if (al < nc) o[1 + al] = pd[al];
+  }
+}
+
+__global__ void pole_dos_reduce_kernel(int ne, int nc, int nslices, const double* part, double* dos, double* pdos) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)ne * (1 + nc);
+  if (idx >= n) return;
+  double s = 0.0;
+  for (int sl = 0; sl < nslices; ++sl) s += part[(int64_t)sl * n + idx];
+  const int e = (int)(idx / (1 + nc)), c = (int)(idx - (int64_t)e * (1 + nc));
+  if (c == 0) dos[e] = s;
+  else if (pdos) pdos[(int64_t)e * nc + c - 1] = s;
+}
+
+hipError_t allow_lds(const void* fn, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace
+
+size_t pole_eig_lds_bytes(int nb, int np) {
+  const int m = nb + np, mq = m + (m & 1);
+  return (size_t)(mq * (mq + 1) + mq * (nb + 1)) * 16;
+}
+
+hipError_t launch_pole_eig(const PoleArgs& a, size_t lds_bytes, hipStream_t s) {
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(pole_eig_kernel), lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pole_eig_kernel, dim3(a.nk), dim3(kEigThreads), lds_bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pole_density(const PoleArgs& a, double mu, int nw_trunc, double* nk_out, double* kscal,
+                               hipStream_t s) {
+  const size_t lds = (size_t)a.nb_max * (a.nb_max + a.np + 1) * 16;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(pole_density_kernel), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pole_density_kernel, dim3(a.nk), dim3(256), lds, s, a, mu, nw_trunc, nk_out, kscal);
+  return hipGetLastError();
+}
+
+hipError_t launch_pole_find_mu(const PoleArgs& a, double n_target, double tol, int method, double lo, double hi,
+                               double mu0, int max_iter, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(pole_mu_kernel, dim3(1), dim3(1024), 0, s, a, n_target, tol, method, lo, hi, mu0, max_iter,
+                     res);
+  return hipGetLastError();
+}
+
+int pole_dos_kslices(int nk, int mp) {
+  const int64_t total = (int64_t)nk * mp;
+  int64_t n = (total + kDosChunk - 1) / kDosChunk;
+  return (int)(n < 1 ? 1 : n > kMaxSlices ? kMaxSlices : n);
+}
+
+hipError_t launch_pole_dos(const PoleArgs& a, double mu, double eta, double e_min, double e_max, int ne,
+                           double* part, double* dos, double* pdos, hipStream_t s) {
+  const int ns = pole_dos_kslices(a.nk, a.mp);
+  const double de = ne > 1 ? (e_max - e_min) / (double)(ne - 1) : 0.0;
+  hipLaunchKernelGGL(pole_dos_kernel, dim3((ne + kDosThreads - 1) / kDosThreads, ns), dim3(kDosThreads), 0, s, a,
+                     mu, eta, e_min, de, ne, ns, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = (int64_t)ne * (1 + a.nc);
+  hipLaunchKernelGGL(pole_dos_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ne, a.nc, ns, part,
+                     dos, pdos);
+  return hipGetLastError();
+}
+
+}  // namespace dmft

@@ -14,9 +14,10 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BISECT, FORM_AUTO, FORM_DENSE, FORM_LOWRANK, NEWTON, DmftLattice, DmftSigma, check
+from ._lib import BISECT, FORM_AUTO, FORM_DENSE, FORM_LOWRANK, NEWTON, DmftLattice, DmftPoles, DmftSigma, check
 
-__all__ = ["Lattice", "SelfEnergy", "Context", "NEWTON", "BISECT", "FORM_AUTO", "FORM_DENSE", "FORM_LOWRANK"]
+__all__ = ["Lattice", "SelfEnergy", "PoleSelfEnergy", "PoleEigensystem", "Context", "NEWTON", "BISECT",
+           "FORM_AUTO", "FORM_DENSE", "FORM_LOWRANK"]
 
 
 def _stream(device):
@@ -79,6 +80,47 @@ class SelfEnergy:
 
     def struct(self):
         return DmftSigma(self.nw, self.beta, _ptr(self.sigma), _ptr(self.sigma_inf), _ptr(self.e_dc))
+
+
+@dataclass
+class PoleSelfEnergy:
+    """Pole form Sigma(i w) = Sigma_inf + sum_i V_i^dag V_i / (i w - p_i) (device-resident)."""
+
+    np: int
+    beta: float
+    p: Optional[torch.Tensor]           # float64 [np]
+    v: Optional[torch.Tensor]           # complex128 [np, nc]
+    sigma_inf: Optional[torch.Tensor]   # complex128 [nc, nc] or None
+    e_dc: torch.Tensor                  # float64 [nc]
+
+    @classmethod
+    def from_host(cls, sig, device="cuda"):
+        """From an object with ``beta``, ``poles`` (list of (p_i, V_i[nc])),
+        ``sigma_inf`` and ``e_dc``."""
+        poles = list(sig.poles)
+        p = v = None
+        if poles:
+            p = torch.as_tensor(np.array([float(q) for q, _ in poles], np.float64), device=device)
+            v = torch.as_tensor(np.ascontiguousarray(np.stack([np.asarray(x, np.complex128) for _, x in poles])),
+                                device=device)
+        si = None if sig.sigma_inf is None else torch.as_tensor(
+            np.ascontiguousarray(sig.sigma_inf, np.complex128), device=device)
+        return cls(len(poles), float(sig.beta), p, v, si,
+                   torch.as_tensor(np.ascontiguousarray(sig.e_dc, np.float64), device=device))
+
+    def struct(self):
+        return DmftPoles(self.np, self.beta, _ptr(self.p), _ptr(self.v), _ptr(self.sigma_inf), _ptr(self.e_dc))
+
+
+@dataclass
+class PoleEigensystem:
+    """Output of Context.pole_eig: per k, mp = nb_max + np entries (zero past nb_k + np)."""
+
+    mp: int
+    evals: torch.Tensor                 # float64 [nk, mp], ascending per k
+    evecs: torch.Tensor                 # complex128 [nk, nb_max, mp]: <phi_n | psi_l>
+    wphys: torch.Tensor                 # float64 [nk, mp]
+    worb: Optional[torch.Tensor]        # float64 [nk, mp, nc] or None
 
 
 class Context:
@@ -282,6 +324,71 @@ class Context:
     def get_variant(self, kind: int, nbp: int) -> int:
         """The variant code later calls of this kind and padded size use."""
         return int(self.lib.dmft_get_variant(self.h, int(kind), int(nbp)))
+
+    # ------------------------------------------------------------------ pole-expansion route
+    def _pole_ws(self, lat: Lattice, pol: PoleSelfEnergy, ne_max: int = 0):
+        n = C.c_size_t()
+        ls, ps = lat.struct(), pol.struct()
+        check(self.h, self.lib.dmft_pole_workspace_size(self.h, C.byref(ls), C.byref(ps), int(ne_max), C.byref(n)))
+        ws = self.workspace(int(n.value))
+        return ws, C.c_size_t(ws.numel())
+
+    def pole_eig(self, lat: Lattice, pol: PoleSelfEnergy, orb: bool = True) -> PoleEigensystem:
+        mp = lat.nb_max + pol.np
+        dev = self.device
+        es = PoleEigensystem(mp, torch.empty((lat.nk, mp), dtype=torch.float64, device=dev),
+                             torch.empty((lat.nk, lat.nb_max, mp), dtype=torch.complex128, device=dev),
+                             torch.empty((lat.nk, mp), dtype=torch.float64, device=dev),
+                             torch.empty((lat.nk, mp, lat.nc), dtype=torch.float64, device=dev) if orb else None)
+        ws, nws = self._pole_ws(lat, pol)
+        ls, ps = lat.struct(), pol.struct()
+        check(self.h, self.lib.dmft_pole_eig(self.h, C.byref(ls), C.byref(ps), _ptr(es.evals), _ptr(es.evecs),
+                                             _ptr(es.wphys), _ptr(es.worb), _ptr(ws), nws, _stream(self.device)))
+        return es
+
+    def pole_sweeps(self, lat: Lattice, pol: PoleSelfEnergy) -> np.ndarray:
+        out = np.zeros(lat.nk, np.int32)
+        ls, ps = lat.struct(), pol.struct()
+        check(self.h, self.lib.dmft_pole_sweeps(self.h, C.byref(ls), C.byref(ps), _ptr(self._ws),
+                                                out.ctypes.data_as(C.c_void_p), _stream(self.device)))
+        return out
+
+    def pole_density(self, lat: Lattice, pol: PoleSelfEnergy, es: PoleEigensystem, mu: float, nw_trunc: int = 0,
+                     nk=True, scalars=True):
+        """(N(k) of all k concatenated or None, [N_tot, n_corr, <H_KS>] or None)."""
+        nk_t = torch.empty(lat.n_size(), dtype=torch.complex128, device=self.device) if nk else None
+        sc_t = torch.empty(3, dtype=torch.float64, device=self.device) if scalars else None
+        ws, nws = self._pole_ws(lat, pol)
+        ls, ps = lat.struct(), pol.struct()
+        check(self.h, self.lib.dmft_pole_density(self.h, C.byref(ls), C.byref(ps), float(mu), int(nw_trunc),
+                                                 _ptr(es.evals), _ptr(es.evecs), _ptr(nk_t), _ptr(sc_t), _ptr(ws),
+                                                 nws, _stream(self.device)))
+        return nk_t, sc_t
+
+    def pole_find_mu(self, lat: Lattice, pol: PoleSelfEnergy, es: PoleEigensystem, n_target: float,
+                     tol_n: float = 1e-8, method=NEWTON, mu_lo: float = -40.0, mu_hi: float = 40.0,
+                     max_iter: int = 200):
+        """(mu, evaluations of N, N(mu))."""
+        ws, nws = self._pole_ws(lat, pol)
+        ls, ps = lat.struct(), pol.struct()
+        mu, passes, n = C.c_double(), C.c_int(), C.c_double()
+        check(self.h, self.lib.dmft_pole_find_mu(self.h, C.byref(ls), C.byref(ps), _ptr(es.evals), _ptr(es.wphys),
+                                                 float(n_target), float(tol_n), int(method), float(mu_lo),
+                                                 float(mu_hi), int(max_iter), C.byref(mu), C.byref(passes),
+                                                 C.byref(n), _ptr(ws), nws, _stream(self.device)))
+        return mu.value, passes.value, n.value
+
+    def pole_dos(self, lat: Lattice, pol: PoleSelfEnergy, es: PoleEigensystem, mu: float, eta: float,
+                 e_min: float, e_max: float, ne: int, pdos: bool = True):
+        """(D [ne], D_alpha [ne, nc] or None) on e_min .. e_max."""
+        d = torch.empty(ne, dtype=torch.float64, device=self.device)
+        pd = torch.empty((ne, lat.nc), dtype=torch.float64, device=self.device) if pdos else None
+        ws, nws = self._pole_ws(lat, pol, ne)
+        ls, ps = lat.struct(), pol.struct()
+        check(self.h, self.lib.dmft_pole_dos(self.h, C.byref(ls), C.byref(ps), _ptr(es.evals), _ptr(es.wphys),
+                                             _ptr(es.worb), float(mu), float(eta), float(e_min), float(e_max),
+                                             int(ne), _ptr(d), _ptr(pd), _ptr(ws), nws, _stream(self.device)))
+        return d, pd
 
     def timing(self, enable: bool):
         """Returns (summed Dyson-kernel ms, timed launches) recorded so far."""

@@ -5,6 +5,8 @@ independent route (library inverse, the paper's pole-expansion /
 pseudo-Hamiltonian density, closed forms, brute-force two-sided sums, finite
 differences, algebraic identities, symmetries).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -514,3 +516,90 @@ def test_hybridization_is_causal():
     for d in delta:
         ah = (d - d.conj().T) / 2j
         assert np.linalg.eigvalsh(ah).max() < 1e-12 * max(1.0, np.abs(d).max())
+
+
+# ---------------------------------------------------------------------------
+# Pole route: eigensystems, mu and DOS / PDOS (Sec. 3.3 eqs. pseudo_H_k, fix_mu;
+# Sec. 3.5.2 eqs. DOS, PDOS).
+
+def test_pole_two_level_closed_form():
+    """One k whose single band is the correlated orbital and one pole: H_ps is
+    2 x 2, with eigenvalues (a + p)/2 -+ sqrt(((a - p)/2)^2 + |v|^2), physical
+    weights |v|^2 / (|v|^2 + (E - a)^2) and a two-Lorentzian DOS."""
+    eps, e_dc, s_inf, p, v = 0.7, 0.4, 0.15, -1.1, 0.6 * np.exp(0.9j)
+    lat = synth.Lattice(1, 1, np.array([1], np.int32), np.array([eps]), np.array([1.0]),
+                        np.array([np.exp(0.3j)]))
+    sig = synth.SelfEnergy(4, 10.0, np.zeros((4, 1, 1), np.complex128), np.array([[s_inf]], np.complex128),
+                           np.array([e_dc]), [(p, np.array([v]))])
+    a = eps + s_inf - e_dc
+    disc = np.sqrt(((a - p) / 2) ** 2 + abs(v) ** 2)
+    ref = np.array([(a + p) / 2 - disc, (a + p) / 2 + disc])
+    wref = abs(v) ** 2 / (abs(v) ** 2 + (ref - a) ** 2)
+    lam, u, w, wo = pole.eigensystem(lat, sig, 0)
+    assert np.abs(lam - ref).max() < 1e-14
+    assert np.abs(w - wref).max() < 1e-14 and np.abs(wo[:, 0] - wref).max() < 1e-14
+    e = np.linspace(-3.0, 3.0, 13)
+    mu, eta = 0.2, 0.05
+    d, pd = pole.dos(lat, sig, mu, eta, e)
+    dref = sum(wl * (eta / np.pi) / ((e + mu - el) ** 2 + eta ** 2) for el, wl in zip(ref, wref))
+    assert relnorm(d, dref) < 1e-13 and relnorm(pd[:, 0], dref) < 1e-13
+    # occupation: the two levels weighted by n_F
+    n, _ = pole.pole_ntot_and_slope([(lam, w)], lat.wk, mu, sig.beta)
+    assert abs(n - np.sum(wref / (np.exp(sig.beta * (ref - mu)) + 1.0))) < 1e-14
+
+
+def test_pole_dos_without_poles_is_band_sum():
+    """No poles and Sigma_inf = diag(V_DC): H_ps = diag(E), so D and D_alpha are
+    Lorentzian sums over the band energies with weights 1 and |S_alpha,v|^2."""
+    wl = small_dshell()
+    lat, s0 = wl.lattice, wl.sigma
+    sig = synth.SelfEnergy(s0.nw, s0.beta, s0.sigma, np.diag(s0.e_dc).astype(np.complex128), s0.e_dc, [])
+    e = np.linspace(-12.0, 12.0, 41)
+    mu, eta = 0.3, 0.1
+    d, pd = pole.dos(lat, sig, mu, eta, e)
+    dref = np.zeros_like(e)
+    pref = np.zeros((e.size, lat.nc))
+    for k in range(lat.nk):
+        lor = (eta / np.pi) / ((e[:, None] + mu - lat.eps_k(k)[None, :]) ** 2 + eta ** 2)
+        dref += lat.wk[k] * lor.sum(axis=1)
+        pref += lat.wk[k] * lor @ (np.abs(lat.proj_k(k)) ** 2).T
+    assert relnorm(d, dref) < 1e-12 and relnorm(pd, pref) < 1e-12
+
+
+@pytest.mark.parametrize("maker", [small_plain, small_fshell])
+def test_pole_eigensystem_sum_rules(maker):
+    """Completeness of the eigenvectors: sum_l |u_l|^2 = nb_k, sum_l |S_alpha u_l|^2
+    = (S S^dag)_aa = 1 (orthonormal projector rows), sum_l u_l u_l^dag = I."""
+    wl = maker()
+    lat, sig = wl.lattice, wl.sigma
+    for k in range(lat.nk):
+        lam, u, w, wo = pole.eigensystem(lat, sig, k)
+        nb = lat.eps_k(k).size
+        assert lam.size == nb + len(sig.poles)
+        assert abs(w.sum() - nb) < 1e-12
+        assert np.abs(wo.sum(axis=0) - 1.0).max() < 1e-12
+        assert np.abs(u @ u.conj().T - np.eye(nb)).max() < 1e-13
+
+
+def _poles_from(sig, mu):
+    """The pole positions of eq. pseudo_H_k are absolute energies (its eigenvalues
+    enter as n_F(E^ps - mu)); exact_density takes them measured from mu."""
+    return dataclasses.replace(sig, poles=[(p - mu, v) for p, v in sig.poles])
+
+
+def test_pole_find_mu_and_slope():
+    """Bisection on the pole-route N_tot reaches the target (checked through the
+    independent exact_density route), and the analytic slope matches central
+    differences of that route."""
+    wl = small_plain(nk=6, nw=16)
+    lat, sig = wl.lattice, wl.sigma
+    n0 = 6.0
+    mu, it, n = pole.pole_find_mu_bisect(lat, sig, n0, 1e-11, -40.0, 40.0)
+    assert abs(n - n0) <= 1e-11
+    assert abs(pole.exact_ntot(lat, _poles_from(sig, mu), mu) - n0) < 1e-10
+    eigs = [pole.eigensystem(lat, sig, k)[::2] for k in range(lat.nk)]
+    _, d = pole.pole_ntot_and_slope(eigs, lat.wk, mu, sig.beta)
+    h = 1e-5
+    fd = (pole.exact_ntot(lat, _poles_from(sig, mu + h), mu + h)
+          - pole.exact_ntot(lat, _poles_from(sig, mu - h), mu - h)) / (2 * h)
+    assert abs(fd - d) <= 1e-6 * abs(d)
