@@ -33,6 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
+# LDS bandwidth of the chip: 256 CUs x 128 B/clk x 2.4 GHz
+LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
 
 # HBM traffic of the timed kernel per launch, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch, scaled by 2 and 1 as a plain 1 GiB copy reads
@@ -48,7 +50,7 @@ TRAFFIC = {
     },
 }
 TRAFFIC_SOURCES = ["paper_1111_2157_amd/csrc/lowrank_impl.h", "paper_1111_2157_amd/csrc/dyson_impl.h",
-                   "paper_1111_2157_amd/csrc/dmft_internal.h", "paper_1111_2157_amd/csrc/lowrank_32.hip"]
+                   "paper_1111_2157_amd/csrc/lowrank_32.hip"]
 
 
 def measured_traffic(workload, nbp, var):
@@ -103,6 +105,8 @@ def parse():
     ap.add_argument("--no-mu", action="store_true", help="skip the mu-search comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
     ap.add_argument("--extra", action="store_true", help="also time the other workloads")
+    ap.add_argument("--section", choices=["pole", "sc"], default=None,
+                    help="time only the pole route or the self-consistency step and print that record")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (use the default variants)")
     ap.add_argument("--batched", action="store_true", help="also time the batched workload (8 iterates, graph)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -261,6 +265,93 @@ def self_consistency(ctx):
     return out
 
 
+def _event_ms(fn, reps):
+    import torch
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def jacobi_step_cost(nb, npl):
+    """FP64 flops and LDS bytes of one Jacobi step (every pair rotating) for one
+    k with nb bands and npl poles: m/2 (m/2 - 1)/2 off-diagonal 2x2 blocks
+    (8 complex scale-and-rotate updates of 10 flops, 4 reads and 8 writes),
+    m/2 diagonal blocks (4 writes) and m/2 nb eigenvector pairs (2 updates,
+    2 reads, 2 writes); m = nb + npl rounded up to even."""
+    m = nb + npl
+    m += m & 1
+    p = m // 2
+    flops = p * (p - 1) // 2 * 80 + p * nb * 20
+    lds = (p * (p - 1) // 2 * 12 + p * 4 + p * nb * 4) * 16
+    return flops, lds, m
+
+
+def pole_route(ctx, tune=True):
+    """The pole-expansion route on the d-shell and f-shell workloads: batched
+    pseudo-Hamiltonian eigensystems, exact N(k), the mu search from the
+    eigenvalues (Newton and bisection) and a 1001-point DOS/PDOS; the
+    eigensolver's rate against the LDS and FP64 peaks (work counted per Jacobi
+    step actually taken), and the route's time against one frequency-sum
+    density pass of the same workload."""
+    import dataclasses
+
+    import torch
+
+    from paper_1111_2157_amd import synth
+    from paper_1111_2157_amd.dyson import BISECT, NEWTON, Lattice, PoleSelfEnergy, SelfEnergy
+
+    out = {}
+    for w in (synth.d_shell(), synth.f_shell()):
+        sig = w.sigma
+        sig_abs = dataclasses.replace(sig, poles=[(p + w.mu, v) for p, v in sig.poles])
+        lat, pol = Lattice.from_host(w.lattice), PoleSelfEnergy.from_host(sig_abs)
+        es = ctx.pole_eig(lat, pol)
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        t_eig = _event_ms(lambda: ctx.pole_eig(lat, pol), 5)
+        ctx.sync_status()
+        sweeps = ctx.pole_sweeps(lat, pol)
+        nb, npl = w.lattice.nb_max, len(sig.poles)
+        fl, lb, m = jacobi_step_cost(nb, npl)
+        steps = int(sweeps.sum()) * (m - 1)
+        t_den = _event_ms(lambda: ctx.pole_density(lat, pol, es, w.mu, 0), 10)
+        _, sc = ctx.pole_density(lat, pol, es, w.mu, 0)
+        n0 = float(sc[0]) + 0.5
+        t0 = time.perf_counter()
+        mu_n, pn, _ = ctx.pole_find_mu(lat, pol, es, n0, 1e-8, NEWTON)
+        t_newton = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        mu_b, pb, _ = ctx.pole_find_mu(lat, pol, es, n0, 1e-8, BISECT)
+        t_bisect = time.perf_counter() - t0
+        t_dos = _event_ms(lambda: ctx.pole_dos(lat, pol, es, w.mu, 0.05, -12.0, 12.0, 1001), 3)
+        ctx.sync_status()
+        s2 = SelfEnergy.from_host(sig)
+        if tune:
+            ctx.autotune(lat, s2, w.mu)
+        t_mats, _, _ = time_density(ctx, lat, s2, w.mu, 3, 1)
+        lds_tbps = steps * lb / (t_eig * 1e-3) / 1e12
+        tflops = steps * fl / (t_eig * 1e-3) / 1e12
+        out[w.name] = {
+            "m": nb + npl, "eig_ms": t_eig, "sweeps_mean": float(sweeps.mean()), "sweeps_max": int(sweeps.max()),
+            "density_exact_ms": t_den, "eig_plus_density_ms": t_eig + t_den,
+            "frequency_sum_density_ms": t_mats * 1e3,
+            "speedup_vs_frequency_sum": t_mats * 1e3 / (t_eig + t_den),
+            "find_mu_newton": {"mu": mu_n, "passes": pn, "seconds": t_newton},
+            "find_mu_bisect": {"mu": mu_b, "passes": pb, "seconds": t_bisect},
+            "dos_1001_points_ms": t_dos,
+            "eig_roofline": {"bound": "lds", "achieved": lds_tbps, "peak": LDS_PEAK_TBPS, "unit": "TB/s",
+                             "frac": lds_tbps / LDS_PEAK_TBPS, "fp64_tflops": tflops,
+                             "fp64_frac": tflops / FP64_PEAK_TFLOPS,
+                             "lds_bytes_per_step": lb, "flop_per_step": fl, "steps": steps},
+        }
+    return out
+
+
 def mu_search(ctx, tune=True):
     import torch
 
@@ -333,6 +424,13 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.section:
+        from paper_1111_2157_amd.dyson import Context
+
+        ctx = Context(0)
+        rec = pole_route(ctx, not args.no_tune) if args.section == "pole" else self_consistency(ctx)
+        print(json.dumps({"section": args.section, "result": rec}), flush=True)
+        return
     import torch
 
     from paper_1111_2157_amd import synth
@@ -399,6 +497,7 @@ def main():
                              "kernel_tflops": f / (km / max(ln, 1) / 1e3) / 1e12}
         extra["adjoint (N_tot, dN/dmu, dN/dSigma)"] = adjoint_pass(ctx)
         extra["self-consistency (E_imp, Delta)"] = self_consistency(ctx)
+        extra["pole route"] = pole_route(ctx, not args.no_tune)
         rec["extra"] = extra
     if args.batched:
         rec["batched"] = batched(ctx)

@@ -58,6 +58,7 @@ struct Layout {
   int kind = KIND_DENSITY;
   Tile tile;
   size_t tune_a = 0, tune_b = 0;  // autotuner scratch: two result copies
+  size_t sc_part = 0;             // partial sums of the impurity level
 };
 
 }  // namespace
@@ -243,6 +244,7 @@ int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, L
   L.ktrace = take((size_t)nk * 2 * sizeof(double));
   L.tune_a = take((size_t)nw * lat->nc * lat->nc * 16 + 64);
   L.tune_b = take((size_t)nw * lat->nc * lat->nc * 16 + 64);
+  L.sc_part = take((size_t)kScParts * lat->nc * lat->nc * 16);
   L.total = o;
   return DMFT_OK;
 }
@@ -533,14 +535,24 @@ int dmft_hybridization(dmft_handle h, const dmft_lattice* lat, const dmft_sigma*
   if (!gloc || !delta) return fail(h, DMFT_EINVAL, "gloc and delta are required");
   if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
   Layout L;
-  int r = prepare(h, lat, sig, ws, ws_bytes, L, KIND_DENSITY, stream);
+  int r = check_shapes(h, lat, sig);
   if (r) return r;
+  r = make_layout(h, lat, sig, L, KIND_DENSITY);
+  if (r) return r;
+  r = check_ws(h, L, ws, ws_bytes);
+  if (r) return r;
+  HIPCHK(h, hipSetDevice(h->device));
+  // uniform windows: the kernels take nb from the argument and read no per-k metadata
+  if (L.ragged) {
+    r = upload_meta(h, L, (char*)ws, stream, false);
+    if (r) return r;
+  }
   char* w = (char*)ws;
   double* eimp = e_imp ? e_imp : (double*)(w + L.tune_a);  // scratch when not requested
   HIPCHK(h, launch_self_consistency(lat->nk, lat->nc, sig->nw, L.ragged ? 0 : lat->nb_max,
                                     (const int32_t*)(w + L.meta_nb), (const int64_t*)(w + L.meta_offb), lat->eps,
                                     lat->wk, lat->proj, sig->e_dc, sig->beta, mu, gloc, sig->sigma, eimp, delta,
-                                    (int*)(w + L.err), stream));
+                                    (double*)(w + L.sc_part), (int*)(w + L.err), stream));
   return DMFT_OK;
 }
 

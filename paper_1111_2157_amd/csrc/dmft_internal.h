@@ -112,11 +112,14 @@ hipError_t launch_batched(const void* items, int n_big, int n_small, const Dyson
 hipError_t launch_batched_lr(const void* items, int n_items, const DysonArgs* args, int* counters, int n_workgroups,
                              hipStream_t s);
 hipError_t launch_copy_doubles(const double* src, double* dst, int n, hipStream_t s);
-// DMFT self-consistency step: E_imp (device [nc][nc] complex) and Delta (device [nw][nc][nc]).
+// DMFT self-consistency step: E_imp (device [nc][nc] complex) and Delta (device [nw][nc][nc]);
+// part holds self_consistency_parts(nk) x nc x nc complex partials of E_imp.
+constexpr int kScParts = 256;
+int self_consistency_parts(int nk);
 hipError_t launch_self_consistency(int nk, int nc, int nw, int nb_uniform, const int32_t* nb, const int64_t* off_b,
                                    const double* eps, const double* wk, const double* proj, const double* e_dc,
                                    double beta, double mu, const double* gloc, const double* sigma, double* e_imp,
-                                   double* delta, int* err, hipStream_t s);
+                                   double* delta, double* part, int* err, hipStream_t s);
 // Per-k [tr N, d tr N/dmu, mubar_k] from the adjoint partials (tail terms included).
 hipError_t launch_adj_epilogue(const EpilogueArgs& a, const double* nbar, hipStream_t s);
 // out[j] = sum_k weight_j(k) kvals[k][j], weight = w_k, or 1 where bit j of unit_mask is set.

@@ -94,6 +94,13 @@ __device__ double truncated_weight(double x, double beta, int nw) {
   return 0.5 - beta * x / 4.0 + 2.0 * s / beta;
 }
 
+// One pair's rotation of a Jacobi step, read by the update pass as two 16-byte words.
+struct __align__(16) JRot {
+  double c, sr, si;  // U = [[c, g], [-conj(g), c]], g = sr + i si
+  int pq;            // p | q << 16
+  int rot;           // 0: identity (the pair is already diagonal)
+};
+
 __device__ __forceinline__ void k_window(const PoleArgs& a, int k, int& nb, int64_t& ob) {
   nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
   ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
@@ -101,8 +108,9 @@ __device__ __forceinline__ void k_window(const PoleArgs& a, int k, int& nb, int6
 
 __global__ void __launch_bounds__(kEigThreads) pole_eig_kernel(PoleArgs a) {
   extern __shared__ double2 lds[];
-  __shared__ double s_c[kMaxM / 2], s_sr[kMaxM / 2], s_si[kMaxM / 2], s_dp[kMaxM / 2], s_dq[kMaxM / 2];
-  __shared__ int s_p[kMaxM / 2], s_q[kMaxM / 2], s_rot[kMaxM / 2], s_inv[kMaxM];
+  __shared__ JRot s_r[kMaxM / 2];
+  __shared__ double s_dp[kMaxM / 2], s_dq[kMaxM / 2];
+  __shared__ int s_inv[kMaxM], s_any[2];
   __shared__ double s_lam[kMaxM];
   __shared__ double red[kEigThreads];
   const int k = blockIdx.x, t = threadIdx.x;
@@ -167,89 +175,114 @@ __global__ void __launch_bounds__(kEigThreads) pole_eig_kernel(PoleArgs a) {
   }
   const double tol = 1e-17 * sqrt(pole_block_sum<kEigThreads>(ss, red));
 
+  // item walks of the two update passes without divisions: item b = t + 256 j
+  // is (b / P, b % P) in the block pass and (b / nb, b % nb) in the vector pass
+  const int bI0 = t / P, bJ0 = t - bI0 * P, bdI = kEigThreads / P, bdJ = kEigThreads - bdI * P;
+  const int vJ0 = t / nb, vi0 = t - vJ0 * nb, vdJ = kEigThreads / nb, vdi = kEigThreads - vdJ * nb;
   int sweep = 0, converged = 0;
   while (sweep < a.max_sweeps) {
     ++sweep;
     int any = 0;
     for (int s = 0; s < mq - 1; ++s) {
-      int rot = 0;
-      if (t < P) {
-        // round-robin: position 0 holds index 0, position j >= 1 index 1 + (j - 1 + s) mod (mq - 1);
-        // pair t joins positions t and mq - 1 - t
-        const int p = t == 0 ? 0 : 1 + (t - 1 + s) % (mq - 1);
-        const int q = 1 + (mq - 2 - t + s) % (mq - 1);
-        const double2 apq = A[p * lda + q];
-        const double app = A[p * lda + p].x, aqq = A[q * lda + q].x;
-        const double r = sqrt(pabs2(apq));
-        double c = 1.0, sr = 0.0, si = 0.0, dp = app, dq = aqq;
-        if (r > tol) {
-          const double z = (aqq - app) / (2.0 * r);
-          const double tt = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          const double sn = tt * c / r;
-          sr = sn * apq.x;
-          si = sn * apq.y;
-          dp = app - tt * r;
-          dq = aqq + tt * r;
-          rot = 1;
+      // rotation parameters: pairs live in wave 0 (P <= 32); its ballot tells
+      // every wave whether the step rotates (flag double-buffered by step parity,
+      // so a wave still reading step s never sees step s + 1's flag)
+      if (t < 64) {
+        int rot = 0;
+        if (t < P) {
+          // round-robin: position 0 holds index 0, position j >= 1 index 1 + (j - 1 + s) mod (mq - 1);
+          // pair t joins positions t and mq - 1 - t
+          const int p = t == 0 ? 0 : 1 + (t - 1 + s) % (mq - 1);
+          const int q = 1 + (mq - 2 - t + s) % (mq - 1);
+          const double2 apq = A[p * lda + q];
+          const double app = A[p * lda + p].x, aqq = A[q * lda + q].x;
+          const double r = sqrt(pabs2(apq));
+          JRot R;
+          R.c = 1.0;
+          R.sr = R.si = 0.0;
+          R.pq = p | (q << 16);
+          if (r > tol) {
+            const double ir = 1.0 / r;
+            const double z = 0.5 * (aqq - app) * ir;
+            const double tt = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+            R.c = 1.0 / sqrt(1.0 + tt * tt);
+            const double sn = tt * R.c * ir;
+            R.sr = sn * apq.x;
+            R.si = sn * apq.y;
+            s_dp[t] = app - tt * r;
+            s_dq[t] = aqq + tt * r;
+            rot = 1;
+          }
+          R.rot = rot;
+          s_r[t] = R;
         }
-        s_p[t] = p;
-        s_q[t] = q;
-        s_c[t] = c;
-        s_sr[t] = sr;
-        s_si[t] = si;
-        s_dp[t] = dp;
-        s_dq[t] = dq;
-        s_rot[t] = rot;
+        const unsigned long long bal = __ballot(rot);
+        if (t == 0) s_any[s & 1] = bal != 0ull;
       }
-      if (!__syncthreads_or(rot)) continue;
+      __syncthreads();
+      if (!s_any[s & 1]) continue;
       any = 1;
       // A <- U^dag A U, one 2x2 block (pair I rows, pair J columns) per item, I <= J
-      for (int b = t; b < P * P; b += kEigThreads) {
-        const int I = b / P, J = b - I * P;
-        if (I > J || !(s_rot[I] | s_rot[J])) continue;
-        const int p1 = s_p[I], q1 = s_q[I];
-        if (I == J) {
-          A[p1 * lda + p1] = pz(s_dp[I], 0.0);
-          A[q1 * lda + q1] = pz(s_dq[I], 0.0);
-          A[p1 * lda + q1] = pz(0.0, 0.0);
-          A[q1 * lda + p1] = pz(0.0, 0.0);
-          continue;
+      for (int I = bI0, J = bJ0; I < P;) {
+        if (I <= J) {
+          const JRot R1 = s_r[I], R2 = s_r[J];
+          if (R1.rot | R2.rot) {
+            const int p1 = R1.pq & 0xffff, q1 = R1.pq >> 16;
+            if (I == J) {
+              A[p1 * lda + p1] = pz(s_dp[I], 0.0);
+              A[q1 * lda + q1] = pz(s_dq[I], 0.0);
+              A[p1 * lda + q1] = pz(0.0, 0.0);
+              A[q1 * lda + p1] = pz(0.0, 0.0);
+            } else {
+              const int p2 = R2.pq & 0xffff, q2 = R2.pq >> 16;
+              const double c1 = R1.c, c2 = R2.c;
+              const double2 g1 = pz(R1.sr, R1.si), g2 = pz(R2.sr, R2.si);
+              const double2 x11 = A[p1 * lda + p2], x12 = A[p1 * lda + q2];
+              const double2 x21 = A[q1 * lda + p2], x22 = A[q1 * lda + q2];
+              // rows: p' = c p - g q, q' = conj(g) p + c q
+              const double2 y11 = psub(pscal(c1, x11), pmul(g1, x21));
+              const double2 y12 = psub(pscal(c1, x12), pmul(g1, x22));
+              const double2 y21 = padd(pmul(pconj(g1), x11), pscal(c1, x21));
+              const double2 y22 = padd(pmul(pconj(g1), x12), pscal(c1, x22));
+              // columns: p' = c p - conj(g) q, q' = g p + c q
+              const double2 z11 = psub(pscal(c2, y11), pmul(pconj(g2), y12));
+              const double2 z12 = padd(pmul(g2, y11), pscal(c2, y12));
+              const double2 z21 = psub(pscal(c2, y21), pmul(pconj(g2), y22));
+              const double2 z22 = padd(pmul(g2, y21), pscal(c2, y22));
+              A[p1 * lda + p2] = z11;
+              A[p1 * lda + q2] = z12;
+              A[q1 * lda + p2] = z21;
+              A[q1 * lda + q2] = z22;
+              A[p2 * lda + p1] = pconj(z11);
+              A[q2 * lda + p1] = pconj(z12);
+              A[p2 * lda + q1] = pconj(z21);
+              A[q2 * lda + q1] = pconj(z22);
+            }
+          }
         }
-        const int p2 = s_p[J], q2 = s_q[J];
-        const double c1 = s_c[I], c2 = s_c[J];
-        const double2 g1 = pz(s_sr[I], s_si[I]), g2 = pz(s_sr[J], s_si[J]);
-        const double2 x11 = A[p1 * lda + p2], x12 = A[p1 * lda + q2];
-        const double2 x21 = A[q1 * lda + p2], x22 = A[q1 * lda + q2];
-        // rows: p' = c p - g q, q' = conj(g) p + c q
-        const double2 y11 = psub(pscal(c1, x11), pmul(g1, x21));
-        const double2 y12 = psub(pscal(c1, x12), pmul(g1, x22));
-        const double2 y21 = padd(pmul(pconj(g1), x11), pscal(c1, x21));
-        const double2 y22 = padd(pmul(pconj(g1), x12), pscal(c1, x22));
-        // columns: p' = c p - conj(g) q, q' = g p + c q
-        const double2 z11 = psub(pscal(c2, y11), pmul(pconj(g2), y12));
-        const double2 z12 = padd(pmul(g2, y11), pscal(c2, y12));
-        const double2 z21 = psub(pscal(c2, y21), pmul(pconj(g2), y22));
-        const double2 z22 = padd(pmul(g2, y21), pscal(c2, y22));
-        A[p1 * lda + p2] = z11;
-        A[p1 * lda + q2] = z12;
-        A[q1 * lda + p2] = z21;
-        A[q1 * lda + q2] = z22;
-        A[p2 * lda + p1] = pconj(z11);
-        A[q2 * lda + p1] = pconj(z12);
-        A[p2 * lda + q1] = pconj(z21);
-        A[q2 * lda + q1] = pconj(z22);
+        I += bdI;
+        J += bdJ;
+        if (J >= P) {
+          J -= P;
+          ++I;
+        }
       }
       // eigenvector columns (rows of VT): p' = c p - conj(g) q, q' = g p + c q
-      for (int b = t; b < P * nb; b += kEigThreads) {
-        const int J = b / nb, i = b - J * nb;
-        if (!s_rot[J]) continue;
-        const int p = s_p[J], q = s_q[J];
-        const double c = s_c[J];
-        const double2 g = pz(s_sr[J], s_si[J]);
-        const double2 vp = VT[p * ldv + i], vq = VT[q * ldv + i];
-        VT[p * ldv + i] = psub(pscal(c, vp), pmul(pconj(g), vq));
-        VT[q * ldv + i] = padd(pmul(g, vp), pscal(c, vq));
+      for (int J = vJ0, i = vi0; J < P;) {
+        const JRot R = s_r[J];
+        if (R.rot) {
+          const int p = R.pq & 0xffff, q = R.pq >> 16;
+          const double2 g = pz(R.sr, R.si);
+          const double2 vp = VT[p * ldv + i], vq = VT[q * ldv + i];
+          VT[p * ldv + i] = psub(pscal(R.c, vp), pmul(pconj(g), vq));
+          VT[q * ldv + i] = padd(pmul(g, vp), pscal(R.c, vq));
+        }
+        J += vdJ;
+        i += vdi;
+        if (i >= nb) {
+          i -= nb;
+          ++J;
+        }
       }
       __syncthreads();
     }

@@ -3,7 +3,8 @@
 //     E_imp        = sum_k w_k S_k diag(E_k) S_k^dag - diag(V_DC)
 //     Delta(i w_n) = i w_n + mu - E_imp - Sigma(i w_n) - G_loc(i w_n)^-1 .
 //
-// E_imp: one work-group per (alpha, beta) entry, a fixed-order sum over k.
+// E_imp: per-block partial sums over strided k (projectors staged in LDS, one
+// thread per (alpha, beta)), then a fixed-order sum of the partials.
 // Delta: one wavefront per four frequencies; lane 16 g + i holds row i of
 // G_loc(i w_{4b+g}) and the inversion is the row-layout Gauss-Jordan sweep of
 // the low-rank kernel (no pivoting: the anti-Hermitian part of G_loc(i w_n),
@@ -13,48 +14,56 @@
 
 namespace dmft {
 
-// Fixed-order sum of a block's values (blockDim.x = 256).
-__device__ __forceinline__ double sc_block_sum(double v, double* red) {
+// E_imp partials: block b sums k = b, b + G, ... (G = gridDim.x); each k's
+// projector and band energies are staged in LDS and thread (alpha, beta) adds
+// w_k sum_r S[alpha][r] E_r conj(S[beta][r]).  One pass over the projectors.
+__global__ void __launch_bounds__(256) eimp_partial_kernel(int nk, int nc, int nb_uniform, const int32_t* nb,
+                                                           const int64_t* off_b, const double* eps,
+                                                           const double* wk, const double* proj, double* part) {
+  __shared__ double2 sS[16 * 64];
+  __shared__ double sE[64];
   const int t = threadIdx.x;
-  red[t] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
-}
-
-__global__ void __launch_bounds__(256) eimp_kernel(int nk, int nc, int nb_uniform, const int32_t* nb,
-                                                   const int64_t* off_b, const double* eps, const double* wk,
-                                                   const double* proj, const double* e_dc, double* e_imp) {
-  __shared__ double red[256];
-  const int al = blockIdx.x / nc, be = blockIdx.x % nc;
+  const int al = t / nc, be = t - al * nc;
+  const bool owner = t < nc * nc;
   const double2* P = reinterpret_cast<const double2*>(proj);
   double sr = 0.0, si = 0.0;
-  for (int k = threadIdx.x; k < nk; k += blockDim.x) {
+  for (int k = blockIdx.x; k < nk; k += gridDim.x) {
     const int n = nb_uniform > 0 ? nb_uniform : nb[k];
     const int64_t ob = nb_uniform > 0 ? (int64_t)k * n : off_b[k];
-    const double2* pk = P + ob * nc;
-    double ar = 0.0, ai = 0.0;
-    for (int r = 0; r < n; ++r) {
-      const double2 x = pk[al * n + r], y = pk[be * n + r];
-      const double e = eps[ob + r];
-      // S[al][r] E_r conj(S[be][r])
-      ar += e * (x.x * y.x + x.y * y.y);
-      ai += e * (x.y * y.x - x.x * y.y);
+    __syncthreads();
+    for (int idx = t; idx < nc * n; idx += 256) sS[idx] = P[ob * nc + idx];
+    for (int r = t; r < n; r += 256) sE[r] = eps[ob + r];
+    __syncthreads();
+    if (owner) {
+      double ar = 0.0, ai = 0.0;
+      for (int r = 0; r < n; ++r) {
+        const double2 x = sS[al * n + r], y = sS[be * n + r];
+        const double e = sE[r];
+        ar += e * (x.x * y.x + x.y * y.y);
+        ai += e * (x.y * y.x - x.x * y.y);
+      }
+      sr += wk[k] * ar;
+      si += wk[k] * ai;
     }
-    sr += wk[k] * ar;
-    si += wk[k] * ai;
   }
-  sr = sc_block_sum(sr, red);
-  si = sc_block_sum(si, red);
-  if (threadIdx.x == 0) {
-    if (al == be) sr -= e_dc[al];
-    reinterpret_cast<double2*>(e_imp)[al * nc + be] = make_double2(sr, si);
+  if (owner) reinterpret_cast<double2*>(part)[(int64_t)blockIdx.x * nc * nc + t] = make_double2(sr, si);
+}
+
+// E_imp = (fixed-order sum of the partials) - diag(V_DC).
+__global__ void __launch_bounds__(256) eimp_reduce_kernel(int nc, int nparts, const double* part, const double* e_dc,
+                                                          double* e_imp) {
+  const int t = threadIdx.x;
+  if (t >= nc * nc) return;
+  const double2* q = reinterpret_cast<const double2*>(part);
+  double sr = 0.0, si = 0.0;
+  for (int b = 0; b < nparts; ++b) {
+    const double2 v = q[(int64_t)b * nc * nc + t];
+    sr += v.x;
+    si += v.y;
   }
+  const int al = t / nc, be = t - al * nc;
+  if (al == be) sr -= e_dc[al];
+  reinterpret_cast<double2*>(e_imp)[t] = make_double2(sr, si);
 }
 
 __global__ void __launch_bounds__(64) delta_kernel(int nw, int nc, double beta, double mu, const double* gloc,
@@ -98,13 +107,19 @@ __global__ void __launch_bounds__(64) delta_kernel(int nw, int nc, double beta, 
   if (nonfinite) atomicOr(err, ERR_NONFINITE);
 }
 
+int self_consistency_parts(int nk) { return nk < kScParts ? nk : kScParts; }
+
 hipError_t launch_self_consistency(int nk, int nc, int nw, int nb_uniform, const int32_t* nb, const int64_t* off_b,
                                    const double* eps, const double* wk, const double* proj, const double* e_dc,
                                    double beta, double mu, const double* gloc, const double* sigma, double* e_imp,
-                                   double* delta, int* err, hipStream_t s) {
-  hipLaunchKernelGGL(eimp_kernel, dim3(nc * nc), dim3(256), 0, s, nk, nc, nb_uniform, nb, off_b, eps, wk, proj, e_dc,
-                     e_imp);
+                                   double* delta, double* part, int* err, hipStream_t s) {
+  const int np = self_consistency_parts(nk);
+  hipLaunchKernelGGL(eimp_partial_kernel, dim3(np), dim3(256), 0, s, nk, nc, nb_uniform, nb, off_b, eps, wk, proj,
+                     part);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(eimp_reduce_kernel, dim3(1), dim3(256), 0, s, nc, np, part, e_dc, e_imp);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(delta_kernel, dim3((nw + 3) / 4), dim3(64), 0, s, nw, nc, beta, mu, gloc, sigma, e_imp, delta,
                      err);
