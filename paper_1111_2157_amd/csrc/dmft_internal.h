@@ -114,7 +114,7 @@ hipError_t launch_batched_lr(const void* items, int n_items, const DysonArgs* ar
 hipError_t launch_copy_doubles(const double* src, double* dst, int n, hipStream_t s);
 // DMFT self-consistency step: E_imp (device [nc][nc] complex) and Delta (device [nw][nc][nc]);
 // part holds self_consistency_parts(nk) x nc x nc complex partials of E_imp.
-constexpr int kScParts = 256;
+constexpr int kScParts = 1024;
 int self_consistency_parts(int nk);
 hipError_t launch_self_consistency(int nk, int nc, int nw, int nb_uniform, const int32_t* nb, const int64_t* off_b,
                                    const double* eps, const double* wk, const double* proj, const double* e_dc,
