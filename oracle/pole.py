@@ -178,3 +178,30 @@ def dos(lat, sig, mu, eta, energies):
         d += lat.wk[k] * lor @ w
         pd += lat.wk[k] * lor @ wo
     return d, pd
+
+
+def energy_terms(lat, sig, mu):
+    """Pole-route sums of the energy functional (Sec. 3.5.1 eqs. H_KS, H_U_energy
+    and <V_DC>), with E^ps absolute (reading of eq. pseudo_H_k above):
+        B      = sum_k w_k sum_m E^ps_m |u_m|^2 n_F(E^ps_m - mu)
+        N_tot  = sum_k w_k sum_m |u_m|^2 n_F(E^ps_m - mu)
+        H_KS   = sum_k w_k sum_n E_n N_nn                      (eq. H_KS)
+        n_a    = sum_k w_k sum_m |S_a u_m|^2 n_F(E^ps_m - mu)  (correlated occupations)
+        V_DC   = sum_a V_DC,a n_a                              (eq. <V_DC> for this V_DC)
+        H_U    = (B - H_KS + V_DC) / 2.
+    H_U is the Galitskii-Migdal value (1/2) tr[Sigma G]: the derivation through
+    G^-1 = i w + mu - H_KS + V_DC - Sigma gives sum_m (E^ps_m - mu) ... + mu N_tot,
+    i.e. B with the absolute E^ps (the printed eq. H_U_energy omits mu N_tot).
+    Returns a dict."""
+    B = N = hks = 0.0
+    na = np.zeros(int(lat.nc))
+    for k in range(lat.nk):
+        lam, u, w, wo = eigensystem(lat, sig, k)
+        f = fermi(lam - mu, sig.beta)
+        wk = lat.wk[k]
+        B += wk * np.sum(lam * w * f)
+        N += wk * np.sum(w * f)
+        hks += wk * np.sum(lat.eps_k(k) * ((np.abs(u) ** 2) @ f))
+        na += wk * (wo.T @ f)
+    vdc = float(np.dot(np.asarray(sig.e_dc, np.float64), na))
+    return {"band": B, "n_tot": N, "h_ks": hks, "n_orb": na, "v_dc": vdc, "h_u": 0.5 * (B - hks + vdc)}

@@ -603,3 +603,86 @@ def test_pole_find_mu_and_slope():
     fd = (pole.exact_ntot(lat, _poles_from(sig, mu + h), mu + h)
           - pole.exact_ntot(lat, _poles_from(sig, mu - h), mu - h)) / (2 * h)
     assert abs(fd - d) <= 1e-6 * abs(d)
+
+
+# ---------------------------------------------------------------------------
+# Hubbard-I atom, the appendix pole fit and the energy functional (Sec. 3.2.4
+# eqs. Dyson and G_imp_atom; appendix eq. dyson_pole; Sec. 3.5.1 eqs. H_KS,
+# H_U_energy, <V_DC>).
+from oracle import atom
+
+
+def test_hubbard1_two_orbital_closed_form():
+    """Two orbitals (one level, two spins): G = (1-n)/(iw - e) + n/(iw - e - U) with
+    n the other orbital's occupation, so Sigma has one pole U^2 n (1-n) at
+    e + U (1-n) and Sigma_inf = U n (e = e_a - mu)."""
+    e_a, U, mu, beta = 0.3, 4.5, 1.1, 6.0
+    (Q, W, sinf), _ = atom.hubbard1_sigma([e_a, e_a], U, mu, beta)
+    _, n = atom.interaction_energy([e_a, e_a], U, mu, beta)
+    a, p = synth.hubbard1_pole(U, n[1], e_a - mu)
+    assert Q.size == 1
+    assert abs(Q[0] - p) < 1e-12 and abs(W[0] - a) < 1e-12 and abs(sinf - U * n[1]) < 1e-13
+
+
+@pytest.mark.parametrize("nc", [3, 5, 10, 14])
+def test_hubbard1_dyson_and_sum_rules(nc):
+    """The fitted pole form satisfies eq. Dyson (Sigma = i w + mu - e - G^-1) at any
+    frequency; the Green's function has unit weight, its first moment is
+    e - mu + U <N_other>, and its occupation sum_N V_N n_F(P_N) equals the
+    atom's thermal <n_a>."""
+    rng = np.random.default_rng(nc)
+    eps = rng.uniform(-2.0, 1.0, nc)
+    U, mu, beta = 3.0, -0.4 + 0.5 * nc / 5, 4.0
+    P, V = atom.green_poles(eps, U, mu, beta)
+    _, n = atom.interaction_energy(eps, U, mu, beta)
+    for a in range(nc):
+        assert abs(V[a].sum() - 1.0) < 1e-13
+        other = n.sum() - n[a]
+        assert abs(np.sum(V[a] * P[a]) - (eps[a] - mu + U * other)) < 1e-11
+        assert abs(np.sum(V[a] * pole.fermi(P[a], beta)) - n[a]) < 1e-12
+        wtol = 1e-13
+        Q, W, sinf = atom.pole_fit(P[a], V[a], eps[a], mu, wtol)
+        assert np.all(W > 0)
+        keep = V[a] > wtol
+        pk, vk = P[a][keep], V[a][keep] / V[a][keep].sum()
+        for w in (0.05, 1.3, 17.0):
+            z = 1j * w
+            sig = sinf + np.sum(W / (z - Q))
+            ref = z + mu - eps[a] - 1.0 / np.sum(vk / (z - pk))
+            assert abs(sig - ref) <= 1e-11 * max(1.0, abs(ref))
+            # the dropped poles change G by about their weight
+            g_all, g_kept = np.sum(V[a] / (z - P[a])), np.sum(vk / (z - pk))
+            assert abs(g_all - g_kept) <= 10 * nc * wtol / min(1.0, w)
+
+
+def _atomic_lattice(eps_imp, U, mu, beta, e_dc, nk=3, wtol=1e-13):
+    """nk identical k-points whose bands are the atom's orbitals (projector: a
+    diagonal of phases), E = e_imp + V_DC, and the atom's Hubbard-I self-energy
+    with absolute pole positions: the lattice Green's function is the atomic one."""
+    nc = len(eps_imp)
+    ph = np.exp(1j * np.linspace(0.2, 2.0, nc))
+    lat = synth.Lattice(nk, nc, np.full(nk, nc, np.int32), np.tile(np.asarray(eps_imp) + e_dc, nk),
+                        np.full(nk, 1.0 / nk), np.tile(np.diag(ph).ravel(), nk))
+    fits = atom.hubbard1_sigma(eps_imp, U, mu, beta, wtol)
+    poles = []
+    for a, (Q, W, _) in enumerate(fits):
+        for q, w in zip(Q, W):
+            poles.append((q + mu, np.sqrt(w) * np.eye(nc)[a]))
+    sinf = np.diag([f[2] for f in fits]).astype(np.complex128)
+    sig = synth.SelfEnergy(1, beta, np.zeros((1, nc, nc), np.complex128), sinf, np.asarray(e_dc, np.float64), poles)
+    return lat, sig
+
+
+@pytest.mark.parametrize("e_dc", [0.0, 0.7])
+def test_energy_atomic_limit(e_dc):
+    """Without hybridisation the lattice with the Hubbard-I self-energy is the atom:
+    the pole-route occupations are the atom's, and (1/2) tr[Sigma G] (with V_DC
+    taken back out) is the atom's <H_U> from exact diagonalisation."""
+    eps = np.array([-1.2, -1.0, -0.9, 0.2, 0.4])
+    U, mu, beta = 2.5, 0.3, 5.0
+    lat, sig = _atomic_lattice(eps, U, mu, beta, np.full(eps.size, e_dc))
+    t = pole.energy_terms(lat, sig, mu)
+    hu, n = atom.interaction_energy(eps, U, mu, beta)
+    assert np.abs(t["n_orb"] - n).max() < 1e-12
+    assert abs(t["n_tot"] - n.sum()) < 1e-12
+    assert abs(t["h_u"] - hu) < 1e-12
