@@ -349,6 +349,57 @@ int dmft_pole_dos(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol,
                   const double* wphys, const double* worb, double mu, double eta, double e_min, double e_max, int ne,
                   double* dos, double* pdos, void* ws, size_t ws_bytes, hipStream_t stream);
 
+
+/* Energy-functional sums of the pole route (Sec. 3.5.1 eqs. H_KS, H_U_energy,
+ * <V_DC>) from dmft_pole_eig's output (worb required):
+ *   out: DEVICE [5 + nc] = { B, N_tot, <H_KS>, <V_DC>, <H_U>, n_alpha (nc) } with
+ *   B       = sum_k w_k sum_l E^ps_l |u_l|^2 n_F(E^ps_l - mu),
+ *   <H_KS>  = sum_k w_k sum_n E_n N(k)_nn,
+ *   n_alpha = sum_k w_k sum_l |P_alpha u_l|^2 n_F(E^ps_l - mu),
+ *   <V_DC>  = sum_alpha V_DC^alpha n_alpha,
+ *   <H_U>   = (B - <H_KS> + <V_DC>) / 2 = (1/2) tr[Sigma G] (Galitskii-Migdal).
+ * With E^ps absolute this <H_U> is the printed eq. H_U_energy plus mu N_tot;
+ * the double-counting energy of eq. E_DC follows from n_alpha per site. */
+int dmft_pole_energy(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, double mu, const double* evals,
+                     const double* evecs, const double* wphys, const double* worb, double* out, void* ws,
+                     size_t ws_bytes, hipStream_t stream);
+
+/* Hubbard-I atoms (Sec. 3.2.4 eqs. Dyson and G_imp_atom; appendix eq.
+ * dyson_pole), batched: atom i has nc spin-orbitals with levels eps[i][a]
+ * (the diagonal of E_imp), interaction H_U = (U_i/2) sum_{a != b} n_a n_b
+ * (eq. H_U at J = 0) and chemical potential mu[i]; all Fock states are
+ * enumerated (2^nc, nc <= 16).  Its Green's function is diagonal with poles
+ * e_a - mu + U N weighted by Boltzmann factors; the self-energy
+ *   Sigma_aa(i w) = sigma_inf[i][a] + sum_j wgt[i][a][j] / (i w + mu - pos[i][a][j])
+ * has npoles[i][a] <= nc - 1 poles, placed by bisection between adjacent
+ * Green's-function poles, with positions on the absolute energy axis (as
+ * dmft_poles takes them).  G poles of weight <= wtol are dropped and the rest
+ * renormalised (1e-13 is a good value; 0 keeps every nonzero weight).
+ *   eps: DEVICE [natoms][nc]; U, mu: DEVICE [natoms];
+ *   sigma_inf: DEVICE [natoms][nc]; npoles: DEVICE int32 [natoms][nc];
+ *   pos, wgt: DEVICE [natoms][nc][nc] (entries past npoles are zero);
+ *   occ: DEVICE [natoms][nc] thermal <n_a>, or NULL; e_u: DEVICE [natoms] <H_U>, or NULL.
+ * No workspace.  The pole vectors of dmft_poles are V = sqrt(wgt) e_a. */
+int dmft_hubbard1(dmft_handle h, int natoms, int nc, const double* eps, const double* U, const double* mu,
+                  double beta, double wtol, double* sigma_inf, int32_t* npoles, double* pos, double* wgt, double* occ,
+                  double* e_u, hipStream_t stream);
+
+/* Matsubara-axis self-energy of a pole form (Sec. 3.2.4 eq. se_pole) at chemical
+ * potential mu, for the frequency-sum route:
+ *   sigma[n] = Sigma_inf + sum_i V_i^dag V_i / (i w_n + mu - p_i),  w_n = (2n+1) pi / beta,
+ * sigma: DEVICE [nw][nc][nc] complex.  pol->e_dc is not used. */
+int dmft_sigma_from_poles(dmft_handle h, int nc, const dmft_poles* pol, int nw, double mu, double* sigma,
+                          hipStream_t stream);
+
+
+/* One atom's dmft_hubbard1 output (npoles [nc], pos and wgt [nc][nc], DEVICE)
+ * as a dmft_poles pole list: pole j of orbital a becomes p = pos[a][j] with
+ * V = sqrt(wgt[a][j]) e_{a0 + a} among nc_lat correlated orbitals, packed
+ * orbital after orbital.  p: DEVICE [nc (nc - 1)], v: DEVICE [nc (nc - 1)][nc_lat]
+ * complex, np_out: DEVICE int32 [1] = number of poles written. */
+int dmft_hubbard1_poles(dmft_handle h, int nc, int nc_lat, int a0, const int32_t* npoles, const double* pos,
+                        const double* wgt, double* p, double* v, int32_t* np_out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

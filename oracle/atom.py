@@ -50,14 +50,13 @@ def green_poles(eps, U, mu, beta):
     E, occ = atom_energies(eps, U, mu)
     X = boltzmann(E, beta)
     n = occ.sum(axis=1)
+    idx = np.arange(1 << nc)
     P = np.zeros((nc, nc))
     V = np.zeros((nc, nc))
     for a in range(nc):
         P[a] = eps[a] - mu + U * np.arange(nc)
-        for g in range(1 << nc):
-            if occ[g, a]:
-                continue
-            V[a, n[g]] += X[g] + X[g | (1 << a)]
+        empty = occ[:, a] == 0                      # Gamma without a; Gamma + a = index | bit a
+        V[a] = np.bincount(n[empty], weights=X[empty] + X[idx[empty] | (1 << a)], minlength=nc)[:nc]
     return P, V
 
 

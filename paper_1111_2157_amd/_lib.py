@@ -19,7 +19,8 @@ EXPORTS = [
     "dmft_batched_graph_capture", "dmft_batched_graph_launch", "dmft_autotune", "dmft_variants",
     "dmft_set_variant", "dmft_get_variant", "dmft_timing", "dmft_batched_set_form", "dmft_batched_form",
     "dmft_hybridization", "dmft_pole_workspace_size", "dmft_pole_eig", "dmft_pole_sweeps",
-    "dmft_pole_density", "dmft_pole_find_mu", "dmft_pole_dos",
+    "dmft_pole_density", "dmft_pole_find_mu", "dmft_pole_dos", "dmft_pole_energy", "dmft_hubbard1",
+    "dmft_sigma_from_poles", "dmft_hubbard1_poles",
     "dmft_sync_status",
 ]
 
@@ -90,6 +91,10 @@ def load():
         "dmft_pole_find_mu": ([P, lp, pp, P, P, D, D, I, D, D, I, C.POINTER(D), C.POINTER(I), C.POINTER(D),
                                P, S, P], I),
         "dmft_pole_dos": ([P, lp, pp, P, P, P, D, D, D, D, I, P, P, P, S, P], I),
+        "dmft_pole_energy": ([P, lp, pp, D, P, P, P, P, P, P, S, P], I),
+        "dmft_hubbard1": ([P, I, I, P, P, P, D, D, P, P, P, P, P, P, P], I),
+        "dmft_sigma_from_poles": ([P, I, pp, I, D, P, P], I),
+        "dmft_hubbard1_poles": ([P, I, I, I, P, P, P, P, P, P, P], I),
         "dmft_set_variant": ([P, I, I, I], I),
         "dmft_get_variant": ([P, I, I], I),
         "dmft_batched_set_form": ([P, I], I),

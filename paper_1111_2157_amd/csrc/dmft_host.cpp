@@ -1252,7 +1252,8 @@ int dmft_batched_graph_launch(dmft_handle h, hipStream_t stream) {
 namespace {
 
 struct PoleLayout {
-  size_t err = 0, res = 0, meta_nb = 0, meta_offb = 0, meta_offn = 0, kscal = 0, sweeps = 0, part = 0, total = 0;
+  size_t err = 0, res = 0, meta_nb = 0, meta_offb = 0, meta_offn = 0, kscal = 0, sweeps = 0, part = 0, epart = 0;
+  size_t total = 0;
   int mp = 0;
   bool ragged = false;
 };
@@ -1288,6 +1289,7 @@ void pole_layout(const dmft_lattice* lat, const dmft_poles* pol, int ne, PoleLay
   P.kscal = take(sizeof(double) * 3 * nk);
   P.sweeps = take(sizeof(int32_t) * nk);
   P.part = take(sizeof(double) * (size_t)pole_dos_kslices(nk, P.mp) * std::max(ne, 1) * (1 + lat->nc));
+  P.epart = take(sizeof(double) * (size_t)pole_energy_parts(nk, P.mp) * (3 + lat->nc));
   P.total = o;
 }
 
@@ -1473,6 +1475,65 @@ int dmft_pole_dos(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol,
   a.wphys = const_cast<double*>(wphys);
   a.worb = pdos ? const_cast<double*>(worb) : nullptr;
   HIPCHK(h, launch_pole_dos(a, mu, eta, e_min, e_max, ne, (double*)(w + P.part), dos, pdos, stream));
+  return DMFT_OK;
+}
+
+int dmft_pole_energy(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol, double mu, const double* evals,
+                     const double* evecs, const double* wphys, const double* worb, double* out, void* ws,
+                     size_t ws_bytes, hipStream_t stream) {
+  if (!evals || !evecs || !wphys || !worb || !out)
+    return fail(h, DMFT_EINVAL, "evals, evecs, wphys, worb and out are required");
+  if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
+  PoleLayout P;
+  int r = pole_prepare(h, lat, pol, 0, ws, ws_bytes, P, stream);
+  if (r) return r;
+  char* w = (char*)ws;
+  PoleArgs a = pole_args(lat, pol, P, w);
+  a.evals = const_cast<double*>(evals);
+  a.evecs = const_cast<double*>(evecs);
+  a.wphys = const_cast<double*>(wphys);
+  a.worb = const_cast<double*>(worb);
+  HIPCHK(h, launch_pole_energy(a, mu, (double*)(w + P.epart), out, stream));
+  return DMFT_OK;
+}
+
+int dmft_hubbard1(dmft_handle h, int natoms, int nc, const double* eps, const double* U, const double* mu,
+                  double beta, double wtol, double* sigma_inf, int32_t* npoles, double* pos, double* wgt, double* occ,
+                  double* e_u, hipStream_t stream) {
+  if (!h) return DMFT_EINVAL;
+  if (natoms < 1) return fail(h, DMFT_EINVAL, "natoms must be >= 1");
+  if (nc < 1 || nc > 16) return fail(h, DMFT_EINVAL, "nc must be in 1..16 (got %d)", nc);
+  if (!(beta > 0) || !std::isfinite(beta)) return fail(h, DMFT_EINVAL, "beta must be positive and finite");
+  if (!(wtol >= 0) || !std::isfinite(wtol) || wtol >= 1.0) return fail(h, DMFT_EINVAL, "wtol must be in [0, 1)");
+  if (!eps || !U || !mu || !sigma_inf || !npoles || !pos || !wgt)
+    return fail(h, DMFT_EINVAL, "eps, U, mu, sigma_inf, npoles, pos and wgt are required");
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, launch_hubbard1(natoms, nc, eps, U, mu, beta, wtol, sigma_inf, npoles, pos, wgt, occ, e_u, stream));
+  return DMFT_OK;
+}
+
+int dmft_sigma_from_poles(dmft_handle h, int nc, const dmft_poles* pol, int nw, double mu, double* sigma,
+                          hipStream_t stream) {
+  if (!h) return DMFT_EINVAL;
+  if (!pol || !sigma) return fail(h, DMFT_EINVAL, "poles and sigma are required");
+  if (nc < 1 || nc > 16) return fail(h, DMFT_EINVAL, "nc must be in 1..16 (got %d)", nc);
+  if (nw < 1) return fail(h, DMFT_EINVAL, "nw must be >= 1");
+  if (pol->np < 0 || (pol->np > 0 && (!pol->p || !pol->v))) return fail(h, DMFT_EINVAL, "bad pole arrays");
+  if (!(pol->beta > 0) || !std::isfinite(pol->beta)) return fail(h, DMFT_EINVAL, "beta must be positive and finite");
+  if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, launch_sigma_from_poles(nw, nc, pol->np, pol->beta, mu, pol->p, pol->v, pol->sigma_inf, sigma, stream));
+  return DMFT_OK;
+}
+
+int dmft_hubbard1_poles(dmft_handle h, int nc, int nc_lat, int a0, const int32_t* npoles, const double* pos,
+                        const double* wgt, double* p, double* v, int32_t* np_out, hipStream_t stream) {
+  if (!h) return DMFT_EINVAL;
+  if (nc < 1 || nc > 16 || nc_lat < 1 || nc_lat > 16 || a0 < 0 || a0 + nc > nc_lat)
+    return fail(h, DMFT_EINVAL, "need 1 <= nc, nc_lat <= 16 and 0 <= a0, a0 + nc <= nc_lat");
+  if (!npoles || !pos || !wgt || !p || !v || !np_out) return fail(h, DMFT_EINVAL, "all arrays are required");
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, launch_hubbard1_poles(nc, nc_lat, a0, npoles, pos, wgt, p, v, np_out, stream));
   return DMFT_OK;
 }
 

@@ -167,5 +167,18 @@ hipError_t launch_pole_find_mu(const PoleArgs& a, double n_target, double tol, i
 int pole_dos_kslices(int nk, int mp);
 hipError_t launch_pole_dos(const PoleArgs& a, double mu, double eta, double e_min, double e_max, int ne,
                            double* part, double* dos, double* pdos, hipStream_t s);
+// Energy-functional sums; part holds pole_energy_parts(nk, mp) x (3 + nc) partials,
+// out = [B, N_tot, <H_KS>, <V_DC>, <H_U>, n_a (nc)].
+int pole_energy_parts(int nk, int mp);
+hipError_t launch_pole_energy(const PoleArgs& a, double mu, double* part, double* out, hipStream_t s);
+// Hubbard-I atoms (one work-group per atom and orbital) and the Matsubara-axis
+// self-energy of a pole form.
+hipError_t launch_hubbard1(int natoms, int nc, const double* eps, const double* U, const double* mu, double beta,
+                           double wtol, double* sigma_inf, int32_t* npoles, double* pos, double* wgt, double* occ,
+                           double* e_u, hipStream_t s);
+hipError_t launch_sigma_from_poles(int nw, int nc, int np, double beta, double mu, const double* p, const double* v,
+                                   const double* sinf, double* sigma, hipStream_t s);
+hipError_t launch_hubbard1_poles(int nc, int nc_lat, int a0, const int32_t* npoles, const double* pos,
+                                 const double* wgt, double* p, double* v, int32_t* np_out, hipStream_t s);
 
 }  // namespace dmft

@@ -514,6 +514,78 @@ __global__ void pole_dos_reduce_kernel(int ne, int nc, int nslices, const double
   else if (pdos) pdos[(int64_t)e * nc + c - 1] = s;
 }
 
+// Energy-functional sums over (k, level m) (Sec. 3.5.1): per block partials of
+// B = sum w_k E^ps |u|^2 n_F, N = sum w_k |u|^2 n_F, <H_KS> = sum w_k n_F sum_n E_n |u_nm|^2
+// and n_a = sum w_k |S_a u|^2 n_F.
+__global__ void __launch_bounds__(256) pole_energy_kernel(PoleArgs a, double mu, double* part) {
+  __shared__ double red[256];
+  const int t = threadIdx.x, nc = a.nc;
+  const int64_t total = (int64_t)a.nk * a.mp;
+  double sb = 0.0, sn = 0.0, sh = 0.0, so[16];
+#pragma unroll
+  for (int al = 0; al < 16; ++al) so[al] = 0.0;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + t; idx < total; idx += (int64_t)gridDim.x * 256) {
+    const int k = (int)(idx / a.mp), m = (int)(idx - (int64_t)k * a.mp);
+    int nb;
+    int64_t ob;
+    k_window(a, k, nb, ob);
+    if (m >= nb + a.np) continue;
+    const double lam = a.evals[idx];
+    const double wf = a.wk[k] * fermi(lam - mu, a.beta);
+    const double wp = a.wphys[idx];
+    sb += wf * lam * wp;
+    sn += wf * wp;
+    const double2* U = reinterpret_cast<const double2*>(a.evecs) + (int64_t)k * a.nb_max * a.mp + m;
+    const double* E = a.eps + ob;
+    double hk = 0.0;
+    for (int n = 0; n < nb; ++n) hk += E[n] * pabs2(U[(int64_t)n * a.mp]);
+    sh += wf * hk;
+#pragma unroll
+    for (int al = 0; al < 16; ++al)
+      if (al < nc) so[al] += wf * a.worb[idx * nc + al];
+  }
+  double* o = part + (int64_t)blockIdx.x * (3 + nc);
+  sb = pole_block_sum<256>(sb, red);
+  sn = pole_block_sum<256>(sn, red);
+  sh = pole_block_sum<256>(sh, red);
+  if (t == 0) {
+    o[0] = sb;
+    o[1] = sn;
+    o[2] = sh;
+  }
+#pragma unroll
+  for (int al = 0; al < 16; ++al)
+    if (al < nc) {
+      const double v = pole_block_sum<256>(so[al], red);
+      if (t == 0) o[3 + al] = v;
+    }
+}
+
+// out = [B, N_tot, <H_KS>, <V_DC> = sum_a V_DC,a n_a, <H_U> = (B - <H_KS> + <V_DC>) / 2, n_a ...]
+__global__ void __launch_bounds__(256) pole_energy_reduce_kernel(int nparts, int nc, const double* part,
+                                                                 const double* e_dc, double* out) {
+  __shared__ double red[256];
+  __shared__ double vals[3 + 16];
+  const int t = threadIdx.x, nv = 3 + nc;
+  for (int j = 0; j < nv; ++j) {
+    double s = 0.0;
+    for (int b = t; b < nparts; b += 256) s += part[(int64_t)b * nv + j];
+    s = pole_block_sum<256>(s, red);
+    if (t == 0) vals[j] = s;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double vdc = 0.0;
+    for (int al = 0; al < nc; ++al) vdc += e_dc[al] * vals[3 + al];
+    out[0] = vals[0];
+    out[1] = vals[1];
+    out[2] = vals[2];
+    out[3] = vdc;
+    out[4] = 0.5 * (vals[0] - vals[2] + vdc);
+    for (int al = 0; al < nc; ++al) out[5 + al] = vals[3 + al];
+  }
+}
+
 hipError_t allow_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -566,6 +638,20 @@ hipError_t launch_pole_dos(const PoleArgs& a, double mu, double eta, double e_mi
   const int64_t n = (int64_t)ne * (1 + a.nc);
   hipLaunchKernelGGL(pole_dos_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ne, a.nc, ns, part,
                      dos, pdos);
+  return hipGetLastError();
+}
+
+int pole_energy_parts(int nk, int mp) {
+  const int64_t n = ((int64_t)nk * mp + 255) / 256;
+  return (int)(n < 1 ? 1 : n > 1024 ? 1024 : n);
+}
+
+hipError_t launch_pole_energy(const PoleArgs& a, double mu, double* part, double* out, hipStream_t s) {
+  const int np = pole_energy_parts(a.nk, a.mp);
+  hipLaunchKernelGGL(pole_energy_kernel, dim3(np), dim3(256), 0, s, a, mu, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pole_energy_reduce_kernel, dim3(1), dim3(256), 0, s, np, a.nc, part, a.e_dc, out);
   return hipGetLastError();
 }
 

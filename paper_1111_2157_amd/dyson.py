@@ -390,6 +390,57 @@ class Context:
                                              int(ne), _ptr(d), _ptr(pd), _ptr(ws), nws, _stream(self.device)))
         return d, pd
 
+    def pole_energy(self, lat: Lattice, pol: PoleSelfEnergy, es: PoleEigensystem, mu: float) -> torch.Tensor:
+        """Device [5 + nc] = [B, N_tot, <H_KS>, <V_DC>, <H_U>, n_alpha ...] (see dmft_pole_energy)."""
+        out = torch.empty(5 + lat.nc, dtype=torch.float64, device=self.device)
+        ws, nws = self._pole_ws(lat, pol)
+        ls, ps = lat.struct(), pol.struct()
+        check(self.h, self.lib.dmft_pole_energy(self.h, C.byref(ls), C.byref(ps), float(mu), _ptr(es.evals),
+                                                _ptr(es.evecs), _ptr(es.wphys), _ptr(es.worb), _ptr(out), _ptr(ws),
+                                                nws, _stream(self.device)))
+        return out
+
+    def hubbard1(self, eps: torch.Tensor, U: torch.Tensor, mu: torch.Tensor, beta: float, wtol: float = 1e-13):
+        """Hubbard-I atoms: eps [natoms, nc], U and mu [natoms] (float64, device).
+        Returns a dict of device tensors sigma_inf [natoms, nc], npoles [natoms, nc],
+        pos and wgt [natoms, nc, nc], occ [natoms, nc], e_u [natoms]."""
+        natoms, nc = eps.shape
+        dev = self.device
+        out = {"sigma_inf": torch.empty((natoms, nc), dtype=torch.float64, device=dev),
+               "npoles": torch.empty((natoms, nc), dtype=torch.int32, device=dev),
+               "pos": torch.empty((natoms, nc, nc), dtype=torch.float64, device=dev),
+               "wgt": torch.empty((natoms, nc, nc), dtype=torch.float64, device=dev),
+               "occ": torch.empty((natoms, nc), dtype=torch.float64, device=dev),
+               "e_u": torch.empty(natoms, dtype=torch.float64, device=dev)}
+        eps, U, mu = eps.contiguous(), U.contiguous(), mu.contiguous()
+        check(self.h, self.lib.dmft_hubbard1(self.h, int(natoms), int(nc), _ptr(eps), _ptr(U), _ptr(mu),
+                                             float(beta), float(wtol), _ptr(out["sigma_inf"]), _ptr(out["npoles"]),
+                                             _ptr(out["pos"]), _ptr(out["wgt"]), _ptr(out["occ"]), _ptr(out["e_u"]),
+                                             _stream(self.device)))
+        return out
+
+    def hubbard1_poles(self, h1, atom: int, nc_lat: int, a0: int = 0):
+        """(p [np], v [np, nc_lat]) of one atom's self-energy poles in the layout of
+        PoleSelfEnergy (orbital a of the atom is correlated orbital a0 + a)."""
+        nc = h1["npoles"].shape[1]
+        p = torch.zeros(max(nc * (nc - 1), 1), dtype=torch.float64, device=self.device)
+        v = torch.zeros((max(nc * (nc - 1), 1), nc_lat), dtype=torch.complex128, device=self.device)
+        npo = torch.zeros(1, dtype=torch.int32, device=self.device)
+        check(self.h, self.lib.dmft_hubbard1_poles(self.h, int(nc), int(nc_lat), int(a0),
+                                                   _ptr(h1["npoles"][atom]), _ptr(h1["pos"][atom]),
+                                                   _ptr(h1["wgt"][atom]), _ptr(p), _ptr(v), _ptr(npo),
+                                                   _stream(self.device)))
+        n = int(npo.item())
+        return p[:n], v[:n]
+
+    def sigma_from_poles(self, pol: PoleSelfEnergy, nc: int, nw: int, mu: float) -> torch.Tensor:
+        """Sigma(i w_n) [nw, nc, nc] of a pole form at chemical potential mu."""
+        sig = torch.empty((nw, nc, nc), dtype=torch.complex128, device=self.device)
+        ps = pol.struct()
+        check(self.h, self.lib.dmft_sigma_from_poles(self.h, int(nc), C.byref(ps), int(nw), float(mu), _ptr(sig),
+                                                     _stream(self.device)))
+        return sig
+
     def timing(self, enable: bool):
         """Returns (summed Dyson-kernel ms, timed launches) recorded so far."""
         ms, n = C.c_double(), C.c_int64()
