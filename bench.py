@@ -105,8 +105,9 @@ def parse():
     ap.add_argument("--no-mu", action="store_true", help="skip the mu-search comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
     ap.add_argument("--extra", action="store_true", help="also time the other workloads")
-    ap.add_argument("--section", choices=["pole", "sc"], default=None,
-                    help="time only the pole route or the self-consistency step and print that record")
+    ap.add_argument("--section", choices=["pole", "sc", "atom"], default=None,
+                    help="time only the pole route, the self-consistency step or the atom and energy "
+                         "sums, and print that record")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (use the default variants)")
     ap.add_argument("--batched", action="store_true", help="also time the batched workload (8 iterates, graph)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -352,6 +353,51 @@ def pole_route(ctx, tune=True):
     return out
 
 
+def atom_section(ctx):
+    """Hubbard-I atoms (64 atoms of 10 and of 14 spin-orbitals, U = 6, beta = 40:
+    every Fock state of every atom, for every orbital) and the energy-functional
+    sums of the pole route on the d-shell and f-shell workloads.  The energy
+    kernel reads, per (k, level) entry, E^ps, |u|^2 and |S_a u|^2 (8 (2 + nc) B)
+    and the physical eigenvector column (16 Nb B): its HBM rate is priced
+    against 8 TB/s."""
+    import dataclasses
+
+    import torch
+
+    from paper_1111_2157_amd import synth
+    from paper_1111_2157_amd.dyson import Lattice, PoleSelfEnergy
+
+    def dev(x):
+        return torch.as_tensor(np.asarray(x, np.float64), device="cuda")
+
+    out = {}
+    for nc in (10, 14):
+        natoms = 64
+        rng = np.random.default_rng(nc)
+        eps, U, mu = dev(rng.uniform(-1.0, 0.5, (natoms, nc))), dev(np.full(natoms, 6.0)), dev(np.zeros(natoms))
+        ctx.hubbard1(eps, U, mu, 40.0)
+        torch.cuda.synchronize()
+        ms = _event_ms(lambda: ctx.hubbard1(eps, U, mu, 40.0), 5)
+        n = natoms * nc * 2 ** nc
+        out["hubbard1-%dx%d" % (natoms, nc)] = {"ms": ms, "state_orbital_evals": n,
+                                                "state_orbital_evals_per_s": n / (ms * 1e-3)}
+    for w in (synth.d_shell(), synth.f_shell()):
+        sig = dataclasses.replace(w.sigma, poles=[(p + w.mu, v) for p, v in w.sigma.poles])
+        lat, pol = Lattice.from_host(w.lattice), PoleSelfEnergy.from_host(sig)
+        es = ctx.pole_eig(lat, pol)
+        ctx.pole_energy(lat, pol, es, w.mu)
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        ms = _event_ms(lambda: ctx.pole_energy(lat, pol, es, w.mu), 10)
+        nb, nc = w.lattice.nb_max, w.lattice.nc
+        nbytes = w.lattice.nk * (nb + len(sig.poles)) * (8 * (2 + nc) + 16 * nb)
+        gbps = nbytes / (ms * 1e-3) / 1e9
+        out["energy-" + w.name] = {"ms": ms, "algorithmic_bytes": nbytes, "gbps": gbps,
+                                   "roofline": {"bound": "hbm", "achieved": gbps, "peak": 8000.0, "unit": "GB/s",
+                                                "frac": gbps / 8000.0}}
+    return out
+
+
 def mu_search(ctx, tune=True):
     import torch
 
@@ -428,7 +474,8 @@ def main():
         from paper_1111_2157_amd.dyson import Context
 
         ctx = Context(0)
-        rec = pole_route(ctx, not args.no_tune) if args.section == "pole" else self_consistency(ctx)
+        rec = {"pole": lambda: pole_route(ctx, not args.no_tune), "sc": lambda: self_consistency(ctx),
+               "atom": lambda: atom_section(ctx)}[args.section]()
         print(json.dumps({"section": args.section, "result": rec}), flush=True)
         return
     import torch
@@ -498,6 +545,7 @@ def main():
         extra["adjoint (N_tot, dN/dmu, dN/dSigma)"] = adjoint_pass(ctx)
         extra["self-consistency (E_imp, Delta)"] = self_consistency(ctx)
         extra["pole route"] = pole_route(ctx, not args.no_tune)
+        extra["atom and energy"] = atom_section(ctx)
         rec["extra"] = extra
     if args.batched:
         rec["batched"] = batched(ctx)

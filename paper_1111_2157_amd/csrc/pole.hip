@@ -561,29 +561,25 @@ __global__ void __launch_bounds__(256) pole_energy_kernel(PoleArgs a, double mu,
     }
 }
 
-// out = [B, N_tot, <H_KS>, <V_DC> = sum_a V_DC,a n_a, <H_U> = (B - <H_KS> + <V_DC>) / 2, n_a ...]
+// Fixed-order sum of partial j over the energy kernel's blocks (one work-group
+// per value), written to its slot of out = [B, N_tot, <H_KS>, <V_DC>, <H_U>, n_a ...].
 __global__ void __launch_bounds__(256) pole_energy_reduce_kernel(int nparts, int nc, const double* part,
-                                                                 const double* e_dc, double* out) {
+                                                                 double* out) {
   __shared__ double red[256];
-  __shared__ double vals[3 + 16];
-  const int t = threadIdx.x, nv = 3 + nc;
-  for (int j = 0; j < nv; ++j) {
-    double s = 0.0;
-    for (int b = t; b < nparts; b += 256) s += part[(int64_t)b * nv + j];
-    s = pole_block_sum<256>(s, red);
-    if (t == 0) vals[j] = s;
-  }
-  __syncthreads();
-  if (t == 0) {
-    double vdc = 0.0;
-    for (int al = 0; al < nc; ++al) vdc += e_dc[al] * vals[3 + al];
-    out[0] = vals[0];
-    out[1] = vals[1];
-    out[2] = vals[2];
-    out[3] = vdc;
-    out[4] = 0.5 * (vals[0] - vals[2] + vdc);
-    for (int al = 0; al < nc; ++al) out[5 + al] = vals[3 + al];
-  }
+  const int t = threadIdx.x, j = blockIdx.x, nv = 3 + nc;
+  double s = 0.0;
+  for (int b = t; b < nparts; b += 256) s += part[(int64_t)b * nv + j];
+  s = pole_block_sum<256>(s, red);
+  if (t == 0) out[j < 3 ? j : j + 2] = s;
+}
+
+// <V_DC> = sum_a V_DC,a n_a and <H_U> = (B - <H_KS> + <V_DC>) / 2.
+__global__ void pole_energy_finish_kernel(int nc, const double* e_dc, double* out) {
+  if (threadIdx.x != 0) return;
+  double vdc = 0.0;
+  for (int al = 0; al < nc; ++al) vdc += e_dc[al] * out[5 + al];
+  out[3] = vdc;
+  out[4] = 0.5 * (out[0] - out[2] + vdc);
 }
 
 hipError_t allow_lds(const void* fn, size_t bytes) {
@@ -651,7 +647,10 @@ hipError_t launch_pole_energy(const PoleArgs& a, double mu, double* part, double
   hipLaunchKernelGGL(pole_energy_kernel, dim3(np), dim3(256), 0, s, a, mu, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pole_energy_reduce_kernel, dim3(1), dim3(256), 0, s, np, a.nc, part, a.e_dc, out);
+  hipLaunchKernelGGL(pole_energy_reduce_kernel, dim3(3 + a.nc), dim3(256), 0, s, np, a.nc, part, out);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pole_energy_finish_kernel, dim3(1), dim3(64), 0, s, a.nc, a.e_dc, out);
   return hipGetLastError();
 }
 
