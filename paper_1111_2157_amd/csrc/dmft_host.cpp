@@ -1382,8 +1382,9 @@ int dmft_pole_eig(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol,
   HIPCHK(h, hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
   if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, h->device) != hipSuccess) optin = 0;
   lim = std::max(lim, optin);
-  if (lds + 8192 > (size_t)lim)
-    return fail(h, DMFT_EUNSUPPORTED, "eigensolver needs %zu B of LDS, the device allows %d", lds + 8192, lim);
+  // dynamic LDS plus the kernel's static arrays (at most 10 KB with 1024 threads)
+  if (lds + 12288 > (size_t)lim)
+    return fail(h, DMFT_EUNSUPPORTED, "eigensolver needs %zu B of LDS, the device allows %d", lds + 12288, lim);
   PoleArgs a = pole_args(lat, pol, P, (char*)ws);
   a.evals = evals;
   a.evecs = evecs;

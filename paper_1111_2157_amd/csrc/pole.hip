@@ -35,7 +35,6 @@
 namespace dmft {
 namespace {
 
-constexpr int kEigThreads = 256;
 constexpr int kMaxM = 64;         // largest pseudo-Hamiltonian (nb + np)
 constexpr int kDosThreads = 256;
 constexpr int kDosChunk = 512;    // eigenpairs per slice of the DOS sum
@@ -53,6 +52,19 @@ __device__ __forceinline__ double2 pfma(double2 a, double2 b, double2 c) {  // c
   return pz(__builtin_fma(a.x, b.x, __builtin_fma(-a.y, b.y, c.x)), __builtin_fma(a.x, b.y, __builtin_fma(a.y, b.x, c.y)));
 }
 __device__ __forceinline__ double pabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+// 1/sqrt(x) and 1/x: the hardware estimates refined by two Newton steps
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = x * y;
+  y = __builtin_fma(0.5 * y, __builtin_fma(-h, y, 1.0), y);
+  h = x * y;
+  return __builtin_fma(0.5 * y, __builtin_fma(-h, y, 1.0), y);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+  return __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+}
 
 // Fixed-order sum over a block of NT threads (NT a power of two).
 template <int NT>
@@ -106,7 +118,11 @@ __device__ __forceinline__ void k_window(const PoleArgs& a, int k, int& nb, int6
   ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
 }
 
-__global__ void __launch_bounds__(kEigThreads) pole_eig_kernel(PoleArgs a) {
+// NT threads per work-group (256, 512 or 1024, chosen at launch from the
+// number of update items per step).
+template <int NT>
+__global__ void __launch_bounds__(NT) pole_eig_kernel(PoleArgs a) {
+  constexpr int kEigThreads = NT;
   extern __shared__ double2 lds[];
   __shared__ JRot s_r[kMaxM / 2];
   __shared__ double s_dp[kMaxM / 2], s_dq[kMaxM / 2];
@@ -202,10 +218,17 @@ __global__ void __launch_bounds__(kEigThreads) pole_eig_kernel(PoleArgs a) {
           R.sr = R.si = 0.0;
           R.pq = p | (q << 16);
           if (r > tol) {
-            const double ir = 1.0 / r;
+            const double ir = rsq_nr(pabs2(apq));
             const double z = 0.5 * (aqq - app) * ir;
-            const double tt = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
-            R.c = 1.0 / sqrt(1.0 + tt * tt);
+            const double az = fabs(z);
+            double tt;
+            if (az > 1e100) {
+              tt = 0.5 / z;  // 1 + z^2 would overflow; t -> 1 / (2 z)
+            } else {
+              const double z2p1 = __builtin_fma(z, z, 1.0);
+              tt = (z >= 0.0 ? 1.0 : -1.0) * rcp_nr(az + z2p1 * rsq_nr(z2p1));
+            }
+            R.c = rsq_nr(__builtin_fma(tt, tt, 1.0));
             const double sn = tt * R.c * ir;
             R.sr = sn * apq.x;
             R.si = sn * apq.y;
@@ -594,11 +617,21 @@ size_t pole_eig_lds_bytes(int nb, int np) {
   return (size_t)(mq * (mq + 1) + mq * (nb + 1)) * 16;
 }
 
-hipError_t launch_pole_eig(const PoleArgs& a, size_t lds_bytes, hipStream_t s) {
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(pole_eig_kernel), lds_bytes);
+template <int NT>
+hipError_t launch_pole_eig_nt(const PoleArgs& a, size_t lds_bytes, hipStream_t s) {
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(pole_eig_kernel<NT>), lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pole_eig_kernel, dim3(a.nk), dim3(kEigThreads), lds_bytes, s, a);
+  hipLaunchKernelGGL(pole_eig_kernel<NT>, dim3(a.nk), dim3(NT), lds_bytes, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_pole_eig(const PoleArgs& a, size_t lds_bytes, hipStream_t s) {
+  // update items of one step at the largest size: 2x2 blocks I <= J and eigenvector pairs
+  const int m = a.nb_max + a.np, mq = m + (m & 1), P = mq / 2;
+  const int items = P * (P + 1) / 2 + P * a.nb_max;
+  if (items <= 512) return launch_pole_eig_nt<256>(a, lds_bytes, s);
+  if (items <= 1536) return launch_pole_eig_nt<512>(a, lds_bytes, s);
+  return launch_pole_eig_nt<1024>(a, lds_bytes, s);
 }
 
 hipError_t launch_pole_density(const PoleArgs& a, double mu, int nw_trunc, double* nk_out, double* kscal,
