@@ -664,13 +664,31 @@ struct LRSet {
     constexpr bool m3 = (VAR & 2) != 0;
     constexpr int occ = (VAR & 4) ? 2 : 1;
     grid.x *= parts;
-    // columns of the row-layout inversions: nc rounded up to 8, 12 or 16
-    if (a.nc <= 8)
+    // columns of the row-layout inversions: nc rounded up to 8, 12 or 16, with
+    // exact 10 (32-band windows) and 14 (48-band windows) for the
+    // d-shell and f-shell orbital counts: every column costs a broadcast and
+    // four FMAs in each of the nc pivot steps
+    if (a.nc <= 8) {
       hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 8, occ>), grid, dim3(64), 0, s, a);
-    else if (a.nc <= 12)
+      return hipGetLastError();
+    }
+    if constexpr (NBP == 32) {
+      if (a.nc <= 10) {
+        hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 10, occ>), grid, dim3(64), 0, s, a);
+        return hipGetLastError();
+      }
+    }
+    if (a.nc <= 12) {
       hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 12, occ>), grid, dim3(64), 0, s, a);
-    else
-      hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 16, occ>), grid, dim3(64), 0, s, a);
+      return hipGetLastError();
+    }
+    if constexpr (NBP == 48) {
+      if (a.nc <= 14) {
+        hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 14, occ>), grid, dim3(64), 0, s, a);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 16, occ>), grid, dim3(64), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t launch(int var, const DysonArgs& a, dim3 grid, hipStream_t s) {
