@@ -213,6 +213,7 @@ constexpr int lr_col_tiles() {
 
 struct LRShared {
   double2 buf[4][16 * 17];  // one 16x16 tile per frequency of the group (rows padded to 17)
+  double2 dtab[4][64];      // d_r = 1 / (i w + mu - E_r) of the group's frequencies (zero past nb)
 };
 
 // Value of lane K of this lane's 16-lane row.
@@ -284,17 +285,6 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
       lr_load_pa<NBP>(pr, P, nc, nb, q, c16);
       lr_load_pt<NBP>(pr, P, nc, nb, q, c16);
     }
-    double ea[T][4], eb[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      int r = 16 * t + c16;
-      eb[t] = r < nb ? eps[r] : 0.0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int r2 = 16 * t + 4 * i + q;
-        ea[t][i] = r2 < nb ? eps[r2] : 0.0;
-      }
-    }
     // running sum of G, column tiles b0 .. b0 + CT; the three-product form
     // needs three accumulators per tile, so it is used here only up to four tiles
     CAcc<M3 && T * CT <= 4> sacc[T][CT];
@@ -313,13 +303,23 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
     double trg = 0.0, trg2 = 0.0;
 
     for (int n = n0; n < n1; n += 4) {
+      // 0. d_r of the four frequencies, each computed once and read from LDS by
+      //    every lane that needs it (a lane would otherwise redo the complex
+      //    reciprocal for each band it touches, the same value 4 to 16 times
+      //    across the wavefront)
+#pragma unroll
+      for (int idx = lane; idx < 4 * NBP; idx += 64) {
+        const int f = idx / NBP, r = idx - f * NBP;
+        const int nf = min(n + f, n1 - 1);
+        const double wn = (double)(2 * nf + 1) * M_PI / beta;
+        sh.dtab[f][r] = r < nb ? inv_z_minus(mu, wn, eps[r]) : make_double2(0.0, 0.0);
+      }
+      wave_sync();
       // 1. X of the four frequencies n .. n+3 (repeating the last one past n1)
       //    into LDS, in the output layout of the matrix core
       if constexpr (RL == 1) lr_load_pt<NBP>(pr, fresh(P), nc, nb, q, c16);
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        const int nf = min(n + f, n1 - 1);
-        const double wn = (double)(2 * nf + 1) * M_PI / beta;
         CAcc<M3> x;
         x.zero();
 #pragma unroll
@@ -329,8 +329,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
             if (16 * t + 4 * i >= nb) break;
             const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
                                       : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
-            const bool valid = 16 * t + 4 * i + q < nb;
-            double2 dd = valid ? inv_z_minus(mu, wn, ea[t][i]) : make_double2(0.0, 0.0);
+            const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
             double2 a1 = cmul(s, dd);
             x.mac_cb(a1.x, a1.y, s.x, s.y);
           }
@@ -389,7 +388,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
           prev[i] = (part_rmw && q + 4 * i < nc && c16 < nc) ? part[i * 64 + lane] : make_double2(0.0, 0.0);
         double2 dcol[T];
 #pragma unroll
-        for (int t = 0; t < T; ++t) dcol[t] = 16 * t + c16 < nb ? inv_z_minus(mu, wn, eb[t]) : make_double2(0.0, 0.0);
+        for (int t = 0; t < T; ++t) dcol[t] = sh.dtab[f][16 * t + c16];
         if (want_s) {
 #pragma unroll
           for (int t = 0; t < T; ++t) {
@@ -505,8 +504,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
               if (16 * t + 4 * i >= nb) break;
               const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
                                       : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
-              const bool valid = 16 * t + 4 * i + q < nb;
-              double2 dd = valid ? inv_z_minus(mu, wn, ea[t][i]) : make_double2(0.0, 0.0);
+              const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
               double2 a2 = cmul(cmul(s, dd), dd);
               x2a.mac_cb(a2.x, a2.y, s.x, s.y);
               double2 a3 = cmul(a2, dd);
