@@ -43,9 +43,9 @@ LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
 # workload and the same tuned variant; otherwise "traffic" is null.
 TRAFFIC = {
     ("d-shell-Nk512-Nb32-Nc10-Nw1024", 32, 10): {
-        "fetch_bytes": 336794.0 * 2 * 1024,
+        "fetch_bytes": 336717.5 * 2 * 1024,
         "write_bytes": 851968.0 * 1024,
-        "sources_sha256": "53195d28d7878c4d2a505a44e4d0e39b8a4c6750ac8252cb6c2e1fcc39281a09",
+        "sources_sha256": "49257f1d06c901758708e2ce63a693ef12719c142d6c6cce0100284cc53f183e",
         "profile": "profiles/lr_kernel_d-shell.md",
     },
 }
