@@ -216,10 +216,12 @@ struct LRShared {
   double2 dtab[4][64];      // d_r = 1 / (i w + mu - E_r) of the group's frequencies (zero past nb)
 };
 
-// Value of lane K of this lane's 16-lane row.
+// Value of lane K of this lane's 16-lane row.  Every lane of a row reads a lane
+// of its own row, so no lane is out of bounds; bound_ctrl lets the compiler
+// skip initialising the destination (the "old" value is never used).
 template <int K>
 __device__ __forceinline__ double row_bcast(double v) {
-  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + K, 0xf, 0xf, false);
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + K, 0xf, 0xf, true);
 }
 
 // Gauss-Jordan steps K .. nc-1 on the row held by this lane (row i of its
@@ -262,6 +264,10 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   const double mu = a.mu_ptr ? *a.mu_ptr : a.mu;
   const int nc = a.nc;
   const int kc = (nc + 3) >> 2;
+  // nc >= 1 (and nb >= nc below): the first chunk of every contraction over
+  // orbitals or bands is always taken, so its accumulator can start from an
+  // inline zero instead of registers cleared beforehand
+  __builtin_assume(kc >= 1 && kc <= 4);
   const double beta = a.beta;
   const bool want_s = (KIND == KIND_DENSITY) && (a.mode & MODE_S);
   const bool want_x = (KIND == KIND_DENSITY) && (a.mode & MODE_GLOC) && PART == 0;
@@ -272,6 +278,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   for (int kk = kk0; kk < kk1; ++kk) {
     const int k = a.klist ? a.klist[kk] : kk;
     const int nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
+    __builtin_assume(nb >= 1 && nb <= NBP);
     const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
     const double* eps = a.eps + ob;
     const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
