@@ -43,9 +43,9 @@ LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
 # workload and the same tuned variant; otherwise "traffic" is null.
 TRAFFIC = {
     ("d-shell-Nk512-Nb32-Nc10-Nw1024", 32, 10): {
-        "fetch_bytes": 336717.5 * 2 * 1024,
-        "write_bytes": 851968.0 * 1024,
-        "sources_sha256": "49257f1d06c901758708e2ce63a693ef12719c142d6c6cce0100284cc53f183e",
+        "fetch_bytes": 336674.5 * 2 * 1024,
+        "write_bytes": 950272.0 * 1024,
+        "sources_sha256": "4ede191217a1a4361659055012863361b097fe2573d636e5e0829bf06fcbca58",
         "profile": "profiles/lr_kernel_d-shell.md",
     },
 }
