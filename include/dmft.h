@@ -282,14 +282,14 @@ int dmft_sync_status(dmft_handle h, void* ws, hipStream_t stream);
  * nb_k entries of column l of Psi (<phi_n|psi_l>):
  *   N(k) = sum_l u_l u_l^dag n_F(E^ps_l - mu),  N_tot = sum_k w_k sum_l |u_l|^2 n_F(E^ps_l - mu).
  * The eigensystems do not depend on mu: one dmft_pole_eig serves every later
- * density, mu search and DOS at any mu.  Limit: nb_max + np <= 64.
+ * density, mu search and DOS at any mu.  Limit: nb_max + np <= 80.
  *
  * Per-k outputs use the padded stride mp = nb_max + np; for k with m_k < mp the
  * entries m_k .. mp-1 are zero (eigenvalue 0 with weight 0, zero vectors).
  * All calls are stream-ordered; the workspace layout is shared by all of them
  * (size from dmft_pole_workspace_size with the largest DOS grid used). */
 typedef struct dmft_poles {
-  int32_t np;              /* number of poles, 0 .. 64 - nb_max                    */
+  int32_t np;              /* number of poles, 0 .. 80 - nb_max                    */
   double beta;             /* inverse temperature (1/eV)                           */
   const double* p;         /* DEVICE [np] real pole positions p_i                  */
   const double* v;         /* DEVICE [np][nc] complex pole vectors V_i             */

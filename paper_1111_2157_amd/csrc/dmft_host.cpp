@@ -1266,8 +1266,8 @@ int check_poles(dmft_handle h, const dmft_lattice* lat, const dmft_poles* pol) {
   if (pol->np > 0 && (!pol->p || !pol->v)) return fail(h, DMFT_EINVAL, "p and v must be set when np > 0");
   if (!pol->e_dc) return fail(h, DMFT_EINVAL, "e_dc must be set");
   if (!(pol->beta > 0) || !std::isfinite(pol->beta)) return fail(h, DMFT_EINVAL, "beta must be positive and finite");
-  if (lat->nb_max + pol->np > 64)
-    return fail(h, DMFT_EUNSUPPORTED, "nb_max + np = %d exceeds 64", lat->nb_max + pol->np);
+  if (lat->nb_max + pol->np > 80)
+    return fail(h, DMFT_EUNSUPPORTED, "nb_max + np = %d exceeds 80", lat->nb_max + pol->np);
   return DMFT_OK;
 }
 

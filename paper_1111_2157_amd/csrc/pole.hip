@@ -15,13 +15,14 @@
 // The eigensystems do not depend on mu, so once they are known every further
 // N(mu) costs O(Nk (Nb + np)).
 //
-// Eigensolver: one work-group per k, the matrix and the physical rows of the
-// eigenvectors resident in LDS, cyclic two-sided Jacobi for complex Hermitian
-// matrices in the round-robin (tournament) order: in each of the m-1 steps of
-// a sweep the m/2 disjoint index pairs rotate at once.  A step is one pass
-// over the 2x2 blocks of the matrix, A <- U^dag A U with U block-diagonal in
-// the step's pairing, computed for the upper blocks and mirrored, plus the
-// same column rotation of the eigenvector rows.  A pair rotates when
+// Eigensolver: one work-group per k, the matrix (upper triangle, packed) and
+// the physical rows of the eigenvectors resident in LDS (m = nb + np <= 80),
+// cyclic two-sided Jacobi for complex Hermitian matrices in the round-robin
+// (tournament) order: in each of the m-1 steps of a sweep the m/2 disjoint
+// index pairs rotate at once.  A step is one pass over the 2x2 blocks of the
+// matrix, A <- U^dag A U with U block-diagonal in the step's pairing, computed
+// for the blocks on and above the diagonal (each stored element belongs to
+// exactly one of them), plus the same column rotation of the eigenvector rows.  A pair rotates when
 // |a_pq| > 1e-17 ||A||_F; the sweep that rotates nothing ends the iteration.
 // The rotation for a pair: with a_pq = r e^{i phi}, zeta = (a_qq - a_pp) / 2r,
 // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2),
@@ -35,7 +36,7 @@
 namespace dmft {
 namespace {
 
-constexpr int kMaxM = 64;         // largest pseudo-Hamiltonian (nb + np)
+constexpr int kMaxM = 80;         // largest pseudo-Hamiltonian (nb + np)
 constexpr int kDosThreads = 256;
 constexpr int kDosChunk = 512;    // eigenpairs per slice of the DOS sum
 constexpr int kMaxSlices = 128;
@@ -113,6 +114,19 @@ struct __align__(16) JRot {
   int rot;           // 0: identity (the pair is already diagonal)
 };
 
+// The Hermitian matrix keeps its upper triangle only, packed by rows: element
+// (r, c), r <= c, of an mq x mq matrix sits at r mq - r (r - 1) / 2 + c - r;
+// (c, r) is its conjugate.  hget/hput pick the stored element and conjugate by
+// select, so lanes reading either triangle do not diverge.
+__device__ __forceinline__ int up_idx(int r, int c, int mq) { return r * mq - ((r * (r - 1)) >> 1) + (c - r); }
+__device__ __forceinline__ double2 hget(const double2* A, int r, int c, int mq) {
+  const double2 v = A[up_idx(min(r, c), max(r, c), mq)];
+  return pz(v.x, r <= c ? v.y : -v.y);
+}
+__device__ __forceinline__ void hput(double2* A, int r, int c, int mq, double2 v) {
+  A[up_idx(min(r, c), max(r, c), mq)] = pz(v.x, r <= c ? v.y : -v.y);
+}
+
 __device__ __forceinline__ void k_window(const PoleArgs& a, int k, int& nb, int64_t& ob) {
   nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
   ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
@@ -135,9 +149,9 @@ __global__ void __launch_bounds__(NT) pole_eig_kernel(PoleArgs a) {
   k_window(a, k, nb, ob);
   const int nc = a.nc, np = a.np;
   const int m = nb + np, mq = m + (m & 1), P = mq >> 1;
-  const int lda = mq + 1, ldv = nb + 1;
-  double2* A = lds;              // mq x lda
-  double2* VT = lds + mq * lda;  // mq x ldv: row l = physical components of eigenvector l
+  const int ldv = nb + 1;
+  double2* A = lds;                          // packed upper triangle, mq (mq + 1) / 2
+  double2* VT = lds + mq * (mq + 1) / 2;     // mq x ldv: row l = physical components of eigenvector l
   const double2* S = reinterpret_cast<const double2*>(a.proj) + ob * nc;
   const double* E = a.eps + ob;
   const double2* SI = reinterpret_cast<const double2*>(a.sigma_inf);
@@ -159,26 +173,21 @@ __global__ void __launch_bounds__(NT) pole_eig_kernel(PoleArgs a) {
     double2 acc = pz(0.0, 0.0);
     for (int al = 0; al < nc; ++al) acc = pfma(pconj(S[al * nb + i]), VT[al * nb + j], acc);
     if (i == j) acc = pz(E[i] + acc.x, 0.0);
-    A[i * lda + j] = acc;
-    A[j * lda + i] = pconj(acc);
+    A[up_idx(i, j, mq)] = acc;
   }
   // coupling rows -V_i S and the pole block diag(p)
   for (int idx = t; idx < np * nb; idx += kEigThreads) {
     const int i = idx / nb, j = idx - i * nb;
     double2 acc = pz(0.0, 0.0);
     for (int al = 0; al < nc; ++al) acc = pfma(V[i * nc + al], S[al * nb + j], acc);
-    A[(nb + i) * lda + j] = pz(-acc.x, -acc.y);
-    A[j * lda + nb + i] = pz(-acc.x, acc.y);
+    A[up_idx(j, nb + i, mq)] = pz(-acc.x, acc.y);  // (j, nb + i) = conj of the coupling row
   }
   for (int idx = t; idx < np * np; idx += kEigThreads) {
     const int i = idx / np, j = idx - i * np;
-    A[(nb + i) * lda + nb + j] = pz(i == j ? a.p[i] : 0.0, 0.0);
+    if (i <= j) A[up_idx(nb + i, nb + j, mq)] = pz(i == j ? a.p[i] : 0.0, 0.0);
   }
   if (m & 1)  // odd size: one decoupled zero row/column completes the pairing
-    for (int j = t; j < mq; j += kEigThreads) {
-      A[m * lda + j] = pz(0.0, 0.0);
-      A[j * lda + m] = pz(0.0, 0.0);
-    }
+    for (int j = t; j < mq; j += kEigThreads) A[up_idx(j, m, mq)] = pz(0.0, 0.0);
   __syncthreads();
   for (int idx = t; idx < mq * nb; idx += kEigThreads) {
     const int l = idx / nb, i = idx - l * nb;
@@ -187,7 +196,7 @@ __global__ void __launch_bounds__(NT) pole_eig_kernel(PoleArgs a) {
   double ss = 0.0;
   for (int idx = t; idx < mq * mq; idx += kEigThreads) {
     const int i = idx / mq, j = idx - i * mq;
-    ss += pabs2(A[i * lda + j]);
+    if (i <= j) ss += (i == j ? 1.0 : 2.0) * pabs2(A[up_idx(i, j, mq)]);
   }
   const double tol = 1e-17 * sqrt(pole_block_sum<kEigThreads>(ss, red));
 
@@ -210,8 +219,8 @@ __global__ void __launch_bounds__(NT) pole_eig_kernel(PoleArgs a) {
           // pair t joins positions t and mq - 1 - t
           const int p = t == 0 ? 0 : 1 + (t - 1 + s) % (mq - 1);
           const int q = 1 + (mq - 2 - t + s) % (mq - 1);
-          const double2 apq = A[p * lda + q];
-          const double app = A[p * lda + p].x, aqq = A[q * lda + q].x;
+          const double2 apq = hget(A, p, q, mq);
+          const double app = A[up_idx(p, p, mq)].x, aqq = A[up_idx(q, q, mq)].x;
           const double r = sqrt(pabs2(apq));
           JRot R;
           R.c = 1.0;
@@ -252,16 +261,15 @@ __global__ void __launch_bounds__(NT) pole_eig_kernel(PoleArgs a) {
           if (R1.rot | R2.rot) {
             const int p1 = R1.pq & 0xffff, q1 = R1.pq >> 16;
             if (I == J) {
-              A[p1 * lda + p1] = pz(s_dp[I], 0.0);
-              A[q1 * lda + q1] = pz(s_dq[I], 0.0);
-              A[p1 * lda + q1] = pz(0.0, 0.0);
-              A[q1 * lda + p1] = pz(0.0, 0.0);
+              A[up_idx(p1, p1, mq)] = pz(s_dp[I], 0.0);
+              A[up_idx(q1, q1, mq)] = pz(s_dq[I], 0.0);
+              hput(A, p1, q1, mq, pz(0.0, 0.0));
             } else {
               const int p2 = R2.pq & 0xffff, q2 = R2.pq >> 16;
               const double c1 = R1.c, c2 = R2.c;
               const double2 g1 = pz(R1.sr, R1.si), g2 = pz(R2.sr, R2.si);
-              const double2 x11 = A[p1 * lda + p2], x12 = A[p1 * lda + q2];
-              const double2 x21 = A[q1 * lda + p2], x22 = A[q1 * lda + q2];
+              const double2 x11 = hget(A, p1, p2, mq), x12 = hget(A, p1, q2, mq);
+              const double2 x21 = hget(A, q1, p2, mq), x22 = hget(A, q1, q2, mq);
               // rows: p' = c p - g q, q' = conj(g) p + c q
               const double2 y11 = psub(pscal(c1, x11), pmul(g1, x21));
               const double2 y12 = psub(pscal(c1, x12), pmul(g1, x22));
@@ -272,14 +280,11 @@ __global__ void __launch_bounds__(NT) pole_eig_kernel(PoleArgs a) {
               const double2 z12 = padd(pmul(g2, y11), pscal(c2, y12));
               const double2 z21 = psub(pscal(c2, y21), pmul(pconj(g2), y22));
               const double2 z22 = padd(pmul(g2, y21), pscal(c2, y22));
-              A[p1 * lda + p2] = z11;
-              A[p1 * lda + q2] = z12;
-              A[q1 * lda + p2] = z21;
-              A[q1 * lda + q2] = z22;
-              A[p2 * lda + p1] = pconj(z11);
-              A[q2 * lda + p1] = pconj(z12);
-              A[p2 * lda + q1] = pconj(z21);
-              A[q2 * lda + q1] = pconj(z22);
+              // each mirrored pair has one slot, written by this block only
+              hput(A, p1, p2, mq, z11);
+              hput(A, p1, q2, mq, z12);
+              hput(A, q1, p2, mq, z21);
+              hput(A, q1, q2, mq, z22);
             }
           }
         }
@@ -316,7 +321,7 @@ __global__ void __launch_bounds__(NT) pole_eig_kernel(PoleArgs a) {
   }
 
   // eigenvalues in ascending order (ties by index)
-  if (t < m) s_lam[t] = A[t * lda + t].x;
+  if (t < m) s_lam[t] = A[up_idx(t, t, mq)].x;
   if (t < kMaxM) s_inv[t] = t < m ? t : 0;
   __syncthreads();
   if (t < m) {
@@ -614,7 +619,7 @@ hipError_t allow_lds(const void* fn, size_t bytes) {
 
 size_t pole_eig_lds_bytes(int nb, int np) {
   const int m = nb + np, mq = m + (m & 1);
-  return (size_t)(mq * (mq + 1) + mq * (nb + 1)) * 16;
+  return (size_t)(mq * (mq + 1) / 2 + mq * (nb + 1)) * 16;
 }
 
 template <int NT>

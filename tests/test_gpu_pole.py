@@ -58,6 +58,12 @@ def _ragged():
     return wl.lattices[1], wl.sigmas[1]
 
 
+def _batched78():
+    """Windows of 60..64 bands with 14 poles: pseudo-Hamiltonians of up to 78 rows."""
+    wl = synth.batched(nk=6, nb_lo=60, nb_hi=64, nw=16, n_iter=2)
+    return wl.lattices[1], wl.sigmas[1]
+
+
 def _w(maker):
     def f():
         wl = maker()
@@ -71,6 +77,7 @@ CASES = {
     "f-shell-m62": (_w(lambda: synth.f_shell(nk=4, nw=32)), -0.4),
     "diff-m54": (_w(lambda: synth.differentiation(nk=4, nw=32)), 0.1),
     "ragged": (_ragged, 0.2),
+    "batched-m78": (_batched78, 0.1),
     "no-poles": (_no_poles, 0.0),
     "tiny-m2": (_tiny, 0.1),
 }
@@ -220,7 +227,7 @@ def test_pole_dos(ctx, name):
     assert relerr(d1.cpu().numpy(), pole.dos(lat, sa, mu0, 0.1, [0.5])[0]) <= RTOL
 
 
-@pytest.mark.parametrize("which", ["d-shell", "f-shell"])
+@pytest.mark.parametrize("which", ["d-shell", "f-shell", "batched-iterate"])
 def test_pole_fullsize(ctx, which):
     """The benchmark's workloads at full size: sampled k-points against the
     oracle, completeness at every k, the mu search and the DOS against the
@@ -229,8 +236,13 @@ def test_pole_fullsize(ctx, which):
 
     from paper_1111_2157_amd.dyson import NEWTON, split_nk
 
-    wl = synth.d_shell() if which == "d-shell" else synth.f_shell()
-    lat, sig, mu0 = wl.lattice, wl.sigma, wl.mu
+    if which == "batched-iterate":
+        # one 14-orbital iterate of the batched workload: 4096 k, 20..64 bands, m up to 78
+        wl = synth.batched()
+        lat, sig, mu0 = wl.lattices[1], wl.sigmas[1], 0.0
+    else:
+        wl = synth.d_shell() if which == "d-shell" else synth.f_shell()
+        lat, sig, mu0 = wl.lattice, wl.sigma, wl.mu
     sa = _absolute(sig, mu0)
     print("pole full", which, flush=True)
     dl, dp, es = _gpu_eig(ctx, lat, sa)
@@ -266,9 +278,11 @@ def test_pole_errors(ctx):
     from paper_1111_2157_amd._lib import DmftError
     from paper_1111_2157_amd.dyson import Lattice, PoleSelfEnergy
 
-    wl = synth.f_shell(nk=2, nb=60, nw=8)   # 60 bands + 14 poles > 64
+    wl = synth.plain(nk=2, nb=64, nw=8)     # 64 bands + 5 + 12 poles > 80
+    extra = [(0.1 * i, np.eye(wl.lattice.nc)[i % wl.lattice.nc]) for i in range(12)]
+    sig = dataclasses.replace(wl.sigma, poles=list(wl.sigma.poles) + extra)
     with pytest.raises(DmftError) as e:
-        ctx.pole_eig(Lattice.from_host(wl.lattice), PoleSelfEnergy.from_host(wl.sigma))
+        ctx.pole_eig(Lattice.from_host(wl.lattice), PoleSelfEnergy.from_host(sig))
     assert e.value.name == "DMFT_EUNSUPPORTED"
     wl = synth.plain(nk=4, nw=8)
     lat = dataclasses.replace(wl.lattice, eps=wl.lattice.eps.copy())
