@@ -280,15 +280,16 @@ def _event_ms(fn, reps):
 
 def jacobi_step_cost(nb, npl):
     """FP64 flops and LDS bytes of one Jacobi step (every pair rotating) for one
-    k with nb bands and npl poles: m/2 (m/2 - 1)/2 off-diagonal 2x2 blocks
-    (8 complex scale-and-rotate updates of 10 flops, 4 reads and 8 writes),
-    m/2 diagonal blocks (4 writes) and m/2 nb eigenvector pairs (2 updates,
-    2 reads, 2 writes); m = nb + npl rounded up to even."""
+    k with nb bands and npl poles, with the matrix stored as its packed upper
+    triangle: m/2 (m/2 - 1)/2 off-diagonal 2x2 blocks (8 complex
+    scale-and-rotate updates of 10 flops, 4 reads and 4 writes of 16 B), m/2
+    diagonal blocks (3 writes) and m/2 nb eigenvector pairs (2 updates, 2 reads,
+    2 writes); m = nb + npl rounded up to even."""
     m = nb + npl
     m += m & 1
     p = m // 2
     flops = p * (p - 1) // 2 * 80 + p * nb * 20
-    lds = (p * (p - 1) // 2 * 12 + p * 4 + p * nb * 4) * 16
+    lds = (p * (p - 1) // 2 * 8 + p * 3 + p * nb * 4) * 16
     return flops, lds, m
 
 
