@@ -109,10 +109,13 @@ __global__ void __launch_bounds__(64) batched_lr_kernel(const BatchItem* items, 
     const BatchItem b = items[it];
     const DysonArgs a = args[b.args];
     // nbp: padded size in the low byte, column part of a 64-band item in bit 8,
-    // bit 9 set when nc <= 8 (row-layout inversions over 8 columns, else 16)
+    // bit 9 set when nc <= 8 and bit 10 when 8 < nc <= 14 (row-layout
+    // inversions over 8 or 14 columns, else 16)
     const int part = (b.nbp >> 8) & 1;
     if (b.nbp & 512)
       lr_batched_item<8>(a, b, part, sh, lane);
+    else if (b.nbp & 1024)
+      lr_batched_item<14>(a, b, part, sh, lane);
     else
       lr_batched_item<16>(a, b, part, sh, lane);
   }

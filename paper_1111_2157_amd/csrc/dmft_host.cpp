@@ -1067,10 +1067,11 @@ int batched_build(dmft_handle h, int n_iter, const dmft_lattice* const* lat, con
           int nwt = std::min(L.tile.wt, sig[s]->nw - wt * L.tile.wt);
           if (lowrank) {
             // one queue; 64-band items in two column parts (size in the low
-            // byte of nbp, part in bit 8, bit 9 set for nc <= 8)
+            // byte of nbp, part in bit 8, bit 9 set for nc <= 8, bit 10 for
+            // 8 < nc <= 14: the columns of the row-layout inversions)
             int parts = b.nbp == 64 ? 2 : 1;
             double c = (nbp * nbp * nc / parts + 2.0 * nbp * nc * nc + 4.0 * nc * nc * nc) * nkt * nwt;
-            const int small_nc = lat[s]->nc <= 8 ? 512 : 0;
+            const int small_nc = lat[s]->nc <= 8 ? 512 : lat[s]->nc <= 14 ? 1024 : 0;
             for (int part = 0; part < parts; ++part)
               small.push_back(Q{{ai, b.nbp | (part << 8) | small_nc, kt, wt}, c});
           } else {
