@@ -82,10 +82,9 @@ hipError_t launch_batched(const void* items, int n_big, int n_small, const Dyson
 }
 
 // One low-rank work item of the batched queue, per padded size.  All paths
-// share one kernel's register allocation; these choices were the fastest
-// measured (the 48-band path with per-stage projector loads spills 20 bytes
-// per lane in this kernel and is still about 9% faster than the spill-free
-// per-use reloads).
+// share one kernel's register allocation; these choices (projector fragments
+// per use for 64 bands, per stage for 48, kept for 32 and 16) were the fastest
+// measured.
 template <int NC>
 __device__ __forceinline__ void lr_batched_item(const DysonArgs& a, const BatchItem& b, int part, LRShared& sh,
                                                 int lane) {
