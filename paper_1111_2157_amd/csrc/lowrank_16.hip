@@ -4,7 +4,7 @@
 
 namespace dmft {
 using LD16 = LRSet<16, KIND_DENSITY, 14, 8, 10, 26, 30>;
-using LA16 = LRSet<16, KIND_ADJ, 13, 10, 8>;
+using LA16 = LRSet<16, KIND_ADJ, 10, 8>;
 using LT16 = LRSet<16, KIND_TRACE, 14, 12, 13, 15, 28, 30>;
 hipError_t launch_lowrank_16(int var, const DysonArgs& a, dim3 grid, hipStream_t s) {
   if (a.mode & MODE_ADJ) return LA16::launch(var, a, grid, s);
