@@ -105,9 +105,9 @@ def parse():
     ap.add_argument("--no-mu", action="store_true", help="skip the mu-search comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
     ap.add_argument("--extra", action="store_true", help="also time the other workloads")
-    ap.add_argument("--section", choices=["pole", "sc", "atom"], default=None,
-                    help="time only the pole route, the self-consistency step or the atom and energy "
-                         "sums, and print that record")
+    ap.add_argument("--section", choices=["pole", "sc", "atom", "adj"], default=None,
+                    help="time only the pole route, the self-consistency step, the atom and energy "
+                         "sums or the two adjoint passes, and print that record")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (use the default variants)")
     ap.add_argument("--batched", action="store_true", help="also time the batched workload (8 iterates, graph)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -229,6 +229,67 @@ def adjoint_pass(ctx, tune=True):
     return {"workload": wl.name, "evals_per_s": evals / sec, "ms_per_pass": sec * 1e3,
             "form": "low-rank" if lowrank else "dense", "variant": var, "flop_per_eval": fl,
             "tflops": fl * evals / sec / 1e12, "tflops_dense_count": dense_fl * evals / sec / 1e12}
+
+
+def general_vjp_pass(ctx):
+    """Forward + general vector-Jacobian product (`density_matrix_vjp`: Sigma-bar
+    and mu-bar for upstream N(k)-bar and G_loc-bar cotangents, both given) on the
+    differentiation workload, in the form the context selects (low-rank by
+    default).  Complex multiply-adds per evaluation:
+      low-rank: X and X2 (2 Nb Nc^2), Nt D S^dag and Nt D^2 S^dag (2 Nb^2 Nc),
+        P1 and P2 (3 Nb Nc^2), fifteen Nc x Nc products and inversions (15 Nc^3);
+      dense: the forward (S^dag Sigma' S, the inversion, W = S G, Z = G S^dag,
+        M = W Z: Nb^3 + 2 Nb^2 Nc + 2 Nb Nc^2) and the product (Y = Nt W^dag,
+        Z^dag Y, X = W S^dag, X^dag Gbar X^dag, Nt G: Nb^3 + Nb^2 Nc + 2 Nb Nc^2
+        + 2 Nc^3);
+    8 flop each."""
+    import numpy as np
+    import torch
+
+    from paper_1111_2157_amd import synth
+    from paper_1111_2157_amd.dyson import Lattice, SelfEnergy
+
+    wl = synth.differentiation()
+    lat, sig = Lattice.from_host(wl.lattice), SelfEnergy.from_host(wl.sigma)
+    mu = -0.8
+    rng = np.random.default_rng(7)
+    nbar = np.concatenate([(rng.standard_normal(n * n) + 1j * rng.standard_normal(n * n)) for n in wl.lattice.nb])
+    gbar = rng.standard_normal(wl.sigma.sigma.shape) + 1j * rng.standard_normal(wl.sigma.sigma.shape)
+    nbt, gbt = torch.as_tensor(nbar, device="cuda"), torch.as_tensor(gbar, device="cuda")
+    ctx.density_matrix_vjp(lat, sig, mu, nbt, gbt)  # warm-up
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    reps = 3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.density_matrix_vjp(lat, sig, mu, nbt, gbt)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    nb, nc = wl.lattice.nb_max, wl.lattice.nc
+    nbp = (nb + 15) // 16 * 16
+    var = ctx.get_variant(3, nbp)
+    lowrank = var >= 0 and bool(var & 8)
+    evals = wl.lattice.nk * wl.sigma.nw
+    dense_fl = 8.0 * (2 * nb ** 3 + 3 * nb * nb * nc + 4 * nb * nc * nc + 2 * nc ** 3)
+    fl = 8.0 * (2 * nb * nb * nc + 5 * nb * nc * nc + 15 * nc ** 3) if lowrank else dense_fl
+    return {"workload": wl.name, "evals_per_s": evals / sec, "ms_per_pass": sec * 1e3,
+            "form": "low-rank" if lowrank else "dense", "variant": var, "flop_per_eval": fl,
+            "tflops": fl * evals / sec / 1e12, "tflops_dense_count": dense_fl * evals / sec / 1e12}
+
+
+def adjoint_section(ctx, tune):
+    """The fused scalar adjoint and the general VJP on the differentiation
+    workload, after autotuning it (as the --extra run does)."""
+    from paper_1111_2157_amd import synth
+    from paper_1111_2157_amd.dyson import Lattice, SelfEnergy
+
+    if tune:
+        w = synth.differentiation()
+        ctx.autotune(Lattice.from_host(w.lattice), SelfEnergy.from_host(w.sigma), w.mu)
+    return {"fused": adjoint_pass(ctx), "general": general_vjp_pass(ctx)}
 
 
 def self_consistency(ctx):
@@ -476,7 +537,8 @@ def main():
 
         ctx = Context(0)
         rec = {"pole": lambda: pole_route(ctx, not args.no_tune), "sc": lambda: self_consistency(ctx),
-               "atom": lambda: atom_section(ctx)}[args.section]()
+               "atom": lambda: atom_section(ctx),
+               "adj": lambda: adjoint_section(ctx, not args.no_tune)}[args.section]()
         print(json.dumps({"section": args.section, "result": rec}), flush=True)
         return
     import torch
@@ -544,6 +606,7 @@ def main():
             extra[w.name] = {"evals_per_s": ev / sc, "ms_per_pass": sc * 1e3, "kernel": kn,
                              "kernel_tflops": f / (km / max(ln, 1) / 1e3) / 1e12}
         extra["adjoint (N_tot, dN/dmu, dN/dSigma)"] = adjoint_pass(ctx)
+        extra["general VJP (Sigma-bar, mu-bar)"] = general_vjp_pass(ctx)
         extra["self-consistency (E_imp, Delta)"] = self_consistency(ctx)
         extra["pole route"] = pole_route(ctx, not args.no_tune)
         extra["atom and energy"] = atom_section(ctx)

@@ -158,7 +158,16 @@ int dmft_ntot(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, dou
  *   nk_bar:    DEVICE, N(k) layout, or NULL (zero);
  *   gloc_bar:  DEVICE [nw][nc][nc], or NULL (zero);
  *   sigma_bar: DEVICE [nw][nc][nc] complex, written;
- *   mu_bar:    DEVICE [1], written, or NULL. */
+ *   mu_bar:    DEVICE [1], written, or NULL.
+ * Kernel kind 3 (see dmft_variants).  The low-rank form (the default) uses,
+ * with Gl = S G S^dag, Rl = I + Gl Sigma', Rr = I + Sigma' Gl, X_j = S D^j S^dag
+ * and Nt = nk_bar + nk_bar^dag,
+ *   sigma_bar_n^dag = sum_k [ (1/beta) Rl S D Nt D S^dag Rr + w_k Gl gloc_bar_n^dag Gl ],
+ *   S G^2 S^dag     = Rl X_2 Rr,
+ *   tr(Nt G^2)      = sum_v Nt_vv d_v^2 + tr(R S (D Nt D^2 + D^2 Nt D) S^dag)
+ *                     + tr(R X_2 R S D Nt D S^dag),
+ * and covers band windows up to 64; the dense adjoint kernel (code 0) windows
+ * up to 48 (DMFT_EUNSUPPORTED above). */
 int density_matrix_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu,
                        int tail_order, const double* nk_bar, const double* gloc_bar,
                        double* sigma_bar, double* mu_bar, void* ws, size_t ws_bytes,
@@ -239,7 +248,9 @@ int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
 
 /* Kernel variants.  kind 0 = density pass (density_matrix, gloc_compute),
  * kind 1 = trace pass (dmft_ntot, find_mu), kind 2 = fused scalar adjoint
- * (dmft_ntot_vjp; code 0 there is the dense adjoint kernel); nbp = padded band-window size
+ * (dmft_ntot_vjp), kind 3 = general vector-Jacobian product
+ * (density_matrix_vjp; not autotuned); code 0 of kinds 2 and 3 is the dense
+ * adjoint kernel; nbp = padded band-window size
  * (16, 32, 48 or 64).  dmft_variants writes up to max variant codes into out
  * (HOST) and returns their number (the first is the default); dmft_set_variant
  * pins one for later calls on this handle (var = -1 restores the default) and

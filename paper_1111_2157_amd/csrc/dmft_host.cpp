@@ -33,7 +33,7 @@ struct Tile {
   int kt = 1, wt = 1;
 };
 
-enum { KIND_DENSITY = 0, KIND_TRACE = 1, KIND_ADJOINT = 2 };
+enum { KIND_DENSITY = 0, KIND_TRACE = 1, KIND_ADJOINT = 2, KIND_GENERAL = 3 };
 
 // One padded-size bucket of k-points.
 struct Bucket {
@@ -170,7 +170,7 @@ Tile choose_tile(const dmft_handle h, int kind, int nk, int nw, int nbp) {
 }
 
 const char* kind_name(int kind) {
-  return kind == KIND_DENSITY ? "density" : kind == KIND_TRACE ? "trace" : "adjoint";
+  return kind == KIND_DENSITY ? "density" : kind == KIND_TRACE ? "trace" : kind == KIND_ADJOINT ? "adjoint" : "general";
 }
 
 int choose_var(const dmft_handle h, int kind, int nbp) {
@@ -361,6 +361,14 @@ int run_dyson(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, con
       DysonArgs aa = a;
       aa.mode = MODE_ADJ;
       HIPCHK(h, launch_dyson(b.nbp, choose_var(h, KIND_ADJOINT, b.nbp), aa, b.n_ktiles, s));
+    } else if (adj.gen == 1 && (choose_var(h, KIND_GENERAL, b.nbp) & 8)) {
+      // general vector-Jacobian product in the low-rank form (same partials as the dense kernel)
+      DysonArgs aa = a;
+      aa.mode = MODE_GEN;
+      aa.nbar = adj.nbar;
+      aa.off_n = L.ragged ? (const int64_t*)(ws + L.meta_offn) : nullptr;
+      aa.gbar = adj.gbar;
+      HIPCHK(h, launch_dyson(b.nbp, choose_var(h, KIND_GENERAL, b.nbp), aa, b.n_ktiles, s));
     } else if (adj.gen >= 0) {
       if (b.nbp > 48) return fail(h, DMFT_EUNSUPPORTED, "the dense adjoint supports band windows up to 48");
       HIPCHK(h, launch_adjoint(b.nbp, adj.gen, a, adj.nbar, L.ragged ? (const int64_t*)(ws + L.meta_offn) : nullptr,
@@ -609,7 +617,7 @@ int ntot_vjp_impl(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
 extern "C" {
 
 int dmft_variants(int kind, int nbp, int* out, int max) {
-  if (kind < 0 || kind > 2) return 0;
+  if (kind < 0 || kind > 3) return 0;
   int v[16];
   int n = dyson_variants(nbp, kind, v, 16);
   for (int i = 0; i < n && i < max && out; ++i) out[i] = v[i];
@@ -617,7 +625,7 @@ int dmft_variants(int kind, int nbp, int* out, int max) {
 }
 
 int dmft_get_variant(dmft_handle h, int kind, int nbp) {
-  if (!h || kind < 0 || kind > 2) return -1;
+  if (!h || kind < 0 || kind > 3) return -1;
   return choose_var(h, kind, nbp);
 }
 
@@ -680,7 +688,6 @@ int density_matrix_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma*
   Layout L;
   int r = prepare(h, lat, sig, ws, ws_bytes, L, KIND_ADJOINT, stream);
   if (r) return r;
-  if (L.nbp_max > 48) return fail(h, DMFT_EUNSUPPORTED, "the adjoint supports band windows up to 48");
   char* w = (char*)ws;
   AdjReq adj;
   adj.gen = 1;

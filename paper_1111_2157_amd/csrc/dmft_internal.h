@@ -16,6 +16,9 @@ enum : int {
   MODE_TRACE = 4,  // accumulate sum_n Re tr G and sum_n Re tr G^2 per (frequency tile, k)
   MODE_ADJ = 8,    // low-rank fused scalar adjoint: MODE_TRACE's sums (stride 3 in tpart) and
                    // w_k S G^2 S^dag per (k tile, n) in xpart
+  MODE_GEN = 16,   // low-rank general vector-Jacobian product: Sigmabar_n per (k tile, n) in xpart
+                   // and the mubar share per (frequency tile, k) in tpart[.][.][2] (stride 3), as
+                   // the dense adjoint kernel writes them
 };
 
 // Error bits raised on the device.
@@ -49,6 +52,9 @@ struct DysonArgs {
   double* xpart;               // MODE_GLOC: [n_ktiles_total][nw][256] complex, lane order
   double* tpart;               // MODE_TRACE:[n_wtiles][nk][2]
   int* err;                    // error word
+  const double* nbar;          // MODE_GEN: complex N(k) cotangent (N(k) layout) or null
+  const int64_t* off_n;        // MODE_GEN: [nk+1] offsets into nbar (ragged) or null (uniform)
+  const double* gbar;          // MODE_GEN: complex G_loc cotangent [nw][nc][nc] or null
 };
 
 struct EpilogueArgs {

@@ -23,10 +23,11 @@ int lowrank_variants(int nbp, int kind, int* out, int max);
 bool dyson_supported(int nbp);
 
 // Dense variants first (the first one is the default), then the low-rank ones.
-// Kind 2 (fused scalar adjoint): the low-rank variants first, then code 0 for
-// the dense adjoint kernel, which exists up to 48 bands.
+// Kinds 2 (fused scalar adjoint) and 3 (general vector-Jacobian product): the
+// low-rank variants first, then code 0 for the dense adjoint kernel, which
+// exists up to 48 bands.
 int dyson_variants(int nbp, int kind, int* out, int max) {
-  if (kind == 2) {
+  if (kind == 2 || kind == 3) {
     int n = lowrank_variants(nbp, kind, out, max);
     if (nbp <= 48 && dyson_supported(nbp) && n < max) out[n++] = 0;
     return n;

@@ -289,8 +289,10 @@ __device__ __forceinline__ void load_pt(Proj<NBP>& pr, const double2* P, int nc,
     }
 }
 
-// KIND_ADJ (fused scalar adjoint of N_tot) exists in the low-rank form only.
-enum { KIND_DENSITY = 0, KIND_TRACE = 1, KIND_ADJ = 2 };
+// KIND_ADJ (fused scalar adjoint of N_tot) and KIND_GEN (general
+// vector-Jacobian product) exist in the low-rank form only; the dense form of
+// both is adjoint.hip.
+enum { KIND_DENSITY = 0, KIND_TRACE = 1, KIND_ADJ = 2, KIND_GEN = 3 };
 
 template <int NBP, int KIND, int SLDS>
 struct KernelShared {

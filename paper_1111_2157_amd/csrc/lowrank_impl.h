@@ -38,7 +38,17 @@
 //      w_k S G^2 S^dag (adjoint kind: the fused scalar adjoint of N_tot,
 //      dN/dSigma_n = (2/beta) [sum_k w_k S G^2 S^dag]^dag), with
 //      S G = (I + X R) S D, G S^dag = D S^dag (I + R X) and I + X R = Gl X^-1 = I + Gl Sigma':
-//          S G^2 S^dag = (I + Gl Sigma') X2 (I + Sigma' Gl).
+//          S G^2 S^dag = (I + Gl Sigma') X2 (I + Sigma' Gl);
+//      or (general kind) the vector-Jacobian product for cotangents Nbar_k of
+//      N(k) and Gbar_n of G_loc.  With Nt = Nbar + Nbar^dag, Rl = I + Gl Sigma'
+//      (= Gl X^-1) and Rr = I + Sigma' Gl (= X^-1 Gl), S G = Rl S D and
+//      G S^dag = D S^dag Rr, so the dense kernel's S G^dag C G^dag S^dag becomes
+//          Sigmabar_n^dag share = (1/beta) Rl P1 Rr + w_k Gl Gbar_n^dag Gl,   P1 = S D Nt D S^dag,
+//      and from G^2 = D^2 + D^2 S^dag R S D + D S^dag R S D^2 + D S^dag R X2 R S D
+//          tr(Nt G^2) = sum_v Nt_vv d_v^2 + tr(R P2) + tr(R X2 R P1),
+//          P2 = S (D Nt D^2 + D^2 Nt D) S^dag;
+//      P1 and P2 come from the two band-window products Nt D S^dag and
+//      Nt D^2 S^dag (O(nb^2 nc)), and mubar also takes -w_k Re<Gbar_n, Rl X2 Rr>.
 //
 // Operand bookkeeping of the 16x16x4 instruction: a matrix M used as the A
 // operand comes from registers holding M^T in the output layout (lane
@@ -283,6 +293,18 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
     const double* eps = a.eps + ob;
     const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
     const double wk = a.wk[k];
+    // general product: Nbar_k (row-major) and the real diagonal of Nt = Nbar + Nbar^dag at
+    // band 16 t + c16
+    const double2* ntb = nullptr;
+    double ntd[KIND == KIND_GEN ? T : 1];
+    if constexpr (KIND == KIND_GEN) {
+      if (a.nbar) ntb = reinterpret_cast<const double2*>(a.nbar) + (a.off_n ? a.off_n[k] : (int64_t)k * nb * nb);
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int v = 16 * t + c16;
+        ntd[t] = (ntb && v < nb) ? 2.0 * ntb[(int64_t)v * nb + v].x : 0.0;
+      }
+    }
     // projector fragments: RL = 0 kept in registers for the whole k; RL = 1
     // loaded per group of four frequencies at the start of the stage that
     // uses them, so that they do not occupy registers in the other stages;
@@ -307,7 +329,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
 #pragma unroll
         for (int c = 0; c < CT; ++c) sacc[t][c].zero();
     }
-    double trg = 0.0, trg2 = 0.0;
+    double trg = 0.0, trg2 = 0.0, mub = 0.0;
 
     for (int n = n0; n < n1; n += 4) {
       // 0. d_r of the four frequencies, each computed once and read from LDS by
@@ -388,7 +410,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
         // products below (the compiler cannot move it above the previous
         // frequency's stores)
         double2* part = reinterpret_cast<double2*>(a.xpart) + ((int64_t)(a.ktile_base + ktile) * a.nw + nf) * 256;
-        const bool part_rmw = kk != kk0 && ((KIND == KIND_DENSITY && want_x) || KIND == KIND_ADJ);
+        const bool part_rmw = kk != kk0 && ((KIND == KIND_DENSITY && want_x) || KIND == KIND_ADJ || KIND == KIND_GEN);
         double2 prev[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -403,13 +425,13 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
             dsum[t].y += dcol[t].y;
           }
         }
-        v4d glr, gli, gltr, glti;  // Gl and (adjoint kind) Gl^T in the output layout
+        v4d glr, gli, gltr, glti;  // Gl and (adjoint kinds) Gl^T in the output layout
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           double2 v = sh.buf[f][(q + 4 * i) * 17 + c16];
           glr[i] = v.x;
           gli[i] = v.y;
-          if constexpr (KIND == KIND_ADJ) {
+          if constexpr (KIND == KIND_ADJ || KIND == KIND_GEN) {
             double2 u = sh.buf[f][c16 * 17 + q + 4 * i];
             gltr[i] = u.x;
             glti[i] = u.y;
@@ -499,6 +521,201 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
               if (q + 4 * i < nc && c16 < nc)
                 part[i * 64 + lane] = make_double2(wk * glr[i] + prev[i].x, wk * gli[i] + prev[i].y);
           }
+        } else if constexpr (KIND == KIND_GEN) {
+          double chk = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
+          if (!__builtin_isfinite(chk)) nonfinite = 1;
+          auto ptf = [&](int t, int i) -> double2 {
+            return RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
+                           : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
+          };
+          // every lane has read Gl of this frequency: its LDS tile is free for transposes
+          wave_sync();
+          // Rr = I + Sigma' Gl
+          CAcc<M3> rra;
+          {
+            v4d id = {0.0, 0.0, 0.0, 0.0}, z = id;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) id[i] = (hasdiag && idg == i) ? 1.0 : 0.0;
+            rra.set(id, z);
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (j >= kc) break;
+            rra.mac(sa_r[j], sa_i[j], glr[j], gli[j]);
+          }
+          const v4d rrr = rra.re(), rri = rra.im();
+          // X2 = S D^2 S^dag
+          CAcc<M3> x2a;
+          x2a.zero();
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              if (16 * t + 4 * i >= nb) break;
+              const double2 s = ptf(t, i);
+              const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
+              const double2 a2 = cmul(cmul(s, dd), dd);
+              x2a.mac_cb(a2.x, a2.y, s.x, s.y);
+            }
+          const v4d x2r = x2a.re(), x2i = x2a.im();
+          // this k's share of Sigmabar_n^dag
+          CAcc<M3> phi;
+          phi.zero();
+          if (ntb) {
+            // Y1 = Nt D S^dag and Y2 = Nt D^2 S^dag, one 16-row tile at a time, each
+            // tile contracted at once into P1 = S D Y1 and P2 = S D Y2 + S D^2 Y1
+            const double2* nt = fresh(ntb);
+            CAcc<M3> p1a, p2a;
+            p1a.zero();
+            p2a.zero();
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+              if (16 * t >= nb) break;
+              const int row = 16 * t + c16;
+              CAcc<M3> y1a, y2a;
+              y1a.zero();
+              y2a.zero();
+#pragma unroll
+              for (int b = 0; b < T; ++b)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  if (16 * b + 4 * j >= nb) break;
+                  const int col = 16 * b + 4 * j + q;
+                  double2 ntv = make_double2(0.0, 0.0);
+                  if (row < nb && col < nb) {
+                    const double2 u = nt[row * nb + col], v = nt[col * nb + row];
+                    ntv = make_double2(u.x + v.x, u.y - v.y);
+                  }
+                  const double2 s = ptf(b, j);
+                  const double2 dd = sh.dtab[f][col];
+                  const double2 b1 = cmul(dd, make_double2(s.x, -s.y));
+                  const double2 b2 = cmul(dd, b1);
+                  y1a.mac(ntv.x, ntv.y, b1.x, b1.y);
+                  y2a.mac(ntv.x, ntv.y, b2.x, b2.y);
+                }
+              const v4d y1r = y1a.re(), y1i = y1a.im(), y2r = y2a.re(), y2i = y2a.im();
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if (16 * t + 4 * i >= nb) break;
+                const double2 s = ptf(t, i);
+                const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
+                const double2 a1 = cmul(s, dd), a2 = cmul(a1, dd);
+                p1a.mac(a1.x, a1.y, y1r[i], y1i[i]);
+                p2a.mac(a1.x, a1.y, y2r[i], y2i[i]);
+                p2a.mac(a2.x, a2.y, y1r[i], y1i[i]);
+              }
+            }
+            const v4d p1r = p1a.re(), p1i = p1a.im(), p2r = p2a.re(), p2i = p2a.im();
+            // Re tr(Nt G^2) = sum_v Nt_vv Re d_v^2 + Re tr(R P2) + Re tr(E F),
+            // E = R X2, F = R P1 (formed transposed: F^T = P1^T R^T)
+            CAcc<M3> ea, fta;
+            ea.zero();
+            fta.zero();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              ea.mac(rtr[j], rti[j], x2r[j], x2i[j]);
+              fta.mac(p1r[j], p1i[j], rtr[j], rti[j]);
+            }
+            double tn = re_dot4(rtr, rti, p2r, p2i) + re_dot4(ea.re(), ea.im(), fta.re(), fta.im());
+            if (q == 0) {
+#pragma unroll
+              for (int t = 0; t < T; ++t) tn += ntd[t] * (dcol[t].x * dcol[t].x - dcol[t].y * dcol[t].y);
+            }
+            mub -= tn / beta;
+            // Rl (P1 / beta) Rr = Y + Gl (Sigma' Y),  Y = (P1 / beta) Rr
+            const double ib = 1.0 / beta;
+            v4d p1tr, p1ti;
+            tile_transpose(p1r * ib, p1i * ib, p1tr, p1ti, sh.buf[f], q, c16);
+            CAcc<M3> ya;
+            ya.zero();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              ya.mac(p1tr[j], p1ti[j], rrr[j], rri[j]);
+            }
+            const v4d yr = ya.re(), yi = ya.im();
+            CAcc<M3> za;
+            za.zero();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              za.mac(sa_r[j], sa_i[j], yr[j], yi[j]);
+            }
+            const v4d zr = za.re(), zi = za.im();
+            phi.set(yr, yi);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              phi.mac(gltr[j], glti[j], zr[j], zi[j]);
+            }
+          }
+          if (a.gbar) {
+            const double2* gb = reinterpret_cast<const double2*>(a.gbar) + (int64_t)nf * nc * nc;
+            // M = S G^2 S^dag = Rl X2 Rr = Y + Gl (Sigma' Y),  Y = X2 Rr; mubar takes -w_k Re<Gbar, M>
+            v4d x2tr, x2ti;
+            tile_transpose(x2r, x2i, x2tr, x2ti, sh.buf[f], q, c16);
+            CAcc<M3> ya;
+            ya.zero();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              ya.mac(x2tr[j], x2ti[j], rrr[j], rri[j]);
+            }
+            const v4d yr = ya.re(), yi = ya.im();
+            CAcc<M3> za;
+            za.zero();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              za.mac(sa_r[j], sa_i[j], yr[j], yi[j]);
+            }
+            const v4d zr = za.re(), zi = za.im();
+            CAcc<M3> ma;
+            ma.set(yr, yi);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              ma.mac(gltr[j], glti[j], zr[j], zi[j]);
+            }
+            const v4d mr = ma.re(), mi = ma.im();
+            double gm = 0.0;
+            double hb_r[4], hb_i[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int al = q + 4 * i;
+              const bool in = al < nc && c16 < nc;
+              const double2 v = in ? gb[al * nc + c16] : make_double2(0.0, 0.0);
+              gm += v.x * mr[i] + v.y * mi[i];
+              // w_k conj(Gbar)[c16][q + 4 i]: registers of (w_k conj(Gbar))^T
+              const double2 u = in ? gb[c16 * nc + al] : make_double2(0.0, 0.0);
+              hb_r[i] = wk * u.x;
+              hb_i[i] = -wk * u.y;
+            }
+            mub -= wk * gm;
+            // + w_k Gl Gbar^dag Gl = H Gl,  H^T = w_k conj(Gbar) Gl^T
+            CAcc<M3> ha;
+            ha.zero();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              ha.mac(hb_r[j], hb_i[j], gltr[j], glti[j]);
+            }
+            const v4d htr = ha.re(), hti = ha.im();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              phi.mac(htr[j], hti[j], glr[j], gli[j]);
+            }
+          }
+          // stored as Sigmabar_n = (share)^dag, the dense adjoint's partial layout
+          v4d ftr, fti;
+          tile_transpose(phi.re(), phi.im(), ftr, fti, sh.buf[f], q, c16);
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (q + 4 * i < nc && c16 < nc) part[i * 64 + lane] = make_double2(ftr[i] + prev[i].x, prev[i].y - fti[i]);
         } else {
           // X2 = S D^2 S^dag, X3 = S D^3 S^dag of this frequency
           CAcc<M3> x2a, x3a;
@@ -611,7 +828,18 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
             sp[e * 64 + lane] = v;
           }
     }
-    if constexpr (KIND != KIND_DENSITY) {
+    if constexpr (KIND == KIND_GEN) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) mub += __shfl_xor(mub, off);
+      if (!__builtin_isfinite(mub)) nonfinite = 1;
+      if (lane == 0) {
+        // [unused, unused, mubar share] in the adjoint layout
+        double* tp = a.tpart + ((int64_t)wtile * a.nk + k) * 3;
+        tp[0] = 0.0;
+        tp[1] = 0.0;
+        tp[2] = mub;
+      }
+    } else if constexpr (KIND != KIND_DENSITY) {
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
         trg += __shfl_xor(trg, off);

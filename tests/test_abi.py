@@ -92,3 +92,21 @@ def test_bench_jacobi_cost_matches_the_hand_count():
     assert (fl, lds, m) == (210 * 80 + 21 * 32 * 20, (210 * 8 + 21 * 3 + 21 * 32 * 4) * 16, 42)
     fl, lds, m = bench.jacobi_step_cost(12, 5)   # odd size: padded to 18
     assert m == 18 and fl == 36 * 80 + 9 * 12 * 20
+
+
+def test_variant_lists_of_the_adjoint_kinds():
+    """Kinds 2 and 3 (fused scalar adjoint, general product) list low-rank codes
+    (bit 3) first, the default, then the dense adjoint kernel (code 0) where it
+    exists (padded windows up to 48); kind 4 does not exist."""
+    from paper_1111_2157_amd import _lib
+
+    lib = _lib.load()
+    buf = (ctypes.c_int * 16)()
+    for kind in (2, 3):
+        for nbp in (16, 32, 48, 64):
+            n = lib.dmft_variants(kind, nbp, buf, 16)
+            codes = list(buf[:n])
+            assert n >= 1 and codes[0] & 8, (kind, nbp, codes)
+            assert (0 in codes) == (nbp <= 48), (kind, nbp, codes)
+            assert all(c & 8 for c in codes if c != 0)
+    assert lib.dmft_variants(4, 32, buf, 16) == 0

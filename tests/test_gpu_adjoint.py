@@ -47,27 +47,123 @@ def test_scalar_adjoint_matches_oracle(ctx, name, maker, mu):
         assert relerr(sb[nn], ref[nn]) <= 1e-10, nn
 
 
-@pytest.mark.parametrize("name,maker,mu", CASES)
-def test_general_vjp_matches_oracle(ctx, name, maker, mu):
+GEN_CASES = CASES + [
+    ("ragged-to-64", lambda: synth.batched(nk=6, nb_lo=40, nb_hi=64, nw=20, n_iter=1), 0.1),
+    ("f-shell-nb60", lambda: synth.f_shell(nk=3, nb=60, nc=14, nw=16, beta=20.0), 0.0),
+]
+
+
+def _padded_sizes(lat):
+    return sorted({(int(n) + 15) // 16 * 16 for n in lat.nb})
+
+
+@pytest.mark.parametrize("form", ["lowrank", "dense", "mixed"])
+@pytest.mark.parametrize("name,maker,mu", GEN_CASES)
+def test_general_vjp_matches_oracle(ctx, name, maker, mu, form):
+    """density_matrix_vjp against the oracle in the low-rank form (the default),
+    the dense adjoint kernel (code 0), and both at once on a ragged lattice
+    (dense on the smallest padded size), whose partial sums then mix forms."""
     import torch
 
     from paper_1111_2157_amd.dyson import Lattice, SelfEnergy
 
     wl = maker()
     lat, sig = wl.lattice, wl.sigma
+    sizes = _padded_sizes(lat)
+    if form == "dense" and sizes[-1] > 48:
+        pytest.skip("the dense adjoint kernel covers band windows up to 48")
+    if form == "mixed" and len(sizes) < 2:
+        pytest.skip("needs band windows of several padded sizes")
     rng = np.random.default_rng(5)
     nbar = [rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) for n in lat.nb]
     gbar = rng.standard_normal(sig.sigma.shape) + 1j * rng.standard_normal(sig.sigma.shape)
     dl, ds = Lattice.from_host(lat), SelfEnergy.from_host(sig)
     nbt = torch.as_tensor(np.concatenate([m.ravel() for m in nbar]), device="cuda")
     gbt = torch.as_tensor(gbar, device="cuda")
-    for use_n, use_g in ((True, True), (True, False), (False, True)):
-        sb, mb = ctx.density_matrix_vjp(dl, ds, mu, nbt if use_n else None, gbt if use_g else None)
+    try:
+        for p in sizes:
+            if form == "dense" or (form == "mixed" and p == sizes[0]):
+                ctx.set_variant(3, p, 0)
+            else:
+                assert ctx.get_variant(3, p) & 8
+        for use_n, use_g in ((True, True), (True, False), (False, True)):
+            sb, mb = ctx.density_matrix_vjp(dl, ds, mu, nbt if use_n else None, gbt if use_g else None)
+            sb, mb = sb.cpu().numpy(), float(mb.cpu().numpy()[0])
+            ctx.sync_status()
+            ref, mref = oracle.vjp(lat, sig, mu, nbar=nbar if use_n else None, gbar=gbar if use_g else None)
+            assert abs(mb - mref) <= 1e-10 * max(1.0, abs(mref)), (use_n, use_g, mb, mref)
+            assert relerr(sb, ref) <= 1e-10, (use_n, use_g)
+    finally:
+        for p in sizes:
+            ctx.set_variant(3, p, -1)
+
+
+@pytest.mark.parametrize("var", [8, 9, 24])
+def test_general_vjp_lowrank_variants(ctx, var):
+    """Every compiled low-rank variant of the general product on a 40-band
+    case against the oracle."""
+    import torch
+
+    from paper_1111_2157_amd.dyson import Lattice, SelfEnergy
+
+    if var not in ctx.variants(3, 48):
+        pytest.skip("variant not compiled for 48 bands")
+    wl = synth.differentiation(nk=4, nw=20)
+    lat, sig = wl.lattice, wl.sigma
+    rng = np.random.default_rng(11)
+    nbar = [rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) for n in lat.nb]
+    gbar = rng.standard_normal(sig.sigma.shape) + 1j * rng.standard_normal(sig.sigma.shape)
+    nbt = torch.as_tensor(np.concatenate([m.ravel() for m in nbar]), device="cuda")
+    gbt = torch.as_tensor(gbar, device="cuda")
+    try:
+        ctx.set_variant(3, 48, var)
+        sb, mb = ctx.density_matrix_vjp(Lattice.from_host(lat), SelfEnergy.from_host(sig), -0.4, nbt, gbt)
         sb, mb = sb.cpu().numpy(), float(mb.cpu().numpy()[0])
         ctx.sync_status()
-        ref, mref = oracle.vjp(lat, sig, mu, nbar=nbar if use_n else None, gbar=gbar if use_g else None)
-        assert abs(mb - mref) <= 1e-10 * max(1.0, abs(mref)), (use_n, use_g, mb, mref)
-        assert relerr(sb, ref) <= 1e-10, (use_n, use_g)
+    finally:
+        ctx.set_variant(3, 48, -1)
+    ref, mref = oracle.vjp(lat, sig, -0.4, nbar=nbar, gbar=gbar)
+    assert abs(mb - mref) <= 1e-10 * max(1.0, abs(mref))
+    assert relerr(sb, ref) <= 1e-10
+
+
+def test_general_vjp_fullsize_forms_agree(ctx):
+    """At the differentiation workload's full size (Nk=1024, Nb=40, Nc=14,
+    Nw=2048) the low-rank and the dense general product agree to 1e-10, and with
+    Nbar_k = w_k I and no G_loc cotangent the general product equals the fused
+    scalar adjoint (dN_tot/dSigma, dN_tot/dmu)."""
+    import torch
+
+    from paper_1111_2157_amd.dyson import Lattice, SelfEnergy
+
+    wl = synth.differentiation()
+    lat, sig = wl.lattice, wl.sigma
+    dl, ds = Lattice.from_host(lat), SelfEnergy.from_host(sig)
+    mu = -0.8
+    rng = np.random.default_rng(3)
+    nbar = np.concatenate([(rng.standard_normal(n * n) + 1j * rng.standard_normal(n * n)) for n in lat.nb])
+    gbar = rng.standard_normal(sig.sigma.shape) + 1j * rng.standard_normal(sig.sigma.shape)
+    nbt, gbt = torch.as_tensor(nbar, device="cuda"), torch.as_tensor(gbar, device="cuda")
+    assert ctx.get_variant(3, 48) & 8
+    sl, ml = ctx.density_matrix_vjp(dl, ds, mu, nbt, gbt)
+    sl, ml = sl.cpu().numpy(), float(ml.cpu().numpy()[0])
+    ctx.sync_status()
+    try:
+        ctx.set_variant(3, 48, 0)
+        sd, md = ctx.density_matrix_vjp(dl, ds, mu, nbt, gbt)
+        sd, md = sd.cpu().numpy(), float(md.cpu().numpy()[0])
+        ctx.sync_status()
+    finally:
+        ctx.set_variant(3, 48, -1)
+    assert relerr(sl, sd) <= 1e-10
+    assert abs(ml - md) <= 1e-10 * max(1.0, abs(md))
+    eye = np.concatenate([(lat.wk[k] * np.eye(n)).ravel() for k, n in enumerate(lat.nb)]).astype(np.complex128)
+    sg, mg = ctx.density_matrix_vjp(dl, ds, mu, torch.as_tensor(eye, device="cuda"), None)
+    out, sf = ctx.dmft_ntot_vjp(dl, ds, mu)
+    sg, mg, out, sf = sg.cpu().numpy(), float(mg.cpu().numpy()[0]), out.cpu().numpy(), sf.cpu().numpy()
+    ctx.sync_status()
+    assert relerr(sg, sf) <= 1e-10
+    assert abs(mg - out[1]) <= 1e-10 * abs(out[1])
 
 
 def test_dn_dsigma_central_differences_on_gpu(ctx):
