@@ -38,26 +38,42 @@ LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
 
 # HBM traffic of the timed kernel per launch, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch, scaled by 2 and 1 as a plain 1 GiB copy reads
-# under --copy-calibration), recorded in profiles/lr_kernel_d-shell.md.  It is
-# valid only for the kernel sources it was measured on (their SHA-256), the same
-# workload and the same tuned variant; otherwise "traffic" is null.
+# under --copy-calibration), recorded in profiles/lr_kernel_d-shell.md, for each
+# frequency tile (kt, wt) the autotuner may keep: the partial sums it writes
+# depend on the tile.  Valid only for the kernel sources it was measured on
+# (their SHA-256), the same workload, variant and tile; otherwise "traffic" is null.
+_D32 = "d-shell-Nk512-Nb32-Nc10-Nw1024"
+_SHA = "86264ad6c65c99acf1848bfe0f1dc02f35b0dd76437db7118f6ce70bb8cdfb94"
 TRAFFIC = {
-    ("d-shell-Nk512-Nb32-Nc10-Nw1024", 32, 10): {
-        "fetch_bytes": 336674.5 * 2 * 1024,
-        "write_bytes": 950272.0 * 1024,
-        "sources_sha256": "4ede191217a1a4361659055012863361b097fe2573d636e5e0829bf06fcbca58",
-        "profile": "profiles/lr_kernel_d-shell.md",
-    },
+    (_D32, 32, 10, 2, 256): {"fetch_bytes": 336678.5 * 2 * 1024, "write_bytes": 851968.0 * 1024},
+    (_D32, 32, 10, 2, 128): {"fetch_bytes": 342055.5 * 2 * 1024, "write_bytes": 884736.0 * 1024},
+    (_D32, 32, 10, 2, 64): {"fetch_bytes": 345257.5 * 2 * 1024, "write_bytes": 950272.0 * 1024},
+    (_D32, 32, 10, 2, 32): {"fetch_bytes": 351661.75 * 2 * 1024, "write_bytes": 1081344.0 * 1024},
 }
+for _r in TRAFFIC.values():
+    _r.update(sources_sha256=_SHA, profile="profiles/lr_kernel_d-shell.md")
 TRAFFIC_SOURCES = ["paper_1111_2157_amd/csrc/lowrank_impl.h", "paper_1111_2157_amd/csrc/dyson_impl.h",
                    "paper_1111_2157_amd/csrc/lowrank_32.hip"]
 
 
-def measured_traffic(workload, nbp, var):
+def tuned_tile(tune):
+    """(kt, wt) of the density pass the autotuner kept, from its report, or None."""
+    import re
+
+    for line in (tune or {}).get("best", []):
+        m = re.match(r"best density: var=\d+ kt=(\d+) wt=(\d+)", line)
+        if m:
+            return int(m.group(1)), int(m.group(2))
+    return None
+
+
+def measured_traffic(workload, nbp, var, tile):
     """Counter-measured HBM bytes per launch of this kernel, or None."""
     import hashlib
 
-    rec = TRAFFIC.get((workload, nbp, var))
+    if tile is None:
+        return None
+    rec = TRAFFIC.get((workload, nbp, var) + tuple(tile))
     if rec is None:
         return None
     h = hashlib.sha256()
@@ -561,7 +577,8 @@ def main():
     evals = nk * nw
     kname, fpe = density_kernel(ctx, nb, nc)
     nbp = (nb + 15) // 16 * 16
-    traffic = measured_traffic(wl.name, nbp, ctx.get_variant(0, nbp))
+    tile = tuned_tile(tune)
+    traffic = measured_traffic(wl.name, nbp, ctx.get_variant(0, nbp), tile)
     fl = fpe * evals
     kavg = kms / max(launches, 1) / 1e3
     achieved = fl / kavg / 1e12
@@ -586,7 +603,8 @@ def main():
                      "traffic_unit": "bytes per launch (HBM, counters)",
                      "traffic_gbps": ((traffic["fetch_bytes"] + traffic["write_bytes"]) / kavg / 1e9) if traffic else None,
                      "traffic_profile": traffic["profile"] if traffic else None,
-                     "kernel": kname, "kernel_ms": kavg * 1e3, "flop_per_eval": fpe,
+                     "kernel": kname, "kernel_tile": list(tile) if tile else None,
+                     "kernel_ms": kavg * 1e3, "flop_per_eval": fpe,
                      "dense_flop_per_eval": flops_per_eval(nb, nc)},
         "autotune": tune,
     }

@@ -129,7 +129,8 @@ def test_general_vjp_lowrank_variants(ctx, var):
 
 def test_general_vjp_fullsize_forms_agree(ctx):
     """At the differentiation workload's full size (Nk=1024, Nb=40, Nc=14,
-    Nw=2048) the low-rank and the dense general product agree to 1e-10, and with
+    Nw=2048) the low-rank and the dense general product agree to 1e-10, the
+    first eight frequencies of Sigma-bar match the oracle, and with
     Nbar_k = w_k I and no G_loc cotangent the general product equals the fused
     scalar adjoint (dN_tot/dSigma, dN_tot/dmu)."""
     import torch
@@ -157,6 +158,17 @@ def test_general_vjp_fullsize_forms_agree(ctx):
         ctx.set_variant(3, 48, -1)
     assert relerr(sl, sd) <= 1e-10
     assert abs(ml - md) <= 1e-10 * max(1.0, abs(md))
+    # oracle on the first frequencies over every k: sigma_bar_n depends only on
+    # Sigma(i w_n) and the cotangents at that n, so a self-energy cut to the
+    # first m frequencies gives the same slices
+    m = 8
+    cut = synth.SelfEnergy(m, sig.beta, sig.sigma[:m].copy(), sig.sigma_inf, sig.e_dc)
+    nbar_k, off = [], 0
+    for n in lat.nb:
+        nbar_k.append(nbar[off:off + n * n].reshape(n, n))
+        off += n * n
+    ref, _ = oracle.vjp(lat, cut, mu, nbar=nbar_k, gbar=gbar[:m])
+    assert relerr(sl[:m], ref) <= 1e-10
     eye = np.concatenate([(lat.wk[k] * np.eye(n)).ravel() for k, n in enumerate(lat.nb)]).astype(np.complex128)
     sg, mg = ctx.density_matrix_vjp(dl, ds, mu, torch.as_tensor(eye, device="cuda"), None)
     out, sf = ctx.dmft_ntot_vjp(dl, ds, mu)
