@@ -283,6 +283,10 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   const bool want_x = (KIND == KIND_DENSITY) && (a.mode & MODE_GLOC) && PART == 0;
   const bool hasdiag = c16 >= q && ((c16 - q) & 3) == 0;
   const int idg = (c16 - q) >> 2;
+  // V_DC of orbital c16 (the row-layout row and the output-layout column are
+  // both c16): read once, not inside the frequency loop, where each guarded
+  // load would be waited for on its own
+  const double edc = c16 < nc ? a.e_dc[c16] : 0.0;
   int bad = 0, nonfinite = 0;
 
   for (int kk = kk0; kk < kk1; ++kk) {
@@ -291,6 +295,18 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
     __builtin_assume(nb >= 1 && nb <= NBP);
     const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
     const double* eps = a.eps + ob;
+    // band energies this lane enters into the resolvent table of every
+    // frequency group (band (lane + 64 it) mod NBP), read once per k; for
+    // 64-band windows (four per lane) they are re-read, which keeps the
+    // adjoint kinds spill-free
+    constexpr int NDT = (4 * NBP + 63) / 64;
+    constexpr bool EPL = NBP <= 48;
+    double epl[NDT];
+#pragma unroll
+    for (int it = 0; it < NDT; ++it) {
+      const int r = (lane + 64 * it) % NBP;
+      epl[it] = (EPL && r < nb) ? eps[r] : 0.0;
+    }
     const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
     const double wk = a.wk[k];
     // general product: Nbar_k (row-major) and the real diagonal of Nt = Nbar + Nbar^dag at
@@ -337,11 +353,25 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
       //    reciprocal for each band it touches, the same value 4 to 16 times
       //    across the wavefront)
 #pragma unroll
-      for (int idx = lane; idx < 4 * NBP; idx += 64) {
+      for (int it = 0; it < NDT; ++it) {
+        const int idx = lane + 64 * it;  // < 4 NBP: NBP is a multiple of 16
         const int f = idx / NBP, r = idx - f * NBP;
         const int nf = min(n + f, n1 - 1);
         const double wn = (double)(2 * nf + 1) * M_PI / beta;
-        sh.dtab[f][r] = r < nb ? inv_z_minus(mu, wn, eps[r]) : make_double2(0.0, 0.0);
+        sh.dtab[f][r] = r < nb ? inv_z_minus(mu, wn, EPL ? epl[it] : eps[r]) : make_double2(0.0, 0.0);
+      }
+      // row ri_ of Sigma(i w) of frequency n + g, for the subtraction in stage
+      // 2 (rows past nc read row nc - 1, in bounds, and discard it there).
+      // Up to 14 columns it is loaded here, so that the loads are in flight
+      // during stage 1; 16 columns would not fit in the registers of the
+      // two-wavefront variants, which load it in stage 2.
+      constexpr bool SG_EARLY = NC <= 14;
+      const double2* sgp =
+          reinterpret_cast<const double2*>(a.sigma) + (int64_t)min(n + g, n1 - 1) * nc * nc + min(ri_, nc - 1) * nc;
+      double2 sgrow[NC];
+      if constexpr (SG_EARLY) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) sgrow[j] = j < nc ? sgp[j] : make_double2(0.0, 0.0);
       }
       wave_sync();
       // 1. X of the four frequencies n .. n+3 (repeating the last one past n1)
@@ -377,15 +407,14 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
           rim[j] = v.y;
         }
         rsweep<0, NC>(rr, rim, ri_, nc, bad);
-        const int ng = min(n + g, n1 - 1);
-        const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)ng * nc * nc;
+        const bool rin = ri_ < nc;
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          if (ri_ < nc && j < nc) {
-            double2 v = sg[ri_ * nc + j];
-            if (j == ri_) v.x -= a.e_dc[j];
-            rr[j] -= v.x;
-            rim[j] -= v.y;
+          if (j < nc) {
+            double2 v = SG_EARLY ? sgrow[j] : sgp[j];
+            if (j == ri_) v.x -= edc;
+            rr[j] -= rin ? v.x : 0.0;
+            rim[j] -= rin ? v.y : 0.0;
           }
         }
         rsweep<0, NC>(rr, rim, ri_, nc, bad);
@@ -447,8 +476,8 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
           double2 v = in ? sg[c16 * nc + be] : make_double2(0.0, 0.0);
           double2 u = in ? sg[be * nc + c16] : make_double2(0.0, 0.0);
           if (c16 == be && in) {
-            v.x -= a.e_dc[c16];
-            u.x -= a.e_dc[c16];
+            v.x -= edc;
+            u.x -= edc;
           }
           sa_r[j] = v.x;
           sa_i[j] = v.y;
