@@ -278,6 +278,10 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   // orbitals or bands is always taken, so its accumulator can start from an
   // inline zero instead of registers cleared beforehand
   __builtin_assume(kc >= 1 && kc <= 4);
+  // every dispatcher keeps nc <= NC columns and takes more than 8 only for
+  // nc > 8, so the first eight pivot steps and columns need no test
+  __builtin_assume(nc >= 1 && nc <= NC);
+  if constexpr (NC > 8) __builtin_assume(nc > 8);
   const double beta = a.beta;
   const bool want_s = (KIND == KIND_DENSITY) && (a.mode & MODE_S);
   const bool want_x = (KIND == KIND_DENSITY) && (a.mode & MODE_GLOC) && PART == 0;
