@@ -297,6 +297,11 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
     const int k = a.klist ? a.klist[kk] : kk;
     const int nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
     __builtin_assume(nb >= 1 && nb <= NBP);
+    // k-points are bucketed by padded size: NBP - 16 < nb, so every chunk but
+    // those of the last 16 bands is full (a wrong hint would cost only speed:
+    // fragments and resolvents past nb are zero).  The adjoint kinds, whose
+    // unrolled bodies would then outgrow the registers, are not told.
+    if constexpr (KIND == KIND_DENSITY || KIND == KIND_TRACE) __builtin_assume(nb > NBP - 16);
     const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
     const double* eps = a.eps + ob;
     // band energies this lane enters into the resolvent table of every
