@@ -43,12 +43,12 @@ LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
 # depend on the tile.  Valid only for the kernel sources it was measured on
 # (their SHA-256), the same workload, variant and tile; otherwise "traffic" is null.
 _D32 = "d-shell-Nk512-Nb32-Nc10-Nw1024"
-_SHA = "9455ab853bf7c4d42fce895472023f1112fc3cb94203a4256fdd4950837af8bf"
+_SHA = "e689bc9aa5c484392041fafbf38ebe64e90375e56b65a25143c36de85ed66764"
 TRAFFIC = {
-    (_D32, 32, 10, 2, 256): {"fetch_bytes": 336615.6875 * 2 * 1024, "write_bytes": 851968.0 * 1024},
-    (_D32, 32, 10, 2, 128): {"fetch_bytes": 341992.0 * 2 * 1024, "write_bytes": 884736.0 * 1024},
-    (_D32, 32, 10, 2, 64): {"fetch_bytes": 345193.0 * 2 * 1024, "write_bytes": 950272.0 * 1024},
-    (_D32, 32, 10, 2, 32): {"fetch_bytes": 351599.0625 * 2 * 1024, "write_bytes": 1081344.0 * 1024},
+    (_D32, 32, 10, 2, 256): {"fetch_bytes": 336611.0625 * 2 * 1024, "write_bytes": 851968.0 * 1024},
+    (_D32, 32, 10, 2, 128): {"fetch_bytes": 341987.5 * 2 * 1024, "write_bytes": 884736.0 * 1024},
+    (_D32, 32, 10, 2, 64): {"fetch_bytes": 345188.5 * 2 * 1024, "write_bytes": 950272.0 * 1024},
+    (_D32, 32, 10, 2, 32): {"fetch_bytes": 351595.5625 * 2 * 1024, "write_bytes": 1081344.0 * 1024},
 }
 for _r in TRAFFIC.values():
     _r.update(sources_sha256=_SHA, profile="profiles/lr_kernel_d-shell.md")
