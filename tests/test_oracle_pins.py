@@ -686,3 +686,178 @@ def test_energy_atomic_limit(e_dc):
     assert np.abs(t["n_orb"] - n).max() < 1e-12
     assert abs(t["n_tot"] - n.sum()) < 1e-12
     assert abs(t["h_u"] - hu) < 1e-12
+
+
+# ------------------------------------------------- the bare sum (tail_order = 0)
+#
+# Without the analytic tail, the density of Sec. 3.3 eq. rho_LDA+DMFT is the
+# positive-frequency sum with only the e^{i w 0+} convergence factor, which
+# gives 1/2 I.  For one level at energy lam the pair n, -n-1 of the sum gives
+# 1/(i w - lam) + 1/(-i w - lam) = -2 lam / (w^2 + lam^2), so the level's weight
+# at finite Nw is
+#     f0(lam) = 1/2 - (2/beta) sum_{n<Nw} lam / (w_n^2 + lam^2),
+# and f0 -> n_F(lam) as Nw -> infinity (sum_{n>=0} 1/(w_n^2 + lam^2)
+# = beta tanh(beta lam / 2) / (4 lam)), with the remainder
+# (2 lam / beta) sum_{n>=Nw} 1/(w_n^2 + lam^2) ~ beta lam / (2 pi^2 Nw).
+# Every matrix with a spectral decomposition of G over levels lam_l (Sigma = 0,
+# or the pole route's pseudo-Hamiltonian) must then give sum_l u_l u_l^dag f0(lam_l).
+
+def bare_fermi(lam, beta, nw):
+    lam = np.asarray(lam, dtype=np.float64)
+    w = wgrid(nw, beta)
+    return 0.5 - (2.0 / beta) * (lam[..., None] / (w ** 2 + lam[..., None] ** 2)).sum(axis=-1)
+
+
+def bare_fermi_slope(lam, beta, nw):
+    """d f0 / d lam = -(2/beta) sum_{n<Nw} (w_n^2 - lam^2) / (w_n^2 + lam^2)^2."""
+    lam = np.asarray(lam, dtype=np.float64)[..., None]
+    w = wgrid(nw, beta)
+    return -(2.0 / beta) * ((w ** 2 - lam ** 2) / (w ** 2 + lam ** 2) ** 2).sum(axis=-1)
+
+
+def _bare_pole_density(lat, sig, k, mu):
+    """sum_l u_l u_l^dag f0(lam_l) from the pseudo-Hamiltonian eigensystem."""
+    h = pole.pseudo_hamiltonian(lat.eps_k(k), lat.proj_k(k), sig.sigma_inf, sig.e_dc, sig.poles, mu)
+    lam, u = np.linalg.eigh(h)
+    up = u[:lat.nb[k], :]
+    return (up * bare_fermi(lam, sig.beta, sig.nw)) @ up.conj().T
+
+
+def test_bare_fermi_converges_to_fermi_as_one_over_nw():
+    beta = 20.0
+    lam = np.array([-2.0, -0.3, 0.0, 0.45, 1.7])
+    for nw in (2048, 8192):
+        err = bare_fermi(lam, beta, nw) - pole.fermi(lam, beta)
+        pred = beta * lam / (2 * np.pi ** 2 * nw)
+        assert np.all(np.abs(err - pred) <= 0.01 * np.abs(pred) + 1e-15), (err, pred)
+
+
+@pytest.mark.parametrize("nw", [48, 600])
+def test_tail0_sigma_zero_gives_bare_fermi(nw):
+    wl = small_plain(nw=nw)
+    lat = wl.lattice
+    sig = synth.SelfEnergy(nw, wl.sigma.beta, np.zeros((nw, lat.nc, lat.nc), np.complex128), None,
+                           wl.sigma.e_dc.copy(), [])
+    mu = -0.4
+    mats, ntr = oracle.density(lat, sig, mu, tail_order=0)
+    for k in range(lat.nk):
+        p = lat.proj_k(k)
+        h = np.diag(lat.eps_k(k)) - p.conj().T @ np.diag(sig.e_dc) @ p - mu * np.eye(lat.nb[k])
+        lam, u = np.linalg.eigh(h)
+        ref = (u * bare_fermi(lam, sig.beta, nw)) @ u.conj().T
+        assert relnorm(mats[k], ref) < RTOL
+        assert abs(ntr[k] - np.trace(ref).real) < 1e-12
+
+
+@pytest.mark.parametrize("maker", [small_plain, small_dshell, small_fshell])
+def test_tail0_density_equals_pole_route(maker):
+    wl = maker()
+    lat, sig = wl.lattice, wl.sigma
+    mu = 0.35
+    mats, _ = oracle.density(lat, sig, mu, tail_order=0)
+    for k in range(lat.nk):
+        assert relnorm(mats[k], _bare_pole_density(lat, sig, k, mu)) < RTOL
+
+
+def test_tail0_ragged_equals_pole_route():
+    wl = small_ragged()
+    for lat, sig in zip(wl.lattices, wl.sigmas):
+        mats, _ = oracle.density(lat, sig, -0.2, tail_order=0)
+        for k in range(lat.nk):
+            assert relnorm(mats[k], _bare_pole_density(lat, sig, k, -0.2)) < RTOL
+
+
+def test_tail0_one_level_closed_form():
+    eps, mu, a, p, beta, nw = -0.6, 0.1, 1.5, 0.7, 9.0, 200
+    lat = synth.Lattice(1, 1, np.array([1], np.int32), np.array([eps]), np.array([1.0]),
+                        np.array([1.0 + 0j]))
+    w = wgrid(nw, beta)
+    sig = synth.SelfEnergy(nw, beta, (a / (1j * w - p)).reshape(nw, 1, 1).astype(np.complex128), None,
+                           np.zeros(1), [(p, np.array([np.sqrt(a)]))])
+    mats, _ = oracle.density(lat, sig, mu, tail_order=0)
+    e = eps - mu
+    root = np.sqrt((e - p) ** 2 + 4 * a)
+    zp, zm = (e + p + root) / 2, (e + p - root) / 2
+    wp, wm = (zp - p) / (zp - zm), (zm - p) / (zm - zp)
+    ref = wp * bare_fermi(np.array([zp]), beta, nw)[0] + wm * bare_fermi(np.array([zm]), beta, nw)[0]
+    assert abs(mats[0][0, 0].real - ref) < 1e-13
+    assert abs(mats[0][0, 0].imag) < 1e-15
+    # the tail-free and the tailed sums differ only by what the tail adds back
+    m2, _ = oracle.density(lat, sig, mu, tail_order=2)
+    tailed = wp * pole.truncated_fermi(np.array([zp]), beta, nw)[0] + wm * pole.truncated_fermi(np.array([zm]), beta, nw)[0]
+    assert abs(m2[0][0, 0].real - tailed) < 1e-13
+    assert abs(ref - tailed) > 1e-4
+
+
+def test_tail0_trace_against_spectral_closed_form():
+    # Sigma = 0: every level moves with -mu, so dN/dmu = -sum_k w_k sum_l f0'(lam_l)
+    wl = small_plain(nk=3, nb=6, nc=2, nw=80, beta=7.0)
+    lat = wl.lattice
+    sig = synth.SelfEnergy(80, 7.0, np.zeros((80, lat.nc, lat.nc), np.complex128), None, wl.sigma.e_dc.copy(), [])
+    mu = 0.25
+    n_o, d_o = oracle.trace(lat, sig, mu, tail_order=0)
+    n_ref = d_ref = 0.0
+    for k in range(lat.nk):
+        p = lat.proj_k(k)
+        lam = np.linalg.eigvalsh(np.diag(lat.eps_k(k)) - p.conj().T @ np.diag(sig.e_dc) @ p - mu * np.eye(lat.nb[k]))
+        n_ref += lat.wk[k] * bare_fermi(lam, sig.beta, sig.nw).sum()
+        d_ref -= lat.wk[k] * bare_fermi_slope(lam, sig.beta, sig.nw).sum()
+    assert abs(n_o - n_ref) < 1e-12 * abs(n_ref)
+    assert abs(d_o - d_ref) < 1e-12 * abs(d_ref)
+
+
+def test_tail0_trace_pole_route_and_finite_difference():
+    wl = grad_case()
+    lat, sig = wl.lattice, wl.sigma
+    mu, h = 0.3, 1e-6
+    n0, d = oracle.trace(lat, sig, mu, tail_order=0)
+    ref = sum(lat.wk[k] * np.trace(_bare_pole_density(lat, sig, k, mu)).real for k in range(lat.nk))
+    assert abs(n0 - ref) < 1e-12 * abs(ref)
+    fd = (oracle.trace(lat, sig, mu + h, tail_order=0)[0] - oracle.trace(lat, sig, mu - h, tail_order=0)[0]) / (2 * h)
+    assert abs(fd - d) <= 1e-6 * abs(d)
+    # the tail changes dN/dmu by sum_k w_k nb_k (beta/4 - (2/beta) sum_n 1/w_n^2) exactly
+    _, d2 = oracle.trace(lat, sig, mu, tail_order=2)
+    w = wgrid(sig.nw, sig.beta)
+    shift = float(np.dot(lat.wk, lat.nb)) * (sig.beta / 4 - 2.0 / sig.beta * np.sum(1.0 / w ** 2))
+    assert abs((d2 - d) - shift) < 1e-12 * max(1.0, abs(shift))
+
+
+def test_tail0_vjp_finite_difference():
+    wl = grad_case()
+    lat, sig = wl.lattice, wl.sigma
+    mu, h = -0.1, 1e-6
+    rng = np.random.default_rng(21)
+    nbar = [rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) for n in lat.nb]
+
+    def loss(s, m):
+        mats, _ = oracle.density(lat, s, m, tail_order=0)
+        return sum(np.vdot(nb_, x).real for nb_, x in zip(nbar, mats))
+
+    sbar, mubar = oracle.vjp(lat, sig, mu, nbar=nbar, tail_order=0)
+    fdmu = (loss(sig, mu + h) - loss(sig, mu - h)) / (2 * h)
+    assert abs(fdmu - mubar) <= 1e-6 * max(1.0, abs(mubar))
+    gmax = np.max(np.abs(sbar))
+    for (n, a, b) in [(0, 1, 1), (4, 0, 2), (sig.nw - 1, 2, 0)]:
+        fd = 0j
+        for unit in (1.0, 1j):
+            vals = []
+            for s in (+1, -1):
+                sg = sig.sigma.copy()
+                sg[n, a, b] += s * h * unit
+                vals.append(loss(synth.SelfEnergy(sig.nw, sig.beta, sg, sig.sigma_inf, sig.e_dc, []), mu))
+            fd += unit * (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - sbar[n, a, b]) <= 1e-6 * gmax
+    # with nbar = w_k I the tail-free mubar is the trace pass's tail-free dN/dmu
+    _, mub1 = oracle.vjp(lat, sig, mu, nbar=[lat.wk[k] * np.eye(lat.nb[k]) for k in range(lat.nk)], tail_order=0)
+    _, d0 = oracle.trace(lat, sig, mu, tail_order=0)
+    assert abs(mub1 - d0) < 1e-10 * abs(d0)
+
+
+def test_tail0_bisection_hits_target():
+    wl = small_plain(nk=4, nb=7, nc=3, nw=64)
+    lat, sig = wl.lattice, wl.sigma
+    n0 = 3.0
+    mu, passes, n = oracle.find_mu_bisect(lat, sig, n0, 1e-9, -40.0, 40.0, tail_order=0)
+    assert abs(n - n0) <= 1e-9
+    ref = sum(lat.wk[k] * np.trace(_bare_pole_density(lat, sig, k, mu)).real for k in range(lat.nk))
+    assert abs(ref - n0) <= 1e-9 + 1e-12
