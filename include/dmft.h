@@ -95,7 +95,13 @@ typedef struct dmft_sigma {
 } dmft_sigma;
 
 /* Handle: host-side plans, the autotune cache and a pinned staging buffer.
- * Selects `device` as the handle's GPU.  Returns DMFT_OK or DMFT_EHIP. */
+ * Selects `device` as the handle's GPU.  Returns DMFT_OK or DMFT_EHIP.
+ * device = DMFT_NO_DEVICE makes a planning handle that makes no HIP call:
+ * it runs every host-side argument check and answers the workspace-size
+ * queries, and any call that would reach the device returns DMFT_EINVAL
+ * after those checks (for sizing workspaces, or checking inputs, on a host
+ * without a GPU). */
+enum { DMFT_NO_DEVICE = -1 };
 int dmft_create(dmft_handle* out, int device);
 int dmft_destroy(dmft_handle h);
 
@@ -194,17 +200,26 @@ int dmft_ntot_vjp(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
  *     the residual, falls back to bisection), starting at mu0;
  *   method DMFT_BISECT: plain bisection of [mu_lo, mu_hi];
  * stops when |N - n_target| <= tol_n.  Each iteration is one dmft_ntot pass and
- * one 16-byte device-to-host copy; the stream is synchronised every iteration.
- * Outputs (HOST): mu_out, passes_out (number of dmft_ntot passes), n_out.
- * Returns DMFT_ENOCONV if the bracket does not contain the target or max_iter
- * passes are used up. */
+ * one 32-byte device-to-host copy (the workspace's error word and N, dN/dmu);
+ * the stream is synchronised once per iteration.
+ * Outputs (HOST): mu_out, passes_out (number of dmft_ntot passes), n_out; they
+ * are written on DMFT_OK and DMFT_ENOCONV.
+ * Returns DMFT_ENOCONV when max_iter passes are used up, or when the bracket
+ * does not contain the target: N(mu) increases with mu, so the iterates then run
+ * into one end of [mu_lo, mu_hi], and the search stops as soon as no double lies
+ * strictly between the current ends (about 55 passes for [-40, 40] eV).  A
+ * device error of a pass returns DMFT_ESINGULAR (vanishing pivot) or
+ * DMFT_ENONFINITE and clears the error word. */
 int find_mu(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, int tail_order,
             double n_target, double tol_n, int method, double mu_lo, double mu_hi, double mu0,
             int max_iter, double* mu_out, int* passes_out, double* n_out, void* ws,
             size_t ws_bytes, hipStream_t stream);
 
-/* Batched pass over several self-energy iterates with uneven band windows:
- * one persistent launch over a cost-sorted queue of (iterate, k, frequency
+/* Batched pass over several self-energy iterates with uneven band windows
+ * (the per-k window of Kohn-Sham states of Sec. 2 eq. 3, within which the
+ * projectors of Sec. 3.1 eq. S_norm are normalised, so nb_k varies with k;
+ * each iterate is a density_matrix of its own lattice and Sigma):
+ * persistent launches over cost-sorted queues of (iterate, k, frequency
  * tile) items, followed by the reductions.  Build the plan once (it uploads
  * the queue and per-k offsets into ws with a synchronous copy), then run
  * dmft_batched_pass as often as needed; it only enqueues kernels, reads each
@@ -262,9 +277,10 @@ int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
  * D = diag(1 / (i w_n + mu - E_v)) and X = P D P^dag (nc x nc), the Woodbury
  * identity gives P G P^dag = (X^-1 - Sigma')^-1 and G = D + D P^dag R P D,
  * R = Sigma' (X^-1 - Sigma')^-1 X^-1, so only nc x nc matrices are inverted.
- * It gives the same outputs to rounding and assumes, as the projector
- * construction of the projection section provides, that the rows of P(k) are
- * orthonormal; other bits of a code tune registers and occupancy only. */
+ * It gives the same outputs to rounding and needs only that P(k) has full row
+ * rank (its nc x nc inversions run without pivoting: the anti-Hermitian part
+ * of X is P Im(D) P^dag, negative definite for w_n > 0); other bits of a code
+ * tune registers and occupancy only. */
 int dmft_variants(int kind, int nbp, int* out, int max);
 int dmft_set_variant(dmft_handle h, int kind, int nbp, int var);
 int dmft_get_variant(dmft_handle h, int kind, int nbp);

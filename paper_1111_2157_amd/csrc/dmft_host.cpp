@@ -68,6 +68,7 @@ struct dmft_handle_s {
   std::string last_error;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
+  void* readback = nullptr;         // pinned 64 B: error word and scalars of a mu-search pass
   hipEvent_t staged = nullptr;      // recorded after the last upload from `pinned`
   std::map<std::string, Tile> tune;  // autotuned tiles keyed by kind/size/nk/nw
   std::map<std::string, int> tvar;   // autotuned kernel variant keyed by kind/size
@@ -111,8 +112,12 @@ int fail(dmft_handle h, int code, const char* fmt, ...) {
   return code;
 }
 
+// Every HIP call of an entry point goes through HIPCHK, which first refuses a
+// planning handle (created without a device): such a handle validates
+// arguments and sizes workspaces but never reaches the runtime.
 #define HIPCHK(h, expr)                                                                    \
   do {                                                                                     \
+    if (!(h) || (h)->device < 0) return fail(h, DMFT_EINVAL, "handle has no device (planning handle)"); \
     hipError_t e_ = (expr);                                                                \
     if (e_ != hipSuccess) return fail(h, DMFT_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
@@ -222,6 +227,14 @@ int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, L
     L.buckets.push_back(b);
   }
   L.n_ktiles_total = base;
+  // the kernels are compiled for one padded size each and take nb_k within
+  // (NBP - 16, NBP] as given (they skip the chunk tests of all but the last
+  // 16 bands); every k of a bucket must satisfy that
+  for (const Bucket& b : L.buckets)
+    for (int32_t k : b.klist)
+      if (!(L.nb[k] > b.nbp - 16 && L.nb[k] <= b.nbp))
+        return fail(h, DMFT_EUNSUPPORTED, "internal: nb[%d] = %d outside the bucket of padded size %d", k, L.nb[k],
+                    b.nbp);
   L.s_stride = L.off_s[nk];
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -229,8 +242,11 @@ int make_layout(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, L
     o = align_up(o + bytes);
     return at;
   };
-  L.err = take(16);
-  L.out2 = take(16 * sizeof(double));
+  // error word (int at offset 0) followed, 16 bytes on, by the small device
+  // results (N_tot and dN/dmu of a trace pass, the adjoint scalars), so the mu
+  // search reads both back with one copy
+  L.err = take(16 + 16 * sizeof(double));
+  L.out2 = L.err + 16;
   L.meta_nb = take(sizeof(int32_t) * nk);
   L.meta_offb = take(sizeof(int64_t) * (nk + 1));
   L.meta_offn = take(sizeof(int64_t) * (nk + 1));
@@ -480,6 +496,13 @@ const char* dmft_strerror(int status) {
 int dmft_create(dmft_handle* out, int device) {
   if (!out) return DMFT_EINVAL;
   *out = nullptr;
+  if (device == DMFT_NO_DEVICE) {
+    // planning handle: no HIP call now or later (HIPCHK refuses it)
+    dmft_handle h = new dmft_handle_s;
+    h->device = DMFT_NO_DEVICE;
+    *out = h;
+    return DMFT_OK;
+  }
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DMFT_EHIP;
   if (hipSetDevice(device) != hipSuccess) return DMFT_EHIP;
@@ -499,6 +522,7 @@ int dmft_destroy(dmft_handle h) {
     (void)hipEventDestroy(h->staged);
   }
   if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->readback) (void)hipHostFree(h->readback);
   for (auto& ev : h->tev) {
     (void)hipEventSynchronize(ev.second);
     h->tfree.push_back(ev);
@@ -715,8 +739,10 @@ int dmft_sync_status(dmft_handle h, void* ws, hipStream_t stream) {
   HIPCHK(h, hipMemcpy(&err, ws, sizeof(int), hipMemcpyDeviceToHost));
   int zero = 0;
   HIPCHK(h, hipMemcpy(ws, &zero, sizeof(int), hipMemcpyHostToDevice));
-  if (err & ERR_NONFINITE) return fail(h, DMFT_ENONFINITE, "device flagged a non-finite value");
+  // a vanishing pivot is reported first: the reciprocal taken after it is what
+  // makes the later values non-finite
   if (err & ERR_SINGULAR) return fail(h, DMFT_ESINGULAR, "device flagged a vanishing pivot");
+  if (err & ERR_NONFINITE) return fail(h, DMFT_ENONFINITE, "device flagged a non-finite value");
   if (err & ERR_NOCONV) return fail(h, DMFT_ENOCONV, "an eigensolver did not converge");
   return DMFT_OK;
 }
@@ -735,30 +761,45 @@ int find_mu(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, int t
   char* w = (char*)ws;
   double* dout = (double*)(w + L.out2);
   int passes = 0;
-  double host[2];
+  // pinned readback slot: the error word and N, dN/dmu come back in one copy
+  if (!h->readback) HIPCHK(h, hipHostMalloc(&h->readback, 64, hipHostMallocDefault));
+  char* rb = (char*)h->readback;
   auto eval = [&](double mu, double* nv, double* dv) -> int {
     int rr = ntot_impl(h, lat, sig, L, w, mu, nullptr, tail_order, dout, stream);
     if (rr) return rr;
-    HIPCHK(h, hipMemcpyAsync(host, dout, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipMemcpyAsync(rb, w + L.err, 16 + 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIPCHK(h, hipStreamSynchronize(stream));
     ++passes;
     int err = 0;
-    HIPCHK(h, hipMemcpy(&err, w + L.err, sizeof(int), hipMemcpyDeviceToHost));
+    std::memcpy(&err, rb, sizeof(int));
     if (err) {
       int zero = 0;
       HIPCHK(h, hipMemcpy(w + L.err, &zero, sizeof(int), hipMemcpyHostToDevice));
-      return fail(h, (err & ERR_NONFINITE) ? DMFT_ENONFINITE : DMFT_ESINGULAR, "device error at mu=%g", mu);
+      return fail(h, (err & ERR_SINGULAR) ? DMFT_ESINGULAR : DMFT_ENONFINITE, "device error at mu=%g", mu);
     }
-    *nv = host[0];
-    if (dv) *dv = host[1];
+    double nd[2];
+    std::memcpy(nd, rb + 16, sizeof nd);
+    *nv = nd[0];
+    if (dv) *dv = nd[1];
     return DMFT_OK;
   };
   double lo = mu_lo, hi = mu_hi, mu = 0.0, nv = 0.0, dv = 0.0;
   int converged = 0;
+  // N(mu) increases with mu.  When [lo, hi] does not contain the target, the
+  // iterates run into one end of the bracket until no double lies strictly
+  // between lo and hi; the search stops there instead of spending max_iter passes.
+  auto collapsed = [&](double next) { return !(next > lo && next < hi); };
+  auto no_bracket = [&]() {
+    if (mu_out) *mu_out = mu;
+    if (passes_out) *passes_out = passes;
+    if (n_out) *n_out = nv;
+    return fail(h, DMFT_ENOCONV, "[%.17g, %.17g] does not bracket n_target = %.17g (N = %.17g after %d passes)",
+                mu_lo, mu_hi, n_target, nv, passes);
+  };
   if (method == DMFT_BISECT) {
-    // N(mu) increases with mu; keep N(lo) < n_target < N(hi) implicitly.
     for (int it = 0; it < max_iter; ++it) {
       mu = 0.5 * (lo + hi);
+      if (it > 0 && collapsed(mu)) return no_bracket();
       r = eval(mu, &nv, nullptr);
       if (r) return r;
       if (std::fabs(nv - n_target) <= tol_n) { converged = 1; break; }
@@ -783,7 +824,10 @@ int find_mu(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, int t
         if (!(next > lo && next < hi)) newton_ok = false;
         if (std::fabs(res) > 0.5 * prev_res && std::fabs(next - mu) > 0.5 * prev_dx) newton_ok = false;
       }
-      if (!newton_ok) next = 0.5 * (lo + hi);
+      if (!newton_ok) {
+        next = 0.5 * (lo + hi);
+        if (collapsed(next)) return no_bracket();
+      }
       prev_dx = std::fabs(next - mu);
       prev_res = std::fabs(res);
       mu = next;

@@ -19,11 +19,12 @@
 //
 // so the nb^3 inversion becomes rank-nc products on the matrix cores and two
 // nc x nc inversions.  Both are Gauss-Jordan sweeps without pivoting, which is
-// safe for the same reason as for A: the rows of S are orthonormal (the
-// projector construction of the projection section), so the anti-Hermitian
-// part of X, S Im(D) S^dag, is negative definite; that of K = X^-1 - Sigma' is
-// then positive definite for a causal Sigma, and every leading block of either
-// matrix is invertible.
+// safe for the same reason as for A: Im d_v = -w_n / (w_n^2 + (mu - E_v)^2) < 0,
+// so for any S of full row rank the anti-Hermitian part of X, S Im(D) S^dag, is
+// negative definite; that of X^-1 is then positive definite, that of
+// K = X^-1 - Sigma' too for a causal Sigma, and every leading block of either
+// matrix is invertible.  (Orthonormal rows, as the projector construction of
+// the projection section gives them, are not needed.)
 //
 // One wavefront walks a (k-tile, frequency-tile) item, four frequencies at a
 // time:
@@ -298,9 +299,11 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
     const int nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
     __builtin_assume(nb >= 1 && nb <= NBP);
     // k-points are bucketed by padded size: NBP - 16 < nb, so every chunk but
-    // those of the last 16 bands is full (a wrong hint would cost only speed:
-    // fragments and resolvents past nb are zero).  The adjoint kinds, whose
-    // unrolled bodies would then outgrow the registers, are not told.
+    // those of the last 16 bands is full.  This is a promise to the compiler,
+    // not a hint: were it false, the chunk and fragment tests it removes could
+    // let loads run past the k-point's bands, so the host checks it for every
+    // bucket before any launch.  The adjoint kinds, whose unrolled bodies
+    // would then outgrow the registers, are not told.
     if constexpr (KIND == KIND_DENSITY || KIND == KIND_TRACE) __builtin_assume(nb > NBP - 16);
     const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
     const double* eps = a.eps + ob;

@@ -133,3 +133,32 @@ def test_lowrank_nonfinite_sigma_is_reported(ctx):
             ctx.sync_status()
         assert e.value.name == "DMFT_ENONFINITE"
     ctx.sync_status()
+
+
+def skewed_projectors(wl, seed=3, amp=0.4):
+    """The workload's lattice with projector rows mixed by a fixed
+    well-conditioned complex matrix M (S -> M S): the rows keep full rank but
+    are no longer orthonormal.  The low-rank inversions need only full row
+    rank: S Im(D) S^dag is negative definite for any such S."""
+    lat = wl.lattice
+    rng = np.random.default_rng(seed)
+    nc = lat.nc
+    m = np.eye(nc) + amp * (rng.standard_normal((nc, nc)) + 1j * rng.standard_normal((nc, nc))) / np.sqrt(2 * nc)
+    m = m * rng.uniform(0.6, 1.6, nc)[:, None]
+    proj = np.concatenate([(m @ lat.proj_k(k)).ravel() for k in range(lat.nk)])
+    s = np.linalg.svd(m, compute_uv=False)
+    assert s[-1] > 0.2 and s[0] / s[-1] < 10
+    return synth.Lattice(lat.nk, nc, lat.nb, lat.eps, lat.wk, proj)
+
+
+@pytest.mark.parametrize("name", ["d-shell-small", "f-shell-small", "nb57-d"])
+def test_lowrank_non_orthonormal_projectors(ctx, name):
+    maker, mu = CASES[name]
+    wl = maker()
+    lat = skewed_projectors(wl)
+    p0 = lat.proj_k(0)
+    assert np.linalg.norm(p0 @ p0.conj().T - np.eye(lat.nc)) > 0.1
+    print("non-orthonormal projectors", name, flush=True)
+    mats, gl, sc = gpu_density(ctx, wl, mu, lat=lat)
+    assert_nk_parity(mats, lat, wl.sigma, mu)
+    assert_gloc_parity(gl, lat, wl.sigma, mu)

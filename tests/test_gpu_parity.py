@@ -204,3 +204,64 @@ def test_every_kernel_variant_matches_oracle(nbp, maker, mu):
         c.sync_status()
         assert abs(out[0] - n_ref) <= RTOL * abs(n_ref) and abs(out[1] - d_ref) <= RTOL * abs(d_ref)
     c.close()
+
+
+def test_tail_order_zero_trace_vjp_and_mu(ctx):
+    """dmft_ntot, density_matrix_vjp and find_mu without the analytic tail
+    against the oracle's tail-free sums (pinned on the CPU against the
+    spectral closed forms)."""
+    import torch
+
+    from paper_1111_2157_amd.dyson import BISECT, NEWTON, Lattice, SelfEnergy
+
+    wl = synth.f_shell(nk=8, nb=20, nc=14, nw=48, beta=15.0, n_narrow=6)
+    lat, sig = wl.lattice, wl.sigma
+    dl, ds = Lattice.from_host(lat), SelfEnergy.from_host(sig)
+    mu = 0.2
+    out = ctx.dmft_ntot(dl, ds, mu, tail_order=0).cpu().numpy()
+    ctx.sync_status()
+    n, d = oracle.trace(lat, sig, mu, tail_order=0)
+    assert abs(out[0] - n) <= RTOL * abs(n) and abs(out[1] - d) <= RTOL * abs(d)
+    rng = np.random.default_rng(12)
+    nbar = [rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)) for m in lat.nb]
+    gbar = rng.standard_normal(sig.sigma.shape) + 1j * rng.standard_normal(sig.sigma.shape)
+    sb, mb = ctx.density_matrix_vjp(dl, ds, mu, torch.as_tensor(np.concatenate([x.ravel() for x in nbar]),
+                                                                device="cuda"),
+                                    torch.as_tensor(gbar, device="cuda"), tail_order=0)
+    ctx.sync_status()
+    ref, mub = oracle.vjp(lat, sig, mu, nbar=nbar, gbar=gbar, tail_order=0)
+    assert abs(float(mb[0]) - mub) <= RTOL * max(1.0, abs(mub))
+    sbn = sb.cpu().numpy()
+    for nn in range(sig.nw):
+        assert relerr(sbn[nn], ref[nn]) <= RTOL, nn
+    n0 = 9.0
+    mu_ref, _, _ = oracle.find_mu_bisect(lat, sig, n0, 1e-12, -40.0, 40.0, max_iter=300, tail_order=0)
+    for m in (NEWTON, BISECT):
+        mu_g, _, ng = ctx.find_mu(dl, ds, n0, 1e-12, m, -40.0, 40.0, max_iter=300, tail_order=0)
+        assert abs(ng - n0) <= 1e-12
+        assert abs(mu_g - mu_ref) <= 1e-10 * max(1.0, abs(mu_ref))
+
+
+def test_mu_parity_on_differentiation_subset(ctx):
+    """Parity mode of the mu search on the differentiation workload (beta = 50,
+    Nb = 40, Nc = 14) at full Nw = 2048 on its first 32 k-points (weights
+    1/32): the oracle's bisection and both GPU searches solve to
+    |N - N0| <= 1e-13 N0, and the roots agree to 1e-10 max(1, |mu|)."""
+    from paper_1111_2157_amd.dyson import BISECT, NEWTON, Lattice, SelfEnergy
+
+    wl = synth.differentiation()
+    sub = wl.lattice.subset(np.arange(32))
+    sub.wk[:] = 1.0 / 32
+    sig = wl.sigma
+    n0 = wl.n_target
+    tol = 1e-13 * n0
+    print("oracle bisection on the 32-k subset", flush=True)
+    mu_ref, p_ref, n_ref = oracle.find_mu_bisect(sub, sig, n0, tol, -40.0, 40.0, max_iter=200)
+    _, d_ref = oracle.trace(sub, sig, mu_ref)
+    assert d_ref > 1e-2
+    dl, ds = Lattice.from_host(sub), SelfEnergy.from_host(sig)
+    for m in (NEWTON, BISECT):
+        mu_g, passes, ng = ctx.find_mu(dl, ds, n0, tol, m, -40.0, 40.0, max_iter=200)
+        print("gpu", m, mu_g, passes, "oracle", mu_ref, p_ref, flush=True)
+        assert abs(ng - n0) <= tol
+        assert abs(mu_g - mu_ref) <= 1e-10 * max(1.0, abs(mu_ref))
