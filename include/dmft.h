@@ -280,7 +280,9 @@ int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
  * It gives the same outputs to rounding and needs only that P(k) has full row
  * rank (its nc x nc inversions run without pivoting: the anti-Hermitian part
  * of X is P Im(D) P^dag, negative definite for w_n > 0); other bits of a code
- * tune registers and occupancy only. */
+ * tune registers and occupancy only.  Code 40 (bits 3 and 5, 64-band windows,
+ * density kind) runs the low-rank step on two-wavefront work-groups that
+ * share the nc x nc part of the step. */
 int dmft_variants(int kind, int nbp, int* out, int max);
 int dmft_set_variant(dmft_handle h, int kind, int nbp, int var);
 int dmft_get_variant(dmft_handle h, int kind, int nbp);

@@ -1,0 +1,62 @@
+// Persistent kernels of the batched pass in the low-rank form: one kernel per
+// class of work items (padded band-window size, columns of the row-layout
+// inversions), each draining its own cost-sorted queue of (iterate, k tile,
+// frequency tile) items from every self-energy iterate.  A class kernel has
+// the register allocation and occupancy of its own size only; 64-band items
+// run on two-wavefront work-groups (lowrank_pair_impl.h), the others on one
+// wavefront (lr_tile of lowrank_impl.h, with the variant that is fastest for
+// that size on its own).  The classes are launched one after another on one
+// stream, largest items first; every work-group pulls items until its queue
+// is empty, so each launch drains.
+#pragma once
+
+#include "lowrank_pair_impl.h"
+
+namespace dmft {
+
+struct BatchItem {
+  int32_t args;   // index into the per-(iterate, size) argument array
+  int32_t nbp;    // padded band-window size of the item
+  int32_t ktile;  // k-tile within that (iterate, size) launch
+  int32_t wtile;  // frequency tile
+};
+
+// Single-wavefront class: NBP in {16, 32, 48}.
+template <int NBP, int RL, bool M3, int NC>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1)))
+lr_class_kernel(const BatchItem* items, int n_items, const DysonArgs* args, int* counter) {
+  __shared__ LRShared sh;
+  const int lane = threadIdx.x;
+  for (;;) {
+    int it = 0;
+    if (lane == 0) it = atomicAdd(counter, 1);
+    it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
+    if (it >= n_items) break;
+    const BatchItem b = items[it];
+    const DysonArgs a = args[b.args];
+    lr_tile<NBP, KIND_DENSITY, RL, M3, NC>(a, b.ktile, b.wtile, 0, sh, lane);
+  }
+}
+
+// Two-wavefront class for 64-band windows.
+template <int NC>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1)))
+lr_pair_class_kernel(const BatchItem* items, int n_items, const DysonArgs* args, int* counter) {
+  __shared__ LRPairShared sh;
+  __shared__ int next;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    // uniform by construction; readfirstlane tells the compiler, so the item and
+    // its arguments are read into scalar registers
+    const int it = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();
+    if (it >= n_items) break;
+    const BatchItem b = items[it];
+    const DysonArgs a = args[b.args];
+    lr_pair_tile<NC>(a, b.ktile, b.wtile, sh, tid);
+  }
+}
+
+}  // namespace dmft

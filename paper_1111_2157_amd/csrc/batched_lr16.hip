@@ -1,0 +1,25 @@
+// Batched low-rank pass: persistent class kernels for band windows padded to 16
+// (see batched_lr.h), one per column count of the row-layout inversions.
+#include "batched_lr.h"
+
+namespace dmft {
+
+hipError_t launch_lr_class_16(int ncls, const void* items, int n_items, const DysonArgs* args, int* counter,
+                              int grid, hipStream_t s) {
+  const BatchItem* it = reinterpret_cast<const BatchItem*>(items);
+  switch (ncls) {
+    case 8:
+      hipLaunchKernelGGL((lr_class_kernel<16, 0, true, 8>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
+      break;
+    case 12:
+      hipLaunchKernelGGL((lr_class_kernel<16, 0, true, 12>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
+      break;
+    case 16:
+      hipLaunchKernelGGL((lr_class_kernel<16, 0, true, 16>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dmft

@@ -19,6 +19,7 @@ using namespace dmft;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxQueues = 32;  // queue counters of a batched plan
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int kNbpSizes[] = {16, 32, 48, 64};
 
@@ -85,6 +86,11 @@ struct dmft_handle_s {
   size_t b_total = 0, b_args = 0, b_items = 0, b_counters = 0, b_mu = 0;
   int b_nbig = 0, b_nsmall = 0, b_nargs = 0, b_wgs = 0;
   bool b_lowrank = false;                // batched items use the low-rank form
+  // low-rank form: one persistent launch per item class, in this order
+  struct LRClassPlan {
+    int nbp, ncls, off, count, grid;
+  };
+  std::vector<LRClassPlan> b_cls;
   int b_form_pref = DMFT_FORM_AUTO;      // form requested for later plans
   void* b_ws = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -995,8 +1001,7 @@ int batched_layout(dmft_handle h, int n_iter, const dmft_lattice* const* lat, co
     o = align_up(o + Ls[s].total);
     for (const Bucket& b : Ls[s].buckets) {
       ++na;
-      // the low-rank form splits 64-band items into two column parts
-      ni += b.n_ktiles * Ls[s].n_wtiles * (b.nbp == 64 ? 2 : 1);
+      ni += b.n_ktiles * Ls[s].n_wtiles;
     }
   }
   *o_args = o;
@@ -1004,7 +1009,7 @@ int batched_layout(dmft_handle h, int n_iter, const dmft_lattice* const* lat, co
   *o_items = o;
   o = align_up(o + sizeof(BatchItemHost) * ni);
   *o_cnt = o;
-  o = align_up(o + 2 * sizeof(int));
+  o = align_up(o + kMaxQueues * sizeof(int));
   *o_mu = o;
   o = align_up(o + sizeof(double) * n_iter);
   *total = o;
@@ -1021,11 +1026,14 @@ int batched_pass_impl(dmft_handle h, const double* mu_dev, double* const* nk_out
   char* w = (char*)ws;
   int n_iter = (int)h->iters.size();
   HIPCHK(h, launch_copy_doubles(mu_dev, (double*)(w + h->b_mu), n_iter, stream));
-  HIPCHK(h, launch_fill_zero(w + h->b_counters, 2 * sizeof(int), stream));
-  if (h->b_lowrank)
-    HIPCHK(h, launch_batched_lr(w + h->b_items, h->b_nsmall, (const DysonArgs*)(w + h->b_args),
-                                (int*)(w + h->b_counters), h->b_wgs, stream));
-  else
+  HIPCHK(h, launch_fill_zero(w + h->b_counters, kMaxQueues * sizeof(int), stream));
+  if (h->b_lowrank) {
+    for (size_t c = 0; c < h->b_cls.size(); ++c) {
+      const auto& k = h->b_cls[c];
+      HIPCHK(h, launch_lr_class(k.nbp, k.ncls, w + h->b_items + sizeof(BatchItemHost) * k.off, k.count,
+                                (const DysonArgs*)(w + h->b_args), (int*)(w + h->b_counters) + c, k.grid, stream));
+    }
+  } else
     HIPCHK(h, launch_batched(w + h->b_items, h->b_nbig, h->b_nsmall, (const DysonArgs*)(w + h->b_args),
                              (int*)(w + h->b_counters), h->b_wgs, stream));
   if (kernel_only) return DMFT_OK;
@@ -1063,6 +1071,7 @@ int batched_build(dmft_handle h, int n_iter, const dmft_lattice* const* lat, con
     double cost;
   };
   std::vector<Q> big, small;
+  std::map<std::pair<int, int>, std::vector<Q>> lrq;  // low-rank queues by (nbp, column class)
   for (int s = 0; s < n_iter; ++s) {
     Layout& L = Ls[s];
     r = upload_meta(h, L, w + base[s], stream, true);
@@ -1117,14 +1126,9 @@ int batched_build(dmft_handle h, int n_iter, const dmft_lattice* const* lat, con
         for (int wt = 0; wt < L.n_wtiles; ++wt) {
           int nwt = std::min(L.tile.wt, sig[s]->nw - wt * L.tile.wt);
           if (lowrank) {
-            // one queue; 64-band items in two column parts (size in the low
-            // byte of nbp, part in bit 8, bit 9 set for nc <= 8, bit 10 for
-            // 8 < nc <= 14: the columns of the row-layout inversions)
-            int parts = b.nbp == 64 ? 2 : 1;
-            double c = (nbp * nbp * nc / parts + 2.0 * nbp * nc * nc + 4.0 * nc * nc * nc) * nkt * nwt;
-            const int small_nc = lat[s]->nc <= 8 ? 512 : lat[s]->nc <= 14 ? 1024 : 0;
-            for (int part = 0; part < parts; ++part)
-              small.push_back(Q{{ai, b.nbp | (part << 8) | small_nc, kt, wt}, c});
+            // one queue per class (padded size, columns of the inversions)
+            double c = (nbp * nbp * nc + 2.0 * nbp * nc * nc + 4.0 * nc * nc * nc) * nkt * nwt;
+            lrq[{b.nbp, lr_nc_class(b.nbp, lat[s]->nc)}].push_back(Q{{ai, b.nbp, kt, wt}, c});
           } else {
             double c = nbp * nbp * (nbp + 2.0 * nc) * nkt * nwt;
             Q qq{{ai, b.nbp, kt, wt}, c};
@@ -1140,13 +1144,32 @@ int batched_build(dmft_handle h, int n_iter, const dmft_lattice* const* lat, con
   std::vector<BatchItemHost> items;
   for (auto& x : big) items.push_back(x.it);
   for (auto& x : small) items.push_back(x.it);
+  int ncu = 0;
+  HIPCHK(h, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
+  ncu = std::max(ncu, 1);
+  h->b_cls.clear();
+  if (lowrank) {
+    // largest padded size first, so that the longest items start earliest
+    for (auto it = lrq.rbegin(); it != lrq.rend(); ++it) {
+      auto& qv = it->second;
+      std::stable_sort(qv.begin(), qv.end(), by_cost);
+      dmft_handle_s::LRClassPlan c;
+      c.nbp = it->first.first;
+      c.ncls = it->first.second;
+      c.off = (int)items.size();
+      c.count = (int)qv.size();
+      // one wavefront per SIMD: four single-wavefront or two pair work-groups per CU
+      c.grid = std::min(c.count, (c.nbp == 64 ? 2 : 4) * ncu);
+      for (auto& x : qv) items.push_back(x.it);
+      h->b_cls.push_back(c);
+    }
+    if ((int)h->b_cls.size() > kMaxQueues) return fail(h, DMFT_EUNSUPPORTED, "too many item classes");
+  }
   HIPCHK(h, hipMemcpy(w + o_args, args.data(), sizeof(DysonArgs) * args.size(), hipMemcpyHostToDevice));
   if (!items.empty())
     HIPCHK(h, hipMemcpy(w + o_items, items.data(), sizeof(BatchItemHost) * items.size(), hipMemcpyHostToDevice));
   int zero = 0;
   HIPCHK(h, hipMemcpy(w + base[0] + Ls[0].err, &zero, sizeof(int), hipMemcpyHostToDevice));
-  int ncu = 0;
-  HIPCHK(h, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
   h->b_tail = tail_order;
   h->b_total = total;
   h->b_args = o_args;
@@ -1157,9 +1180,9 @@ int batched_build(dmft_handle h, int n_iter, const dmft_lattice* const* lat, con
   h->b_nsmall = (int)small.size();
   h->b_nargs = (int)args.size();
   h->b_lowrank = lowrank;
-  // dense: two-wavefront work-groups, one per SIMD pair; low-rank: one
-  // wavefront per work-group and per SIMD (the kernel runs one wave per SIMD)
-  h->b_wgs = (lowrank ? 4 : 2) * std::max(ncu, 1);
+  // dense: two-wavefront work-groups, one per SIMD pair (the low-rank classes
+  // size their own grids above)
+  h->b_wgs = 2 * ncu;
   h->b_ws = ws;
   return DMFT_OK;
 }

@@ -114,9 +114,13 @@ struct BatchItemHost {
 };
 hipError_t launch_batched(const void* items, int n_big, int n_small, const DysonArgs* args, int* counters,
                           int n_workgroups, hipStream_t s);
-// The same walk in the low-rank form: every item takes one single-wavefront work-group.
-hipError_t launch_batched_lr(const void* items, int n_items, const DysonArgs* args, int* counters, int n_workgroups,
-                             hipStream_t s);
+// The low-rank form: one persistent kernel per class (padded size nbp, ncls
+// columns of the row-layout inversions, lr_nc_class) over items[0 .. n_items),
+// pulling from *counter (reset to 0 before the launch); grid work-groups of 64
+// threads, or 128 for nbp = 64 (two-wavefront items).
+int lr_nc_class(int nbp, int nc);
+hipError_t launch_lr_class(int nbp, int ncls, const void* items, int n_items, const DysonArgs* args, int* counter,
+                           int grid, hipStream_t s);
 hipError_t launch_copy_doubles(const double* src, double* dst, int n, hipStream_t s);
 // DMFT self-consistency step: E_imp (device [nc][nc] complex) and Delta (device [nw][nc][nc]);
 // part holds self_consistency_parts(nk) x nc x nc complex partials of E_imp.

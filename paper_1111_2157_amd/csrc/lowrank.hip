@@ -14,8 +14,22 @@ int lowrank_variants_16(int kind, int* out, int max);
 int lowrank_variants_32(int kind, int* out, int max);
 int lowrank_variants_48(int kind, int* out, int max);
 int lowrank_variants_64(int kind, int* out, int max);
+hipError_t launch_lowrank_pair64(const DysonArgs& a, dim3 grid, hipStream_t s);
+hipError_t launch_lr_class_16(int ncls, const void* items, int n_items, const DysonArgs* args, int* counter, int grid,
+                              hipStream_t s);
+hipError_t launch_lr_class_32(int ncls, const void* items, int n_items, const DysonArgs* args, int* counter, int grid,
+                              hipStream_t s);
+hipError_t launch_lr_class_48(int ncls, const void* items, int n_items, const DysonArgs* args, int* counter, int grid,
+                              hipStream_t s);
+hipError_t launch_lr_class_64(int ncls, const void* items, int n_items, const DysonArgs* args, int* counter, int grid,
+                              hipStream_t s);
+
+// Code 40 (low-rank bit 3, pair bit 5): the two-wavefront kernel for 64-band
+// windows of lowrank_pair_impl.h, density kind only.
+constexpr int kPairVariant = 40;
 
 hipError_t launch_lowrank(int nbp, int var, const DysonArgs& a, dim3 grid, hipStream_t s) {
+  if (var == kPairVariant) return nbp == 64 ? launch_lowrank_pair64(a, grid, s) : hipErrorInvalidValue;
   switch (nbp) {
     case 16: return launch_lowrank_16(var, a, grid, s);
     case 32: return launch_lowrank_32(var, a, grid, s);
@@ -31,8 +45,33 @@ int lowrank_variants(int nbp, int kind, int* out, int max) {
     case 16: return lowrank_variants_16(kind, out, max);
     case 32: return lowrank_variants_32(kind, out, max);
     case 48: return lowrank_variants_48(kind, out, max);
-    case 64: return lowrank_variants_64(kind, out, max);
+    case 64: {
+      int n = lowrank_variants_64(kind, out, max);
+      if (kind == 0 && n < max) out[n++] = kPairVariant;
+      return n;
+    }
     default: return 0;
+  }
+}
+
+// Column class of the batched kernels: nc rounded up to 8, 10 (32 bands),
+// 12, 14 (48 and 64 bands) or 16.
+int lr_nc_class(int nbp, int nc) {
+  if (nc <= 8) return 8;
+  if (nbp == 32 && nc <= 10) return 10;
+  if (nc <= 12) return 12;
+  if ((nbp == 48 || nbp == 64) && nc <= 14) return 14;
+  return 16;
+}
+
+hipError_t launch_lr_class(int nbp, int ncls, const void* items, int n_items, const DysonArgs* args, int* counter,
+                           int grid, hipStream_t s) {
+  switch (nbp) {
+    case 16: return launch_lr_class_16(ncls, items, n_items, args, counter, grid, s);
+    case 32: return launch_lr_class_32(ncls, items, n_items, args, counter, grid, s);
+    case 48: return launch_lr_class_48(ncls, items, n_items, args, counter, grid, s);
+    case 64: return launch_lr_class_64(ncls, items, n_items, args, counter, grid, s);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -1,0 +1,344 @@
+// Low-rank Dyson step for 64-band windows on a pair of wavefronts (gfx950).
+//
+// The low-rank form (lowrank_impl.h) keeps the running frequency sum of G,
+// a 64 x 64 complex matrix, in the registers of the wavefront that owns the
+// k-point.  With one wavefront that sum only fits in the four-product form and
+// leaves no room for the rest, so a single-wavefront item covers half of the
+// columns and the nc x nc part of the step (X, both inversions, R) is computed
+// twice, once per half.  Here a work-group of two wavefronts shares one item
+// (k-tile, frequency tile):
+//
+//   wavefront w owns the column tiles b = 2w, 2w + 1 of the running sum
+//   (eight 16 x 16 tiles, three-product form) and, for each group of eight
+//   frequencies, the stage of frequencies 4w .. 4w + 3 of the group:
+//
+//   0. d_r = 1 / (i w_n + mu - E_r) of its four frequencies into an LDS table,
+//      and Sigma(i w_n) of the same frequencies staged into LDS;
+//   1. X_f = S D_f S^dag on the matrix cores (contraction over the bands);
+//   2. lane 16 g + i takes row i of X_g: both inversions in the row layout
+//      (rsweep), Gl_g = (X_g^-1 - Sigma'_g)^-1 back to LDS, and the lane's
+//      row of w_k Gl_g added to the G_loc partial (read during the second
+//      inversion);
+//   -- work-group barrier: the d tables, Sigma and Gl of all eight frequencies
+//      are now in LDS --
+//   3. for each of the eight frequencies, both wavefronts: R = Sigma' +
+//      Sigma' Gl Sigma' (recomputed by each: a few nc x nc products), and for
+//      the owned columns Q_b = (R S D)_b and sum_n G[t][b] += (D S^dag)_t Q_b
+//      for all four row tiles t.
+//   -- work-group barrier before the next group overwrites the LDS --
+//
+// so X and the inversions are computed once per frequency, and the running sum
+// uses three matrix-core products per complex product.  Results and partial
+// layouts are those of lr_tile (the same epilogues reduce them).
+#pragma once
+
+#include "lowrank_impl.h"
+
+namespace dmft {
+
+struct LRPairShared {
+  double2 buf[8][16 * 17];  // X, then Gl, of the group's eight frequencies (rows padded to 17)
+  double2 sg[8][16 * 17];   // Sigma(i w_n) of the same frequencies (V_DC is taken off where read)
+  double2 dtab[8][64];      // d_r of the same frequencies (zero past nb)
+};
+
+// Three-product complex multiply-add with the operand sums given.
+__device__ __forceinline__ void mac3(v4d& p1, v4d& p2, v4d& p3, double ar, double ai, double as, double br, double bi,
+                                     double bs) {
+  p1 = mma(ar, br, p1);
+  p2 = mma(ai, bi, p2);
+  p3 = mma(as, bs, p3);
+}
+
+// NC: columns kept in the row-layout inversions (nc <= NC).
+template <int NC>
+__device__ __forceinline__ void lr_pair_tile(const DysonArgs& a, int ktile, int wtile, LRPairShared& sh, int tid) {
+  constexpr int NBP = 64, T = 4;
+  const int w = tid >> 6, lane = tid & 63;
+  const int q = lane >> 4, c16 = lane & 15;
+  const int n0 = wtile * a.wt;
+  const int n1 = min(n0 + a.wt, a.nw);
+  const int kk0 = ktile * a.kt;
+  const int kk1 = min(kk0 + a.kt, a.nklist);
+  const double mu = a.mu_ptr ? *a.mu_ptr : a.mu;
+  const int nc = a.nc;
+  const int kc = (nc + 3) >> 2;
+  // the launch keeps nc <= NC columns and takes more than 8 only for nc > 8
+  __builtin_assume(kc >= 1 && kc <= 4);
+  __builtin_assume(nc >= 1 && nc <= NC);
+  if constexpr (NC > 8) __builtin_assume(nc > 8);
+  const double beta = a.beta;
+  const bool want_s = (a.mode & MODE_S) != 0;
+  const bool want_x = (a.mode & MODE_GLOC) != 0;
+  const bool hasdiag = c16 >= q && ((c16 - q) & 3) == 0;
+  const int idg = (c16 - q) >> 2;
+  // V_DC of orbital c16: every diagonal element of Sigma' a lane reads is (c16, c16)
+  const double edc = c16 < nc ? a.e_dc[c16] : 0.0;
+  int bad = 0, nonfinite = 0;
+
+  for (int kk = kk0; kk < kk1; ++kk) {
+    const int k = a.klist ? a.klist[kk] : kk;
+    const int nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
+    // every k of a 64-band bucket has 48 < nb <= 64 (checked on the host)
+    __builtin_assume(nb > NBP - 16 && nb <= NBP);
+    const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
+    const double* eps = a.eps + ob;
+    const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
+    const double wk = a.wk[k];
+    // running sum of G: all four row tiles of the two owned column tiles
+    v4d s1[T][2], s2[T][2], s3[T][2];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) s1[t][c] = s2[t][c] = s3[t][c] = (v4d){0.0, 0.0, 0.0, 0.0};
+    double2 dsum[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+
+    for (int n = n0; n < n1; n += 8) {
+      // ---- 0. resolvent table and Sigma of this wavefront's four frequencies
+      const int nw0 = n + 4 * w;
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int f = it, r = lane;  // 4 x 64 entries: frequency it, band lane
+        const int nf = min(nw0 + f, n1 - 1);
+        const double wn = (double)(2 * nf + 1) * M_PI / beta;
+        sh.dtab[4 * w + f][r] = r < nb ? inv_z_minus(mu, wn, eps[r]) : make_double2(0.0, 0.0);
+      }
+      // Sigma of the four frequencies, NC x NC positions each, loaded now and
+      // stored to LDS after the X products (their latency hides behind them)
+      constexpr int NPOS = 4 * NC * NC;
+      constexpr int NLD = (NPOS + 63) / 64;
+      double2 sgl[NLD];
+#pragma unroll
+      for (int m = 0; m < NLD; ++m) {
+        const int idx = lane + 64 * m;
+        const int f = idx / (NC * NC), rem = idx - f * (NC * NC);
+        const int ra = rem / NC, cb = rem - ra * NC;
+        const int nf = min(nw0 + f, n1 - 1);
+        const bool in = idx < NPOS && ra < nc && cb < nc;
+        sgl[m] = in ? reinterpret_cast<const double2*>(a.sigma)[(int64_t)nf * nc * nc + ra * nc + cb]
+                    : make_double2(0.0, 0.0);
+      }
+      wave_sync();
+      // ---- 1. X_f = S D_f S^dag of the four frequencies into LDS
+      {
+        double ptr_[T][4], pti_[T][4];
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double2 v = lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb);
+            ptr_[t][i] = v.x;
+            pti_[t][i] = v.y;
+          }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          CAcc<true> x;
+          x.zero();
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              if (16 * t + 4 * i >= nb) break;
+              const double2 s = make_double2(ptr_[t][i], pti_[t][i]);
+              const double2 dd = sh.dtab[4 * w + f][16 * t + 4 * i + q];
+              const double2 a1 = cmul(s, dd);
+              x.mac_cb(a1.x, a1.y, s.x, s.y);
+            }
+          const v4d xr = x.re(), xi = x.im();
+#pragma unroll
+          for (int i = 0; i < 4; ++i) sh.buf[4 * w + f][(q + 4 * i) * 17 + c16] = make_double2(xr[i], xi[i]);
+        }
+      }
+      // Sigma to LDS.  The positions are recomputed from a lane index the
+      // compiler cannot see through, so that they are not kept (and spilled)
+      // across the X products.
+      int lane_r = lane;
+      asm volatile("" : "+v"(lane_r));
+#pragma unroll
+      for (int m = 0; m < NLD; ++m) {
+        const int idx = lane_r + 64 * m;
+        const int f = idx / (NC * NC), rem = idx - f * (NC * NC);
+        const int ra = rem / NC, cb = rem - ra * NC;
+        if (idx < NPOS && ra < nc && cb < nc) sh.sg[4 * w + f][ra * 17 + cb] = sgl[m];
+      }
+      wave_sync();
+      // ---- 2. row layout: invert X, subtract Sigma', invert K -> Gl; G_loc partial
+      {
+        const int g = 4 * w + q, ri = c16;
+        const int nfg = n + g;  // frequencies past n1 were clamped copies: no partial
+        double rr[NC], rim[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const double2 v = sh.buf[g][ri * 17 + j];
+          rr[j] = v.x;
+          rim[j] = v.y;
+        }
+        rsweep<0, NC>(rr, rim, ri, nc, bad);
+        const bool rin = ri < nc;
+        // this lane's row of the G_loc partial of frequency nfg: element
+        // (ri, j) sits at (ri / 4) * 64 + 16 (ri % 4) + j in the partial's
+        // matrix-core lane order; read now, used after the second inversion
+        const bool gl_row = want_x && rin && nfg < n1;
+        double2* prow = reinterpret_cast<double2*>(a.xpart) +
+                        ((int64_t)(a.ktile_base + ktile) * a.nw + min(nfg, n1 - 1)) * 256 + (ri >> 2) * 64 +
+                        16 * (ri & 3);
+        double2 prev[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+          prev[j] = (gl_row && kk != kk0 && j < nc) ? prow[j] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          if (j < nc && rin) {
+            double2 v = sh.sg[g][ri * 17 + j];
+            if (j == ri) v.x -= edc;
+            rr[j] -= v.x;
+            rim[j] -= v.y;
+          }
+        }
+        rsweep<0, NC>(rr, rim, ri, nc, bad);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) sh.buf[g][ri * 17 + j] = make_double2(rr[j], rim[j]);
+        if (gl_row) {
+#pragma unroll
+          for (int j = 0; j < NC; ++j)
+            if (j < nc) prow[j] = make_double2(wk * rr[j] + prev[j].x, wk * rim[j] + prev[j].y);
+        }
+      }
+      __syncthreads();
+      // ---- 3. all eight frequencies: R, the G_loc partial, the owned columns of sum_n G
+      // projector fragments S[q + 4 j][16 t + c16] for every row tile (A operands of
+      // (D S^dag)_t and, for the owned columns, B operands of Q)
+      double par[4][T], pai[4][T];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const double2 v = lr_proj(fresh(P), q + 4 * j, 16 * t + c16, nc, nb);
+          par[j][t] = v.x;
+          pai[j][t] = v.y;
+        }
+#pragma unroll 1
+      for (int f8 = 0; f8 < 8; ++f8) {
+        const int nf = n + f8;
+        if (nf >= n1) break;
+        v4d glr, gli;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double2 v = sh.buf[f8][(q + 4 * i) * 17 + c16];
+          glr[i] = v.x;
+          gli[i] = v.y;
+        }
+        double sa_r[4], sa_i[4];
+        v4d sbr, sbi;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int be = q + 4 * j;
+          const bool in = c16 < nc && be < nc;
+          double2 v = in ? sh.sg[f8][c16 * 17 + be] : make_double2(0.0, 0.0);
+          double2 u = in ? sh.sg[f8][be * 17 + c16] : make_double2(0.0, 0.0);
+          if (in && be == c16) {
+            v.x -= edc;
+            u.x -= edc;
+          }
+          sa_r[j] = v.x;
+          sa_i[j] = v.y;
+          sbr[j] = u.x;
+          sbi[j] = u.y;
+        }
+        // V = Gl^T Sigma'^T, R^T = Sigma'^T + Sigma'^T V
+        CAcc<true> va;
+        va.zero();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (j >= kc) break;
+          va.mac(glr[j], gli[j], sa_r[j], sa_i[j]);
+        }
+        const v4d vr = va.re(), vi = va.im();
+        CAcc<true> ra;
+        ra.set((v4d){sa_r[0], sa_r[1], sa_r[2], sa_r[3]}, (v4d){sa_i[0], sa_i[1], sa_i[2], sa_i[3]});
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (j >= kc) break;
+          ra.mac(sbr[j], sbi[j], vr[j], vi[j]);
+        }
+        const v4d rtr = ra.re(), rti = ra.im();
+        double chk = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
+        if (!__builtin_isfinite(chk)) nonfinite = 1;
+        if (!want_s) continue;
+        // (register arrays are indexed by compile-time values only: the owned
+        // column tiles 2w, 2w + 1 are picked by selects, not by indexing with w)
+        double2 dcol[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) dcol[t] = sh.dtab[f8][16 * t + c16];
+        double2 down[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          down[c] = w ? dcol[2 + c] : dcol[c];
+          dsum[c].x += down[c].x;
+          dsum[c].y += down[c].y;
+        }
+        // Q_b = (R S)_b D_b for the owned column tiles, operand sums formed once
+        double qr[2][4], qi[2][4], qs[2][4];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          CAcc<true> qa;
+          qa.zero();
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (j >= kc) break;
+            qa.mac(rtr[j], rti[j], w ? par[j][2 + c] : par[j][c], w ? pai[j][2 + c] : pai[j][c]);
+          }
+          const v4d xr = qa.re(), xi = qa.im();
+          const double2 db = down[c];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double2 v = cmul(make_double2(xr[i], xi[i]), db);
+            qr[c][i] = v.x;
+            qi[c][i] = v.y;
+            qs[c][i] = v.x + v.y;
+          }
+        }
+        // sum_n G[t][b] += (D S^dag)_t Q_b, contraction over the orbitals
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (j >= kc) break;
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            const double2 aa = cmul(dcol[t], make_double2(par[j][t], -pai[j][t]));
+            const double as = aa.x + aa.y;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) mac3(s1[t][c], s2[t][c], s3[t][c], aa.x, aa.y, as, qr[c][j], qi[c][j], qs[c][j]);
+          }
+        }
+      }
+      __syncthreads();
+    }  // frequency groups
+
+    if (want_s) {
+      double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int b = 2 * w + c;
+          const v4d re = s1[t][c] - s2[t][c], im = s3[t][c] - s1[t][c] - s2[t][c];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int e = (t * T + b) * 4 + i;  // address only: no register indexed by w
+            double2 v = make_double2(re[i], im[i]);
+            if (t == b && hasdiag && idg == i) {
+              v.x += dsum[c].x;
+              v.y += dsum[c].y;
+            }
+            sp[e * 64 + lane] = v;
+          }
+        }
+    }
+  }  // k
+  if (bad) atomicOr(a.err, ERR_SINGULAR);
+  if (nonfinite) atomicOr(a.err, ERR_NONFINITE);
+}
+
+}  // namespace dmft
