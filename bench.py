@@ -1,23 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark of the lattice Dyson step on one MI355X.
 
-A step is one full pass of the hot path over the d-shell workload (Nk=512,
-Nb=32, Nc=10 in two 5-orbital sites, beta=40/eV, Nw=1024 positive Matsubara
-frequencies, complex128): build A(k, i w_n), invert it, project to G_loc,
-Matsubara-sum into N(k) with the analytic tail, and reduce N_tot, n_corr and
-<H_KS> -- i.e. one density_matrix call with every output.  Inputs are seeded
-synthetic arrays resident in HBM before the timed region starts.
+A step is one full pass of the hot path over the batched workload: 8
+self-energy iterates (4 with Nc = 5, 4 with Nc = 14) on Nk = 4096 k-points whose
+band windows are drawn from U{20..64}, beta = 40/eV, Nw = 2048 positive
+Matsubara frequencies, complex128.  For every iterate, k and frequency the
+pass builds A(k, i w_n), inverts it (low-rank form), projects to G_loc and
+Matsubara-sums N(k) with the analytic tail -- the batched plan's persistent
+launches, replayed from the hipGraph they were captured into.  Inputs are
+seeded synthetic arrays resident in HBM before the timed region starts.
 
 The JSON line also carries
-  * "roofline": achieved FP64 rate of the dominant kernel (the Dyson kernel)
-    from its average duration, measured with hipEvents on its own stream
-    inside the timed region, against the MI355X FP64 peak;
-  * "cpu_baseline": the FP64 CPU oracle timed on a bounded sample of the same
-    workload on this host's cores;
+  * "roofline": achieved FP64 rate of the batched Dyson section (the class
+    kernels of one pass, which run concurrently) from its average duration,
+    measured with hipEvents captured into the graph around it and read after
+    every replay of the timed region, against the MI355X FP64 peak; the
+    algorithmic count is the low-rank form's 8 (Nb^2 Nc + 2 Nb Nc^2 + 5 Nc^3)
+    flop per (k, i w_n) evaluation, summed over the ragged windows;
+  * "cpu_baseline": the FP64 CPU oracle timed on a bounded k-sample of every
+    iterate on this host's cores;
   * "mu_search": Newton (dN/dmu from the adjoint trace pass) against
     bisection, same kernels, bracket [-40, 40] eV, start at its midpoint,
     stop at |N - N0| < 1e-8, on the differentiation workload (Nk=1024, Nb=40,
-    Nc=14, beta=50, Nw=2048, N0=20).
+    Nc=14, beta=50, Nw=2048, N0=20);
+  * "workloads": the d-shell and f-shell density passes and the differentiation
+    workload's fused forward + adjoint pass, each with its own kernel rate.
 """
 from __future__ import annotations
 
@@ -36,51 +43,37 @@ FP64_PEAK_TFLOPS = 78.6
 # LDS bandwidth of the chip: 256 CUs x 128 B/clk x 2.4 GHz
 LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
 
-# HBM traffic of the timed kernel per launch, from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch, scaled by 2 and 1 as a plain 1 GiB copy reads
-# under --copy-calibration), recorded in profiles/lr_kernel_d-shell.md, for each
-# frequency tile (kt, wt) the autotuner may keep: the partial sums it writes
-# depend on the tile.  Valid only for the kernel sources it was measured on
-# (their SHA-256), the same workload, variant and tile; otherwise "traffic" is null.
-_D32 = "d-shell-Nk512-Nb32-Nc10-Nw1024"
-_SHA = "e689bc9aa5c484392041fafbf38ebe64e90375e56b65a25143c36de85ed66764"
-TRAFFIC = {
-    (_D32, 32, 10, 2, 256): {"fetch_bytes": 336611.0625 * 2 * 1024, "write_bytes": 851968.0 * 1024},
-    (_D32, 32, 10, 2, 128): {"fetch_bytes": 341987.5 * 2 * 1024, "write_bytes": 884736.0 * 1024},
-    (_D32, 32, 10, 2, 64): {"fetch_bytes": 345188.5 * 2 * 1024, "write_bytes": 950272.0 * 1024},
-    (_D32, 32, 10, 2, 32): {"fetch_bytes": 351595.5625 * 2 * 1024, "write_bytes": 1081344.0 * 1024},
-}
-for _r in TRAFFIC.values():
-    _r.update(sources_sha256=_SHA, profile="profiles/lr_kernel_d-shell.md")
-TRAFFIC_SOURCES = ["paper_1111_2157_amd/csrc/lowrank_impl.h", "paper_1111_2157_amd/csrc/dyson_impl.h",
-                   "paper_1111_2157_amd/csrc/lowrank_32.hip"]
+# HBM traffic of the batched Dyson section per pass: the sum over its class
+# kernels of rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, scaled
+# by 2 and 1, the factors a plain 1 GiB copy reads under --copy-calibration),
+# recorded in the profile named below.  Valid only for the kernel sources it
+# was measured on (their SHA-256) and the same workload, form and item classes
+# (padded size, inversion columns, items); otherwise "traffic" is null.
+TRAFFIC_SOURCES = ["paper_1111_2157_amd/csrc/lowrank_impl.h", "paper_1111_2157_amd/csrc/lowrank_pair_impl.h",
+                   "paper_1111_2157_amd/csrc/batched_lr.h", "paper_1111_2157_amd/csrc/dyson_impl.h",
+                   "paper_1111_2157_amd/csrc/batched_lr16.hip", "paper_1111_2157_amd/csrc/batched_lr32.hip",
+                   "paper_1111_2157_amd/csrc/batched_lr48.hip", "paper_1111_2157_amd/csrc/batched_lr64.hip"]
+TRAFFIC = {}
 
 
-def tuned_tile(tune):
-    """(kt, wt) of the density pass the autotuner kept, from its report, or None."""
-    import re
-
-    for line in (tune or {}).get("best", []):
-        m = re.match(r"best density: var=\d+ kt=(\d+) wt=(\d+)", line)
-        if m:
-            return int(m.group(1)), int(m.group(2))
-    return None
+def class_key(classes):
+    return tuple((c["nbp"], c["ncls"], c["items"]) for c in classes)
 
 
-def measured_traffic(workload, nbp, var, tile):
-    """Counter-measured HBM bytes per launch of this kernel, or None."""
+def sources_sha256():
     import hashlib
 
-    if tile is None:
-        return None
-    rec = TRAFFIC.get((workload, nbp, var) + tuple(tile))
-    if rec is None:
-        return None
     h = hashlib.sha256()
     for p in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
-    if h.hexdigest() != rec["sources_sha256"]:
+    return h.hexdigest()
+
+
+def measured_traffic(workload, form, classes):
+    """Counter-measured HBM bytes per pass of the class kernels, or None."""
+    rec = TRAFFIC.get((workload, form, class_key(classes)))
+    if rec is None or rec["sources_sha256"] != sources_sha256():
         return None
     return rec
 
@@ -94,10 +87,11 @@ def flops_per_eval(nb, nc):
 
 def flops_per_eval_lowrank(nb, nc):
     """Algorithmic FP64 flops of one density-pass evaluation in the low-rank
-    (Woodbury) form: X = S D S^dag (Nb Nc^2 complex MACs), invert X and
-    K = X^-1 - Sigma' (2 Nc^3), R = Sigma' K^-1 X^-1 (2 Nc^3), R S (Nb Nc^2),
-    D S^dag (R S D) (Nb^2 Nc); 8 real flops per complex multiply-add."""
-    return 8.0 * (nb * nb * nc + 2.0 * nb * nc * nc + 4.0 * nc ** 3)
+    (Woodbury) form, 8 (Nb^2 Nc + 2 Nb Nc^2 + 5 Nc^3): X = S D S^dag and R S
+    (Nb Nc^2 complex multiply-adds each), D S^dag (R S D) (Nb^2 Nc), and the
+    nc x nc work -- two inversions, R = Sigma' + Sigma' Gl Sigma', the G_loc
+    share -- counted as 5 Nc^3; 8 real flops per complex multiply-add."""
+    return 8.0 * (nb * nb * nc + 2.0 * nb * nc * nc + 5.0 * nc ** 3)
 
 
 def density_kernel(ctx, nb, nc):
@@ -119,13 +113,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mu", action="store_true", help="skip the mu-search comparison")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle sample time")
-    ap.add_argument("--extra", action="store_true", help="also time the other workloads")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the d-shell, f-shell and fused-adjoint passes")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU oracle sample time")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time the general VJP, the pole route, the self-consistency step and the atom")
     ap.add_argument("--section", choices=["pole", "sc", "atom", "adj"], default=None,
                     help="time only the pole route, the self-consistency step, the atom and energy "
                          "sums or the two adjoint passes, and print that record")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (use the default variants)")
-    ap.add_argument("--batched", action="store_true", help="also time the batched workload (8 iterates, graph)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device three times (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -177,40 +173,45 @@ def host_cpu():
     return None
 
 
-def cpu_baseline(wl, mu, target_s):
-    """The FP64 oracle on this host's cores (OpenMP over k, at most 16 threads
-    unless ORACLE_THREADS says otherwise) on a bounded k-sample of the same
-    workload, plus a single-thread rate on a smaller sample."""
-    import numpy as np
+def host_nproc():
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count()
 
+
+def cpu_baseline(wl, mu, target_s):
+    """The FP64 oracle (N(k) of every iterate) on this host's cores -- OpenMP
+    over k with ORACLE_THREADS threads, else the host's cores up to 16, the CPU
+    share of one GPU on the machines this runs on -- over the first m k-points
+    of each of the batched workload's iterates, all frequencies; m is sized
+    for about target_s seconds.  The rate is evaluations per second of that
+    sample, which scales linearly (every (k, i w_n) evaluation is independent),
+    plus a single-thread rate on a smaller sample."""
     import oracle
 
-    lat, sig = wl.lattice, wl.sigma
-    cores = int(os.environ.get("ORACLE_THREADS", min(16, os.cpu_count() or 1)))
-    # calibrate on a few k-points, then size the sample to ~target_s
-    t0 = time.perf_counter()
-    oracle.density(lat, sig, mu, 2, klist=list(range(cores)), nthreads=cores)
-    t_cal = time.perf_counter() - t0
-    nsel = int(max(cores, min(lat.nk, cores * max(1, int(target_s / max(t_cal, 1e-3))))))
-    ks = list(range(nsel))
-    t0 = time.perf_counter()
-    oracle.density(lat, sig, mu, 2, klist=ks, nthreads=cores)
-    t = time.perf_counter() - t0
-    evals = nsel * sig.nw
-    # single thread: as many k-points as fit in about a quarter of the target
-    t0 = time.perf_counter()
-    oracle.density(lat, sig, mu, 2, klist=[0], nthreads=1)
-    t1 = time.perf_counter() - t0
-    n1 = int(max(1, min(lat.nk, (target_s / 4) / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.density(lat, sig, mu, 2, klist=list(range(n1)), nthreads=1)
-    t1 = time.perf_counter() - t0
+    lats, sigs = wl.lattices, wl.sigmas
+    cores = int(os.environ.get("ORACLE_THREADS", min(16, host_nproc() or 1)))
+
+    def run(m, threads):
+        t0 = time.perf_counter()
+        for lat, sig in zip(lats, sigs):
+            oracle.density(lat, sig, mu, 2, klist=list(range(m)), nthreads=threads)
+        return time.perf_counter() - t0
+
+    t_cal = run(1, 1)  # one k of each iterate on one thread
+    m = int(max(1, min(lats[0].nk, target_s / max(t_cal, 1e-3) * cores * 0.8)))
+    m = max(cores, (m // cores) * cores)
+    t = run(m, cores)
+    evals = m * sum(s.nw for s in sigs)
+    m1 = int(max(1, min(lats[0].nk, (target_s / 4) / max(t_cal, 1e-3))))
+    t1 = run(m1, 1)
     return {"value": evals / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": "N(k) of the first %d of %d k-points over all %d frequencies (%d evals, %.1f s)"
-                      % (nsel, lat.nk, sig.nw, evals, t),
-            "single_thread": {"value": n1 * sig.nw / t1, "unit": "evals/s",
-                              "sample": "first %d k-points, %.1f s" % (n1, t1)},
-            "host_cpu": host_cpu()}
+            "sample": "N(k) of the first %d k-points of each of the %d iterates over all %d frequencies "
+                      "(%d evals, %.1f s); G_loc not formed" % (m, len(lats), sigs[0].nw, evals, t),
+            "single_thread": {"value": m1 * sum(s.nw for s in sigs) / t1, "unit": "evals/s",
+                              "sample": "first %d k-points of each iterate, %.1f s" % (m1, t1)},
+            "host_cpu": host_cpu(), "host_nproc": host_nproc(), "host_cpu_count": os.cpu_count()}
 
 
 def adjoint_pass(ctx, tune=True):
@@ -499,44 +500,87 @@ def mu_search(ctx, tune=True):
     return out
 
 
-def batched(ctx, steps=2):
-    """The batched workload: Nk=4096, nb_k ~ U{20..64}, 8 self-energy iterates
-    (Nc 5 and 14), Nw=2048, beta=40: one persistent launch per pass, replayed
-    from its hipGraph."""
+def batched_flops(wl):
+    """Algorithmic low-rank flops of one batched pass, summed over the ragged windows."""
+    fl = 0.0
+    for lat, sig in zip(wl.lattices, wl.sigmas):
+        fl += sig.nw * float(np.sum(flops_per_eval_lowrank(lat.nb.astype(float), float(lat.nc))))
+    return fl
+
+
+def batched_headline(ctx, steps, warmup, tune=True):
+    """The batched workload: plan (the autotuner picks the form and tiles),
+    capture one pass into a hipGraph with kernel timing on, replay it warmup
+    times, then time steps replays.  Returns the record's measurement fields."""
     import torch
 
     from paper_1111_2157_amd import synth
-    from paper_1111_2157_amd.dyson import Lattice, SelfEnergy
+    from paper_1111_2157_amd.dyson import FORM_AUTO, FORM_LOWRANK, Lattice, SelfEnergy
 
     wl = synth.batched()
     lats = [Lattice.from_host(l) for l in wl.lattices]
     sigs = [SelfEnergy.from_host(s) for s in wl.sigmas]
+    ctx.batched_set_form(FORM_AUTO if tune else FORM_LOWRANK)
     t0 = time.perf_counter()
     ctx.batched_plan(lats, sigs, 2)
     plan_s = time.perf_counter() - t0
     mu_dev = torch.zeros(len(lats), dtype=torch.float64, device="cuda")
     nks, gls = ctx.batched_outputs()
+    ctx.timing(True)
     ctx.batched_graph_capture(mu_dev, nks, gls)
     torch.cuda.synchronize()
     ctx.batched_sync_status()
+    for _ in range(warmup):
+        ctx.batched_graph_launch()
+    torch.cuda.synchronize()
+    ctx.timing(True)  # reads the warm-up replays and starts counting afresh
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         ctx.batched_graph_launch()
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
+    kms, launches = ctx.timing(False)
+    ctx.batched_sync_status()
+    # per-class kernel durations (concurrent, so they overlap) from two directly
+    # enqueued passes: a graph replay is timed as a whole
+    ctx.timing(True)
+    for _ in range(2):
+        ctx.batched_pass(mu_dev, nks, gls)
+    torch.cuda.synchronize()
+    direct_ms, npass = ctx.timing(False)
+    classes = ctx.batched_classes()
+    ctx.batched_sync_status()
     evals = sum(l.nk for l in wl.lattices) * wl.sigmas[0].nw
-    from paper_1111_2157_amd.dyson import FORM_LOWRANK
-    lowrank = ctx.batched_form() == FORM_LOWRANK
-    per_eval = flops_per_eval_lowrank if lowrank else flops_per_eval
-    flops = 0.0
-    for l, s in zip(wl.lattices, wl.sigmas):
-        flops += s.nw * float(np.sum(per_eval(l.nb.astype(float), float(l.nc))))
+    fl = batched_flops(wl)
+    kavg = kms / max(launches, 1) / 1e3
+    for c in classes:
+        c["kernel_ms_per_pass"] = c.pop("kernel_ms") / max(npass, 1)
+    from paper_1111_2157_amd.dyson import FORM_LOWRANK as LR
+    form = "low-rank" if ctx.batched_form() == LR else "dense"
     del nks, gls
     ctx._b_ws = None
     torch.cuda.empty_cache()
-    return {"workload": wl.name, "evals_per_s": evals / sec, "ms_per_pass": sec * 1e3,
-            "form": "low-rank" if lowrank else "dense", "tflops": flops / sec / 1e12,
-            "plan_seconds": plan_s, "graph": True}
+    return wl, {"sec": sec, "evals": evals, "flops": fl, "kernel_s": kavg, "launches": launches,
+                "classes": classes, "plan_seconds": plan_s, "form": form,
+                "direct_pass_ms": direct_ms / max(npass, 1)}
+
+
+def density_workload(ctx, wl, steps, tune):
+    """One autotuned density pass (N(k), G_loc, scalars) of a single-lattice workload."""
+    from paper_1111_2157_amd.dyson import Lattice, SelfEnergy
+
+    lat, sig = Lattice.from_host(wl.lattice), SelfEnergy.from_host(wl.sigma)
+    if tune:
+        ctx.autotune(lat, sig, wl.mu)
+    sec, kms, ln = time_density(ctx, lat, sig, wl.mu, steps, 1)
+    nb, nc = wl.lattice.nb_max, wl.lattice.nc
+    ev = wl.lattice.nk * sig.nw
+    kn, fp = density_kernel(ctx, nb, nc)
+    kavg = kms / max(ln, 1) / 1e3
+    return {"evals_per_s": ev / sec, "ms_per_pass": sec * 1e3, "kernel": kn, "kernel_ms": kavg * 1e3,
+            "flop_per_eval": fp, "kernel_tflops": fp * ev / kavg / 1e12,
+            "kernel_frac": fp * ev / kavg / 1e12 / FP64_PEAK_TFLOPS}
 
 
 def main():
@@ -548,91 +592,74 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
-    if args.section:
-        from paper_1111_2157_amd.dyson import Context
+    from paper_1111_2157_amd.dyson import Context
 
-        ctx = Context(0)
+    ctx = Context(0)
+    if args.section:
         rec = {"pole": lambda: pole_route(ctx, not args.no_tune), "sc": lambda: self_consistency(ctx),
                "atom": lambda: atom_section(ctx),
                "adj": lambda: adjoint_section(ctx, not args.no_tune)}[args.section]()
         print(json.dumps({"section": args.section, "result": rec}), flush=True)
         return
-    import torch
-
     from paper_1111_2157_amd import synth
-    from paper_1111_2157_amd.dyson import Context, Lattice, SelfEnergy
 
-    wl = synth.d_shell()
-    lat, sig = Lattice.from_host(wl.lattice), SelfEnergy.from_host(wl.sigma)
-    ctx = Context(0)
-    mu = wl.mu
-    tune = None
-    if not args.no_tune:
-        t0 = time.perf_counter()
-        rep = ctx.autotune(lat, sig, mu)
-        tune = {"seconds": time.perf_counter() - t0,
-                "best": [l for l in rep.splitlines() if l.startswith("best")]}
-    sec, kms, launches = time_density(ctx, lat, sig, mu, args.steps, args.warmup)
-    nk, nw, nb, nc = wl.lattice.nk, sig.nw, wl.lattice.nb_max, wl.lattice.nc
-    evals = nk * nw
-    kname, fpe = density_kernel(ctx, nb, nc)
-    nbp = (nb + 15) // 16 * 16
-    tile = tuned_tile(tune)
-    traffic = measured_traffic(wl.name, nbp, ctx.get_variant(0, nbp), tile)
-    fl = fpe * evals
-    kavg = kms / max(launches, 1) / 1e3
-    achieved = fl / kavg / 1e12
+    wl, m = batched_headline(ctx, args.steps, args.warmup, not args.no_tune)
+    achieved = m["flops"] / m["kernel_s"] / 1e12
+    traffic = measured_traffic(wl.name, m["form"], m["classes"])
     rec = {
         "metric": "(k,iw) Dyson evals/s",
-        "value": evals / sec,
+        "value": m["evals"] / m["sec"],
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sec * 1e3,
+        "ms_per_step": m["sec"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "nk": nk, "nb": nb, "nc": nc, "nw": nw, "beta": sig.beta,
-                   "mu": mu, "outputs": "N(k), G_loc, N_tot/n_corr/<H_KS>", "tail_order": 2},
+        "config": {"workload": wl.name, "nk": wl.lattices[0].nk, "iterates": len(wl.lattices),
+                   "nb": "U{%d..%d}" % (int(wl.lattices[0].nb.min()), int(wl.lattices[0].nb.max())),
+                   "nc": sorted({l.nc for l in wl.lattices}), "nw": wl.sigmas[0].nw, "beta": wl.sigmas[0].beta,
+                   "mu": 0.0, "outputs": "N(k) and G_loc of every iterate", "tail_order": 2,
+                   "graph": True, "form": m["form"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": (traffic["fetch_bytes"] + traffic["write_bytes"]) if traffic else None,
-                     "traffic_unit": "bytes per launch (HBM, counters)",
-                     "traffic_gbps": ((traffic["fetch_bytes"] + traffic["write_bytes"]) / kavg / 1e9) if traffic else None,
+                     "traffic": traffic["bytes"] if traffic else None,
+                     "traffic_unit": "HBM bytes per pass of the class kernels (counters)",
+                     "traffic_gbps": traffic["bytes"] / m["kernel_s"] / 1e9 if traffic else None,
                      "traffic_profile": traffic["profile"] if traffic else None,
-                     "kernel": kname, "kernel_tile": list(tile) if tile else None,
-                     "kernel_ms": kavg * 1e3, "flop_per_eval": fpe,
-                     "dense_flop_per_eval": flops_per_eval(nb, nc)},
-        "autotune": tune,
+                     "kernel": "batched low-rank Dyson pass: %d concurrent class launches and the epilogue "
+                               "reductions, timed per graph replay" % len(m["classes"]),
+                     "kernel_ms": m["kernel_s"] * 1e3, "timed_launches": m["launches"],
+                     "dyson_section_ms_direct": m["direct_pass_ms"],
+                     "flop_per_pass": m["flops"],
+                     "flop_count": "8 (Nb^2 Nc + 2 Nb Nc^2 + 5 Nc^3) per (k, i w_n), low-rank form"},
+        "batched_classes": m["classes"],
+        "plan_seconds": m["plan_seconds"],
     }
     if not args.no_mu:
         rec["mu_search"] = mu_search(ctx, not args.no_tune)
+    if not args.no_workloads:
+        tune = not args.no_tune
+        wls = {}
+        for maker, steps in ((synth.d_shell, 10), (synth.f_shell, 3)):
+            w = maker()
+            wls[w.name] = density_workload(ctx, w, steps, tune)
+        wls["diff fused forward + adjoint (N_tot, dN/dmu, dN/dSigma)"] = adjoint_pass(ctx)
+        rec["workloads"] = wls
     if args.extra:
         extra = {}
-        for name, maker in (("plain", synth.plain), ("f-shell", synth.f_shell), ("diff", synth.differentiation)):
-            w = maker()
-            l2, s2 = Lattice.from_host(w.lattice), SelfEnergy.from_host(w.sigma)
-            if not args.no_tune:
-                ctx.autotune(l2, s2, w.mu)
-            sc, km, ln = time_density(ctx, l2, s2, w.mu, 3 if name != "plain" else 20, 1)
-            ev = w.lattice.nk * s2.nw
-            kn, fp = density_kernel(ctx, w.lattice.nb_max, w.lattice.nc)
-            f = fp * ev
-            extra[w.name] = {"evals_per_s": ev / sc, "ms_per_pass": sc * 1e3, "kernel": kn,
-                             "kernel_tflops": f / (km / max(ln, 1) / 1e3) / 1e12}
-        extra["adjoint (N_tot, dN/dmu, dN/dSigma)"] = adjoint_pass(ctx)
+        w = synth.plain()
+        extra[w.name] = density_workload(ctx, w, 20, not args.no_tune)
         extra["general VJP (Sigma-bar, mu-bar)"] = general_vjp_pass(ctx)
         extra["self-consistency (E_imp, Delta)"] = self_consistency(ctx)
         extra["pole route"] = pole_route(ctx, not args.no_tune)
         extra["atom and energy"] = atom_section(ctx)
         rec["extra"] = extra
-    if args.batched:
-        rec["batched"] = batched(ctx)
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(wl, mu, args.cpu_seconds)
+        rec["cpu_baseline"] = cpu_baseline(wl, 0.0, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
 
 

@@ -252,6 +252,18 @@ enum { DMFT_FORM_AUTO = -1, DMFT_FORM_DENSE = 0, DMFT_FORM_LOWRANK = 1 };
 int dmft_batched_set_form(dmft_handle h, int form);
 int dmft_batched_form(dmft_handle h);
 
+/* Item classes of the current low-rank batched plan.  Its items are grouped
+ * by padded band-window size and column count of the nc x nc inversions; each
+ * class is one persistent launch, and the launches of a pass run concurrently
+ * on side streams of the handle (joined back into the pass's stream, also
+ * inside a captured graph).  Writes up to max entries (HOST arrays, any may be
+ * NULL): nbp, ncls, items per class, and the class kernel's summed duration in
+ * ms over the dmft_batched_pass calls timed since dmft_timing(h, 1, ...) (graph
+ * replays are timed as a whole; reading waits for the last timed pass).
+ * Returns the number of classes (0 without a low-rank plan) or a negative
+ * status. */
+int dmft_batched_classes(dmft_handle h, int max, int32_t* nbp, int32_t* ncls, int32_t* items, double* kernel_ms);
+
 /* Autotuner: times every compiled kernel variant of the three kinds (density
  * pass, trace pass, fused scalar adjoint) that fits this shape on the
  * handle's GPU, with a few frequency-tile sizes, after checking that each one
@@ -289,14 +301,20 @@ int dmft_get_variant(dmft_handle h, int kind, int nbp);
 
 /* Kernel timing (for roofline reports).  enable = 1 clears the counters and
  * starts recording a pair of hipEvents around every launch of the Dyson kernel
- * (on the stream it is launched on); enable = 0 stops recording.  Every call
- * first waits for the events recorded so far and returns, in HOST memory,
- * the summed kernel time in ms and the number of timed launches (either
- * pointer may be NULL).  Timing adds two event records per launch. */
+ * (on the stream it is launched on); enable = 0 stops recording.  A batched
+ * pass counts as one launch: its events bracket all class kernels of the pass
+ * (from before the fork to after the join); a graph replay is bracketed by a
+ * pair around hipGraphLaunch on the launch stream, which also covers the
+ * pass's epilogue reductions (dmft_batched_graph_launch reads the previous
+ * replay's events before launching the next).  Every call first
+ * waits for the events recorded so far and returns, in HOST memory, the
+ * summed kernel time in ms and the number of timed launches (either pointer
+ * may be NULL).  Timing adds two event records per launch. */
 int dmft_timing(dmft_handle h, int enable, double* kernel_ms, int64_t* launches);
 
 /* Synchronise `stream` and report the error word kept in ws (then clear it). */
 int dmft_sync_status(dmft_handle h, void* ws, hipStream_t stream);
+
 
 
 /* ------------------------------------------------------------------------

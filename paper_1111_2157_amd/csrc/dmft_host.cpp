@@ -91,6 +91,23 @@ struct dmft_handle_s {
     int nbp, ncls, off, count, grid;
   };
   std::vector<LRClassPlan> b_cls;
+  // the class kernels of a pass run concurrently on side streams (fork/join,
+  // also inside a captured graph), so that the tail of one class overlaps the
+  // next class instead of idling the chip; all streams have the default priority
+  std::vector<hipStream_t> b_side;
+  hipEvent_t b_fork = nullptr;
+  std::vector<hipEvent_t> b_join;
+  // kernel timing of the batched pass: one event pair around the whole Dyson
+  // section and one per class, recorded by every timed pass and read before
+  // the next one; a graph replay is timed by a pair around hipGraphLaunch
+  // (events recorded inside a captured graph carry no usable timestamps here),
+  // which then also covers the pass's epilogue reductions
+  std::pair<hipEvent_t, hipEvent_t> b_tspan{nullptr, nullptr};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> b_tcls;
+  bool b_tpending = false;   // span events of a pass not yet read
+  bool b_tcls_pending = false;  // per-class events of that pass recorded too
+  bool b_capturing = false;  // batched_pass_impl runs under stream capture
+  std::vector<double> b_cls_ms;
   int b_form_pref = DMFT_FORM_AUTO;      // form requested for later plans
   void* b_ws = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -105,6 +122,8 @@ struct dmft_handle_s {
 };
 
 namespace {
+
+int batched_harvest(dmft_handle h);
 
 int fail(dmft_handle h, int code, const char* fmt, ...) {
   if (h) {
@@ -522,6 +541,19 @@ int dmft_destroy(dmft_handle h) {
   if (!h) return DMFT_EINVAL;
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->cap_stream) (void)hipStreamSynchronize(h->cap_stream);
+  for (hipStream_t st : h->b_side) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (hipEvent_t e : h->b_join) (void)hipEventDestroy(e);
+  if (h->b_fork) (void)hipEventDestroy(h->b_fork);
+  if (h->b_tspan.first) (void)hipEventDestroy(h->b_tspan.first);
+  if (h->b_tspan.second) (void)hipEventDestroy(h->b_tspan.second);
+  for (auto& ev : h->b_tcls) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->staged) {
     (void)hipEventSynchronize(h->staged);
@@ -679,6 +711,8 @@ int dmft_set_variant(dmft_handle h, int kind, int nbp, int var) {
 
 int dmft_timing(dmft_handle h, int enable, double* kernel_ms, int64_t* launches) {
   if (!h) return DMFT_EINVAL;
+  int rb = batched_harvest(h);
+  if (rb) return rb;
   for (auto& ev : h->tev) {
     HIPCHK(h, hipEventSynchronize(ev.second));
     float ms = 0.f;
@@ -693,6 +727,7 @@ int dmft_timing(dmft_handle h, int enable, double* kernel_ms, int64_t* launches)
   if (enable) {
     h->t_ms = 0.0;
     h->t_count = 0;
+    std::fill(h->b_cls_ms.begin(), h->b_cls_ms.end(), 0.0);
   }
   h->timing = enable != 0;
   return DMFT_OK;
@@ -1018,6 +1053,56 @@ int batched_layout(dmft_handle h, int n_iter, const dmft_lattice* const* lat, co
   return DMFT_OK;
 }
 
+// Side streams and fork/join events of the concurrent class launches.
+int batched_streams(dmft_handle h, int nside) {
+  while ((int)h->b_side.size() < nside) {
+    hipStream_t st = nullptr;
+    HIPCHK(h, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    h->b_side.push_back(st);
+    hipEvent_t e = nullptr;
+    HIPCHK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->b_join.push_back(e);
+  }
+  if (!h->b_fork) HIPCHK(h, hipEventCreateWithFlags(&h->b_fork, hipEventDisableTiming));
+  return DMFT_OK;
+}
+
+// Timing events of the current plan (one pair per class and one for the span).
+int batched_events(dmft_handle h) {
+  if (!h->b_tspan.first) {
+    HIPCHK(h, hipEventCreate(&h->b_tspan.first));
+    HIPCHK(h, hipEventCreate(&h->b_tspan.second));
+  }
+  while (h->b_tcls.size() < h->b_cls.size()) {
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    HIPCHK(h, hipEventCreate(&ev.first));
+    HIPCHK(h, hipEventCreate(&ev.second));
+    h->b_tcls.push_back(ev);
+  }
+  if (h->b_cls_ms.size() < h->b_cls.size()) h->b_cls_ms.resize(h->b_cls.size(), 0.0);
+  return DMFT_OK;
+}
+
+// Reads the timing events of the last timed batched pass (waits for it) and
+// adds them to the handle's kernel time: the span counts as one launch.
+int batched_harvest(dmft_handle h) {
+  if (!h->b_tpending) return DMFT_OK;
+  h->b_tpending = false;
+  HIPCHK(h, hipEventSynchronize(h->b_tspan.second));
+  float ms = 0.f;
+  HIPCHK(h, hipEventElapsedTime(&ms, h->b_tspan.first, h->b_tspan.second));
+  h->t_ms += ms;
+  h->t_count += 1;
+  if (h->b_tcls_pending) {
+    h->b_tcls_pending = false;
+    for (size_t c = 0; c < h->b_cls.size() && c < h->b_tcls.size(); ++c) {
+      HIPCHK(h, hipEventElapsedTime(&ms, h->b_tcls[c].first, h->b_tcls[c].second));
+      h->b_cls_ms[c] += ms;
+    }
+  }
+  return DMFT_OK;
+}
+
 int batched_pass_impl(dmft_handle h, const double* mu_dev, double* const* nk_out, double* const* gloc_out,
                       void* ws, size_t ws_bytes, hipStream_t stream, bool kernel_only) {
   if (h->iters.empty()) return fail(h, DMFT_EINVAL, "no batched plan (call dmft_batched_plan first)");
@@ -1025,17 +1110,40 @@ int batched_pass_impl(dmft_handle h, const double* mu_dev, double* const* nk_out
   if (!mu_dev) return fail(h, DMFT_EINVAL, "mu_dev is NULL");
   char* w = (char*)ws;
   int n_iter = (int)h->iters.size();
+  const bool timed = h->timing && !kernel_only && !h->b_capturing;
+  if (timed) {
+    int r = batched_harvest(h);  // the previous pass's events are re-recorded below
+    if (r) return r;
+    r = batched_events(h);
+    if (r) return r;
+  }
   HIPCHK(h, launch_copy_doubles(mu_dev, (double*)(w + h->b_mu), n_iter, stream));
   HIPCHK(h, launch_fill_zero(w + h->b_counters, kMaxQueues * sizeof(int), stream));
+  if (timed) HIPCHK(h, hipEventRecord(h->b_tspan.first, stream));
   if (h->b_lowrank) {
+    const int nside = (int)h->b_side.size();
+    HIPCHK(h, hipEventRecord(h->b_fork, stream));
+    for (hipStream_t st : h->b_side) HIPCHK(h, hipStreamWaitEvent(st, h->b_fork, 0));
     for (size_t c = 0; c < h->b_cls.size(); ++c) {
       const auto& k = h->b_cls[c];
+      hipStream_t st = h->b_side[c % nside];
+      if (timed) HIPCHK(h, hipEventRecord(h->b_tcls[c].first, st));
       HIPCHK(h, launch_lr_class(k.nbp, k.ncls, w + h->b_items + sizeof(BatchItemHost) * k.off, k.count,
-                                (const DysonArgs*)(w + h->b_args), (int*)(w + h->b_counters) + c, k.grid, stream));
+                                (const DysonArgs*)(w + h->b_args), (int*)(w + h->b_counters) + c, k.grid, st));
+      if (timed) HIPCHK(h, hipEventRecord(h->b_tcls[c].second, st));
+    }
+    for (int i = 0; i < nside; ++i) {
+      HIPCHK(h, hipEventRecord(h->b_join[i], h->b_side[i]));
+      HIPCHK(h, hipStreamWaitEvent(stream, h->b_join[i], 0));
     }
   } else
     HIPCHK(h, launch_batched(w + h->b_items, h->b_nbig, h->b_nsmall, (const DysonArgs*)(w + h->b_args),
                              (int*)(w + h->b_counters), h->b_wgs, stream));
+  if (timed) {
+    HIPCHK(h, hipEventRecord(h->b_tspan.second, stream));
+    h->b_tpending = true;
+    h->b_tcls_pending = h->b_lowrank;
+  }
   if (kernel_only) return DMFT_OK;
   for (int s = 0; s < n_iter; ++s) {
     const auto& it = h->iters[s];
@@ -1164,6 +1272,9 @@ int batched_build(dmft_handle h, int n_iter, const dmft_lattice* const* lat, con
       h->b_cls.push_back(c);
     }
     if ((int)h->b_cls.size() > kMaxQueues) return fail(h, DMFT_EUNSUPPORTED, "too many item classes");
+    int rs = batched_streams(h, std::min<int>(3, (int)h->b_cls.size()));
+    if (rs) return rs;
+    h->b_cls_ms.assign(h->b_cls.size(), 0.0);
   }
   HIPCHK(h, hipMemcpy(w + o_args, args.data(), sizeof(DysonArgs) * args.size(), hipMemcpyHostToDevice));
   if (!items.empty())
@@ -1228,12 +1339,16 @@ int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
-  double best = 1e300;
+  double best = 1e300, best_lowrank = 1e300;
   std::vector<Tile> best_tiles = base_tiles;
-  bool best_lr = false;
-  for (bool lr : {false, true}) {
+  bool best_lr = true;
+  // low-rank form first; the dense form's other tiles are timed only when its
+  // first one comes within 1.5x of the best low-rank plan
+  for (bool lr : {true, false}) {
     if (h->b_form_pref != DMFT_FORM_AUTO && lr != (h->b_form_pref == DMFT_FORM_LOWRANK)) continue;
+    double first = -1.0;
     for (int f : {1, 2, 4}) {
+      if (!lr && first > 1.5 * best_lowrank) break;
       std::vector<Tile> cand = base_tiles;
       for (int s = 0; s < n_iter; ++s) cand[s].wt = std::max(4, base_tiles[s].wt / f);
       std::vector<Layout> Ls;
@@ -1253,6 +1368,8 @@ int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
       HIPCHK(h, hipEventSynchronize(e1));
       float ms = 0.f;
       HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+      if (first < 0) first = ms;
+      if (lr) best_lowrank = std::min(best_lowrank, (double)ms);
       if (ms < best) {
         best = ms;
         best_tiles = cand;
@@ -1285,7 +1402,9 @@ int dmft_batched_graph_capture(dmft_handle h, const double* mu_dev, double* cons
     h->graph = nullptr;
   }
   HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  h->b_capturing = true;  // no timing events inside the graph
   int r = batched_pass_impl(h, mu_dev, nk_out, gloc_out, ws, ws_bytes, h->cap_stream, false);
+  h->b_capturing = false;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
   if (r) {
@@ -1306,6 +1425,21 @@ int dmft_batched_set_form(dmft_handle h, int form) {
   return DMFT_OK;
 }
 
+int dmft_batched_classes(dmft_handle h, int max, int32_t* nbp, int32_t* ncls, int32_t* items, double* kernel_ms) {
+  if (!h) return DMFT_EINVAL;
+  if (h->iters.empty() || !h->b_lowrank) return 0;
+  int rb = batched_harvest(h);
+  if (rb) return rb;
+  const int n = (int)h->b_cls.size();
+  for (int c = 0; c < n && c < max; ++c) {
+    if (nbp) nbp[c] = h->b_cls[c].nbp;
+    if (ncls) ncls[c] = h->b_cls[c].ncls;
+    if (items) items[c] = h->b_cls[c].count;
+    if (kernel_ms) kernel_ms[c] = c < (int)h->b_cls_ms.size() ? h->b_cls_ms[c] : 0.0;
+  }
+  return n;
+}
+
 int dmft_batched_form(dmft_handle h) {
   if (!h || h->iters.empty()) return -1;
   return h->b_lowrank ? DMFT_FORM_LOWRANK : DMFT_FORM_DENSE;
@@ -1314,7 +1448,18 @@ int dmft_batched_form(dmft_handle h) {
 int dmft_batched_graph_launch(dmft_handle h, hipStream_t stream) {
   if (!h) return DMFT_EINVAL;
   if (!h->gexec) return fail(h, DMFT_EINVAL, "no captured graph");
+  if (h->timing) {
+    int r = batched_harvest(h);  // the previous pass's or replay's events
+    if (r) return r;
+    r = batched_events(h);
+    if (r) return r;
+    HIPCHK(h, hipEventRecord(h->b_tspan.first, stream));
+  }
   HIPCHK(h, hipGraphLaunch(h->gexec, stream));
+  if (h->timing) {
+    HIPCHK(h, hipEventRecord(h->b_tspan.second, stream));
+    h->b_tpending = true;
+  }
   return DMFT_OK;
 }
 

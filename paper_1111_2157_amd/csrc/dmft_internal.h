@@ -122,6 +122,7 @@ int lr_nc_class(int nbp, int nc);
 hipError_t launch_lr_class(int nbp, int ncls, const void* items, int n_items, const DysonArgs* args, int* counter,
                            int grid, hipStream_t s);
 hipError_t launch_copy_doubles(const double* src, double* dst, int n, hipStream_t s);
+
 // DMFT self-consistency step: E_imp (device [nc][nc] complex) and Delta (device [nw][nc][nc]);
 // part holds self_consistency_parts(nk) x nc x nc complex partials of E_imp.
 constexpr int kScParts = 1024;

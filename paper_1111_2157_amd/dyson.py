@@ -287,6 +287,22 @@ class Context:
         """Form of the current batched plan (FORM_DENSE or FORM_LOWRANK), -1 without a plan."""
         return int(self.lib.dmft_batched_form(self.h))
 
+    def batched_classes(self):
+        """Item classes of the low-rank batched plan: list of dicts with the
+        padded size, inversion columns, item count and summed kernel ms since
+        timing was enabled."""
+        n = self.lib.dmft_batched_classes(self.h, 0, None, None, None, None)
+        if n < 0:
+            check(self.h, n)
+        nbp, ncls, items = (np.zeros(max(n, 1), np.int32) for _ in range(3))
+        ms = np.zeros(max(n, 1), np.float64)
+        n = self.lib.dmft_batched_classes(self.h, n, nbp.ctypes.data_as(C.c_void_p), ncls.ctypes.data_as(C.c_void_p),
+                                          items.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p))
+        if n < 0:
+            check(self.h, n)
+        return [{"nbp": int(nbp[i]), "ncls": int(ncls[i]), "items": int(items[i]), "kernel_ms": float(ms[i])}
+                for i in range(n)]
+
     def _batched_ptrs(self, outs):
         n = len(self._b_ls)
         return (C.c_void_p * n)(*[(o.data_ptr() if o is not None else 0) for o in outs])
