@@ -315,6 +315,24 @@ int dmft_timing(dmft_handle h, int enable, double* kernel_ms, int64_t* launches)
 /* Synchronise `stream` and report the error word kept in ws (then clear it). */
 int dmft_sync_status(dmft_handle h, void* ws, hipStream_t stream);
 
+/* density_matrix without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation): the call makes no allocating runtime call
+ * (no device, pinned or event allocation) and runs on the library's own scratch
+ * array, 64 MiB per GPU, held from library load until the process ends.
+ * Arguments and outputs are those of density_matrix, except:
+ *   - band windows must be uniform (lat->nb NULL, or every entry nb_max),
+ *     DMFT_EINVAL otherwise;
+ *   - tiles are coarsened until the pass fits the scratch; a shape whose
+ *     smallest layout needs more returns DMFT_EWORKSPACE before any launch;
+ *   - status: DEVICE int32 [1] or NULL, written on the stream with DMFT_OK,
+ *     DMFT_ESINGULAR or DMFT_ENONFINITE for this call (the scratch's error
+ *     word is cleared at the start of every call).
+ * All calls on one GPU share its scratch array: calls that overlap on one GPU
+ * (two streams, two threads) race and must be ordered by the caller. */
+int density_matrix_noalloc(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu,
+                           int tail_order, double* nk, double* gloc, double* scalars, int32_t* status,
+                           hipStream_t stream);
 
 
 /* ------------------------------------------------------------------------

@@ -22,7 +22,7 @@ EXPORTS = [
     "dmft_hybridization", "dmft_pole_workspace_size", "dmft_pole_eig", "dmft_pole_sweeps",
     "dmft_pole_density", "dmft_pole_find_mu", "dmft_pole_dos", "dmft_pole_energy", "dmft_hubbard1",
     "dmft_sigma_from_poles", "dmft_hubbard1_poles",
-    "dmft_sync_status",
+    "dmft_sync_status", "density_matrix_noalloc",
 ]
 
 STATUS = {0: "DMFT_OK", -1: "DMFT_EINVAL", -2: "DMFT_EHIP", -3: "DMFT_ENONFINITE",
@@ -101,6 +101,7 @@ def load():
         "dmft_batched_set_form": ([P, I], I),
         "dmft_batched_form": ([P], I),
         "dmft_batched_classes": ([P, I, P, P, P, P], I),
+        "density_matrix_noalloc": ([P, lp, sp, D, I, P, P, P, P, P], I),
         "dmft_hybridization": ([P, lp, sp, D, P, P, P, P, S, P], I),
         "dmft_timing": ([P, I, C.POINTER(D), C.POINTER(C.c_int64)], I),
         "dmft_sync_status": ([P, P, P], I),

@@ -500,9 +500,74 @@ int ntot_impl(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, con
 
 }  // namespace
 
+// ============================================================ allocation-free density pass
+
+namespace dmft {
+
+// density_matrix on a caller-independent scratch buffer (the library's
+// file-scope device array, see noalloc.hip): uniform band windows only, so the
+// per-k metadata is generated on the device instead of staged through pinned
+// host memory, and tiles coarsened until the layout fits `cap` bytes.  Makes
+// no allocating call: no device or pinned allocation, no event creation.
+int density_noalloc_impl(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu, int tail_order,
+                         double* nk, double* gloc, double* scalars, int32_t* status, hipStream_t s) {
+  if (!h) return DMFT_EINVAL;
+  if (tail_order != 0 && tail_order != 2) return fail(h, DMFT_EINVAL, "tail_order must be 0 or 2");
+  if (!nk && !gloc && !scalars) return fail(h, DMFT_EINVAL, "no output requested");
+  if (!std::isfinite(mu)) return fail(h, DMFT_EINVAL, "mu is not finite");
+  int r = check_shapes(h, lat, sig);
+  if (r) return r;
+  if (lat->nb)
+    for (int k = 0; k < lat->nk; ++k)
+      if (lat->nb[k] != lat->nb_max)
+        return fail(h, DMFT_EINVAL, "the allocation-free pass takes uniform band windows (nb[%d] = %d, nb_max = %d)",
+                    k, lat->nb[k], lat->nb_max);
+  dmft_lattice u = *lat;
+  u.nb = nullptr;
+  const size_t cap = noalloc_scratch_bytes();
+  Layout L;
+  Tile t = choose_tile(h, KIND_DENSITY, u.nk, sig->nw, nbp_of(u.nb_max));
+  for (;;) {
+    r = make_layout(h, &u, sig, L, KIND_DENSITY, &t);
+    if (r) return r;
+    if (L.total <= cap) break;
+    // fewer k tiles shrink the G_loc partials, fewer frequency tiles those of sum_n G
+    if (t.kt < u.nk) {
+      t.kt = std::min(u.nk, 2 * t.kt);
+    } else if (t.wt < sig->nw) {
+      t.wt = std::min(sig->nw, 2 * t.wt);
+    } else {
+      return fail(h, DMFT_EWORKSPACE, "this shape needs %zu bytes of scratch; the allocation-free scratch holds %zu",
+                  L.total, cap);
+    }
+  }
+  if (h->device < 0) return fail(h, DMFT_EINVAL, "handle has no device (planning handle)");
+  char* w = (char*)noalloc_scratch(h->device);
+  if (!w) return fail(h, DMFT_EHIP, "no scratch address for device %d", h->device);
+  HIPCHK(h, hipSetDevice(h->device));
+  // metadata and a cleared error word (a kernel: the scratch keeps the last call's contents)
+  HIPCHK(h, launch_uniform_meta(u.nk, u.nb_max, nbp_of(u.nb_max), (int32_t*)(w + L.meta_nb),
+                                (int64_t*)(w + L.meta_offb), (int64_t*)(w + L.meta_offn), (int32_t*)(w + L.meta_nbp),
+                                (int32_t*)(w + L.meta_klist), (int64_t*)(w + L.meta_offs), (int*)(w + L.err), s));
+  const bool timing = h->timing;
+  h->timing = false;  // timing would create events
+  r = density_impl(h, &u, sig, L, w, mu, nullptr, tail_order, nk, gloc, scalars, s);
+  h->timing = timing;
+  if (r) return r;
+  if (status) HIPCHK(h, launch_status_code((const int*)(w + L.err), status, s));
+  return DMFT_OK;
+}
+
+}  // namespace dmft
+
 // ============================================================================ C ABI
 
 extern "C" {
+
+int density_matrix_noalloc(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, double mu, int tail_order,
+                           double* nk, double* gloc, double* scalars, int32_t* status, hipStream_t stream) {
+  return dmft::density_noalloc_impl(h, lat, sig, mu, tail_order, nk, gloc, scalars, status, stream);
+}
 
 const char* dmft_strerror(int status) {
   switch (status) {
@@ -531,6 +596,8 @@ int dmft_create(dmft_handle* out, int device) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DMFT_EHIP;
   if (hipSetDevice(device) != hipSuccess) return DMFT_EHIP;
+  // the allocation-free entry point's scratch address on this device (once per device)
+  if (noalloc_setup(device) != hipSuccess) return DMFT_EHIP;
   dmft_handle h = new dmft_handle_s;
   h->device = device;
   *out = h;

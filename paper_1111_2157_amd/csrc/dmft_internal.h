@@ -122,7 +122,17 @@ int lr_nc_class(int nbp, int nc);
 hipError_t launch_lr_class(int nbp, int ncls, const void* items, int n_items, const DysonArgs* args, int* counter,
                            int grid, hipStream_t s);
 hipError_t launch_copy_doubles(const double* src, double* dst, int n, hipStream_t s);
-
+// Allocation-free entry point (noalloc.hip): the library's device scratch array.
+// noalloc_setup looks up its address on `device` (current) once per device;
+// noalloc_scratch returns it (nullptr before setup), noalloc_scratch_bytes its size.
+hipError_t noalloc_setup(int device);
+void* noalloc_scratch(int device);
+size_t noalloc_scratch_bytes();
+// Per-k metadata of a uniform lattice (nb bands, padded size nbp) and a cleared error word.
+hipError_t launch_uniform_meta(int nk, int nb, int nbp, int32_t* nbv, int64_t* offb, int64_t* offn, int32_t* nbpv,
+                               int32_t* klist, int64_t* offs, int* err, hipStream_t s);
+// status[0] = DMFT_ESINGULAR, DMFT_ENONFINITE or DMFT_OK from the error word.
+hipError_t launch_status_code(const int* err, int32_t* status, hipStream_t s);
 // DMFT self-consistency step: E_imp (device [nc][nc] complex) and Delta (device [nw][nc][nc]);
 // part holds self_consistency_parts(nk) x nc x nc complex partials of E_imp.
 constexpr int kScParts = 1024;
