@@ -17,6 +17,9 @@ hipError_t launch_lr_class_32(int ncls, const void* items, int n_items, const Dy
     case 12:
       hipLaunchKernelGGL((lr_class_kernel<32, 0, true, 12>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
       break;
+    case 14:
+      hipLaunchKernelGGL((lr_class_kernel<32, 0, true, 14>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
+      break;
     case 16:
       hipLaunchKernelGGL((lr_class_kernel<32, 0, true, 16>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
       break;

@@ -55,12 +55,14 @@ int lowrank_variants(int nbp, int kind, int* out, int max) {
 }
 
 // Column class of the batched kernels: nc rounded up to 8, 10 (32 bands),
-// 12, 14 (48 and 64 bands) or 16.
+// 12, 14 (32, 48 and 64 bands) or 16.  Every column costs a broadcast and
+// four FMAs in each of the nc pivot steps of both inversions, which on small
+// windows weighs as much as the matrix-core work.
 int lr_nc_class(int nbp, int nc) {
   if (nc <= 8) return 8;
   if (nbp == 32 && nc <= 10) return 10;
   if (nc <= 12) return 12;
-  if ((nbp == 48 || nbp == 64) && nc <= 14) return 14;
+  if (nbp >= 32 && nc <= 14) return 14;
   return 16;
 }
 

@@ -261,6 +261,47 @@ __device__ __forceinline__ void rsweep(double (&rr)[NC], double (&ri)[NC], int i
   }
 }
 
+// S[c16 & 7][r] from the lane's S[c16][r] when nc <= 8: rows 8 .. 15 of S are
+// zero, so adding the value eight lanes away along the 16-lane row (row_ror:8)
+// moves S[c16 - 8][r] into lanes 8 .. 15 and leaves lanes 0 .. 7 unchanged.
+__device__ __forceinline__ double2 lower_rows8(double2 s) {
+  return make_double2(s.x + __builtin_amdgcn_update_dpp(0.0, s.x, 0x128, 0xf, 0xf, true),
+                      s.y + __builtin_amdgcn_update_dpp(0.0, s.y, 0x128, 0xf, 0xf, true));
+}
+
+// X_f = S D_f S^dag of the four frequencies of a group when nc <= 8: two
+// frequencies per matrix-core product, stacked in the A rows (row 8 h + alpha
+// holds S[alpha][r] d_{2c + h}[r]); the B columns are S[beta][r]^* as before.
+// Output register i holds row 4 i + q, i.e. frequency 2c + (i >> 1), row
+// 4 (i & 1) + q: half the products of one frequency per product.
+template <int NBP, int RL, bool M3>
+__device__ __forceinline__ void lr_x_packed(const Proj<NBP>& pr, const double2* P, int nc, int nb, LRShared& sh,
+                                            int q, int c16) {
+  constexpr int T = NBP / 16;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int fa = 2 * c + (c16 >> 3);  // frequency of this lane's A row
+    CAcc<M3> x;
+    x.zero();
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (16 * t + 4 * i >= nb) break;
+        const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
+                                  : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
+        const double2 sa = lower_rows8(s);
+        const double2 dd = sh.dtab[fa][16 * t + 4 * i + q];
+        const double2 a1 = cmul(sa, dd);
+        x.mac_cb(a1.x, a1.y, s.x, s.y);
+      }
+    const v4d xr = x.re(), xi = x.im();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      sh.buf[2 * c + (i >> 1)][(4 * (i & 1) + q) * 17 + c16] = make_double2(xr[i], xi[i]);
+  }
+}
+
 template <int NBP, int KIND, int RL, bool M3, int NC, int PART>
 __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int wtile, LRShared& sh, int lane) {
   constexpr int T = NBP / 16;
@@ -389,24 +430,28 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
       // 1. X of the four frequencies n .. n+3 (repeating the last one past n1)
       //    into LDS, in the output layout of the matrix core
       if constexpr (RL == 1) lr_load_pt<NBP>(pr, fresh(P), nc, nb, q, c16);
+      if constexpr (NC <= 8) {
+        lr_x_packed<NBP, RL, M3>(pr, P, nc, nb, sh, q, c16);
+      } else {
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        CAcc<M3> x;
-        x.zero();
+        for (int f = 0; f < 4; ++f) {
+          CAcc<M3> x;
+          x.zero();
 #pragma unroll
-        for (int t = 0; t < T; ++t)
+          for (int t = 0; t < T; ++t)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (16 * t + 4 * i >= nb) break;
-            const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
-                                      : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
-            const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
-            double2 a1 = cmul(s, dd);
-            x.mac_cb(a1.x, a1.y, s.x, s.y);
-          }
-        const v4d xr = x.re(), xi = x.im();
+            for (int i = 0; i < 4; ++i) {
+              if (16 * t + 4 * i >= nb) break;
+              const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
+                                        : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
+              const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
+              double2 a1 = cmul(s, dd);
+              x.mac_cb(a1.x, a1.y, s.x, s.y);
+            }
+          const v4d xr = x.re(), xi = x.im();
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sh.buf[f][(q + 4 * i) * 17 + c16] = make_double2(xr[i], xi[i]);
+          for (int i = 0; i < 4; ++i) sh.buf[f][(q + 4 * i) * 17 + c16] = make_double2(xr[i], xi[i]);
+        }
       }
       wave_sync();
       // 2. row layout: invert X, subtract Sigma', invert K -> Gl, back to LDS

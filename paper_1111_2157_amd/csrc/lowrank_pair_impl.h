@@ -14,7 +14,8 @@
 //
 //   0. d_r = 1 / (i w_n + mu - E_r) of its four frequencies into an LDS table,
 //      and Sigma(i w_n) of the same frequencies staged into LDS;
-//   1. X_f = S D_f S^dag on the matrix cores (contraction over the bands);
+//   1. X_f = S D_f S^dag on the matrix cores (contraction over the bands; for
+//      nc <= 8 two frequencies per product, see lr_x_packed);
 //   2. lane 16 g + i takes row i of X_g: both inversions in the row layout
 //      (rsweep), Gl_g = (X_g^-1 - Sigma'_g)^-1 back to LDS, and the lane's
 //      row of w_k Gl_g added to the G_loc partial (read during the second
@@ -130,23 +131,48 @@ __device__ __forceinline__ void lr_pair_tile(const DysonArgs& a, int ktile, int 
             ptr_[t][i] = v.x;
             pti_[t][i] = v.y;
           }
+        if constexpr (NC <= 8) {
+          // two frequencies per product, stacked in the A rows (see lr_x_packed)
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-          CAcc<true> x;
-          x.zero();
+          for (int c = 0; c < 2; ++c) {
+            const int fa = 4 * w + 2 * c + (c16 >> 3);
+            CAcc<true> x;
+            x.zero();
 #pragma unroll
-          for (int t = 0; t < T; ++t)
+            for (int t = 0; t < T; ++t)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              if (16 * t + 4 * i >= nb) break;
-              const double2 s = make_double2(ptr_[t][i], pti_[t][i]);
-              const double2 dd = sh.dtab[4 * w + f][16 * t + 4 * i + q];
-              const double2 a1 = cmul(s, dd);
-              x.mac_cb(a1.x, a1.y, s.x, s.y);
-            }
-          const v4d xr = x.re(), xi = x.im();
+              for (int i = 0; i < 4; ++i) {
+                if (16 * t + 4 * i >= nb) break;
+                const double2 s = make_double2(ptr_[t][i], pti_[t][i]);
+                const double2 sa = lower_rows8(s);
+                const double2 dd = sh.dtab[fa][16 * t + 4 * i + q];
+                const double2 a1 = cmul(sa, dd);
+                x.mac_cb(a1.x, a1.y, s.x, s.y);
+              }
+            const v4d xr = x.re(), xi = x.im();
 #pragma unroll
-          for (int i = 0; i < 4; ++i) sh.buf[4 * w + f][(q + 4 * i) * 17 + c16] = make_double2(xr[i], xi[i]);
+            for (int i = 0; i < 4; ++i)
+              sh.buf[4 * w + 2 * c + (i >> 1)][(4 * (i & 1) + q) * 17 + c16] = make_double2(xr[i], xi[i]);
+          }
+        } else {
+#pragma unroll
+          for (int f = 0; f < 4; ++f) {
+            CAcc<true> x;
+            x.zero();
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if (16 * t + 4 * i >= nb) break;
+                const double2 s = make_double2(ptr_[t][i], pti_[t][i]);
+                const double2 dd = sh.dtab[4 * w + f][16 * t + 4 * i + q];
+                const double2 a1 = cmul(s, dd);
+                x.mac_cb(a1.x, a1.y, s.x, s.y);
+              }
+            const v4d xr = x.re(), xi = x.im();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sh.buf[4 * w + f][(q + 4 * i) * 17 + c16] = make_double2(xr[i], xi[i]);
+          }
         }
       }
       // Sigma to LDS.  The positions are recomputed from a lane index the
