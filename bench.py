@@ -542,8 +542,9 @@ def batched_headline(ctx, steps, warmup, tune=True):
     sec = (time.perf_counter() - t0) / steps
     kms, launches = ctx.timing(False)
     ctx.batched_sync_status()
-    # per-class kernel durations (concurrent, so they overlap) from two directly
-    # enqueued passes: a graph replay is timed as a whole
+    # per-class kernel durations (overlapping when the plan runs the classes
+    # concurrently) from two directly enqueued passes: a graph replay is timed
+    # as a whole
     ctx.timing(True)
     for _ in range(2):
         ctx.batched_pass(mu_dev, nks, gls)
@@ -558,11 +559,12 @@ def batched_headline(ctx, steps, warmup, tune=True):
         c["kernel_ms_per_pass"] = c.pop("kernel_ms") / max(npass, 1)
     from paper_1111_2157_amd.dyson import FORM_LOWRANK as LR
     form = "low-rank" if ctx.batched_form() == LR else "dense"
+    concurrent = ctx.batched_concurrent() == 1
     del nks, gls
     ctx._b_ws = None
     torch.cuda.empty_cache()
     return wl, {"sec": sec, "evals": evals, "flops": fl, "kernel_s": kavg, "launches": launches,
-                "classes": classes, "plan_seconds": plan_s, "form": form,
+                "classes": classes, "plan_seconds": plan_s, "form": form, "concurrent": concurrent,
                 "direct_pass_ms": direct_ms / max(npass, 1)}
 
 
@@ -630,8 +632,9 @@ def main():
                      "traffic_unit": "HBM bytes per pass of the class kernels (counters)",
                      "traffic_gbps": traffic["bytes"] / m["kernel_s"] / 1e9 if traffic else None,
                      "traffic_profile": traffic["profile"] if traffic else None,
-                     "kernel": "batched low-rank Dyson pass: %d concurrent class launches and the epilogue "
-                               "reductions, timed per graph replay" % len(m["classes"]),
+                     "kernel": "batched low-rank Dyson pass: %d class launches (%s) and the epilogue "
+                               "reductions, timed per graph replay"
+                               % (len(m["classes"]), "concurrent" if m["concurrent"] else "one after another"),
                      "kernel_ms": m["kernel_s"] * 1e3, "timed_launches": m["launches"],
                      "dyson_section_ms_direct": m["direct_pass_ms"],
                      "flop_per_pass": m["flops"],

@@ -254,15 +254,22 @@ int dmft_batched_form(dmft_handle h);
 
 /* Item classes of the current low-rank batched plan.  Its items are grouped
  * by padded band-window size and column count of the nc x nc inversions; each
- * class is one persistent launch, and the launches of a pass run concurrently
- * on side streams of the handle (joined back into the pass's stream, also
- * inside a captured graph).  Writes up to max entries (HOST arrays, any may be
+ * class is one persistent launch.  The launches of a pass run either
+ * concurrently on side streams of the handle (joined back into the pass's
+ * stream, also inside a captured graph) or one after another on the pass's
+ * stream, whichever the plan timed faster (dmft_batched_set_concurrent(h, 1)
+ * or (h, 0) fixes it for later plans instead, (h, -1) restores the timing;
+ * DMFT_EINVAL for another value); dmft_batched_concurrent returns 1 for the
+ * first, 0 for the second and -1 without a low-rank plan.  Writes up
+ * to max entries (HOST arrays, any may be
  * NULL): nbp, ncls, items per class, and the class kernel's summed duration in
  * ms over the dmft_batched_pass calls timed since dmft_timing(h, 1, ...) (graph
  * replays are timed as a whole; reading waits for the last timed pass).
  * Returns the number of classes (0 without a low-rank plan) or a negative
  * status. */
 int dmft_batched_classes(dmft_handle h, int max, int32_t* nbp, int32_t* ncls, int32_t* items, double* kernel_ms);
+int dmft_batched_concurrent(dmft_handle h);
+int dmft_batched_set_concurrent(dmft_handle h, int mode);
 
 /* Autotuner: times every compiled kernel variant of the three kinds (density
  * pass, trace pass, fused scalar adjoint) that fits this shape on the

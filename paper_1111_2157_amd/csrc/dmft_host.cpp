@@ -95,6 +95,8 @@ struct dmft_handle_s {
   // also inside a captured graph), so that the tail of one class overlaps the
   // next class instead of idling the chip; all streams have the default priority
   std::vector<hipStream_t> b_side;
+  bool b_concurrent = true;  // else the classes run one after another on the pass's stream (plan's choice)
+  int b_conc_pref = -1;      // -1: the plan times both; 0 / 1: fixed
   hipEvent_t b_fork = nullptr;
   std::vector<hipEvent_t> b_join;
   // kernel timing of the batched pass: one event pair around the whole Dyson
@@ -1187,7 +1189,15 @@ int batched_pass_impl(dmft_handle h, const double* mu_dev, double* const* nk_out
   HIPCHK(h, launch_copy_doubles(mu_dev, (double*)(w + h->b_mu), n_iter, stream));
   HIPCHK(h, launch_fill_zero(w + h->b_counters, kMaxQueues * sizeof(int), stream));
   if (timed) HIPCHK(h, hipEventRecord(h->b_tspan.first, stream));
-  if (h->b_lowrank) {
+  if (h->b_lowrank && !h->b_concurrent) {
+    for (size_t c = 0; c < h->b_cls.size(); ++c) {
+      const auto& k = h->b_cls[c];
+      if (timed) HIPCHK(h, hipEventRecord(h->b_tcls[c].first, stream));
+      HIPCHK(h, launch_lr_class(k.nbp, k.ncls, w + h->b_items + sizeof(BatchItemHost) * k.off, k.count,
+                                (const DysonArgs*)(w + h->b_args), (int*)(w + h->b_counters) + c, k.grid, stream));
+      if (timed) HIPCHK(h, hipEventRecord(h->b_tcls[c].second, stream));
+    }
+  } else if (h->b_lowrank) {
     const int nside = (int)h->b_side.size();
     HIPCHK(h, hipEventRecord(h->b_fork, stream));
     for (hipStream_t st : h->b_side) HIPCHK(h, hipStreamWaitEvent(st, h->b_fork, 0));
@@ -1444,9 +1454,37 @@ int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
       }
     }
   }
+  r = batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, &best_tiles, best_lr);
+  if (r) return r;
+  // class kernels concurrently on side streams or one after another: the
+  // overlap fills each class's tail but makes the classes share the CUs, so
+  // time both and keep the faster (the later of two timings of each, the first
+  // pass after a rebuild warming the caches)
+  h->b_concurrent = h->b_conc_pref != 0;
+  if (best_lr && h->b_cls.size() > 1 && h->b_conc_pref < 0) {
+    HIPCHK(h, hipMemcpy(w + h->b_mu, mu0.data(), sizeof(double) * n_iter, hipMemcpyHostToDevice));
+    double t[2] = {0.0, 0.0};
+    for (int rep = 0; rep < 2; ++rep)
+      for (int conc = 0; conc < 2; ++conc) {
+        h->b_concurrent = conc != 0;
+        HIPCHK(h, hipEventRecord(e0, stream));
+        r = batched_pass_impl(h, (const double*)(w + h->b_mu), nullptr, nullptr, ws, ws_bytes, stream, true);
+        if (r) return r;
+        HIPCHK(h, hipEventRecord(e1, stream));
+        HIPCHK(h, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+        t[conc] = ms;
+      }
+    h->b_concurrent = t[1] <= t[0];
+    // the timing passes may have flagged the error word (mu = 0 need not suit
+    // the inputs): the plan starts clean, as batched_build leaves it
+    int zero = 0;
+    HIPCHK(h, hipMemcpy(w + h->iters[0].base + h->iters[0].lay.err, &zero, sizeof(int), hipMemcpyHostToDevice));
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, &best_tiles, best_lr);
+  return DMFT_OK;
 }
 
 int dmft_batched_pass(dmft_handle h, const double* mu_dev, double* const* nk_out, double* const* gloc_out, void* ws,
@@ -1505,6 +1543,18 @@ int dmft_batched_classes(dmft_handle h, int max, int32_t* nbp, int32_t* ncls, in
     if (kernel_ms) kernel_ms[c] = c < (int)h->b_cls_ms.size() ? h->b_cls_ms[c] : 0.0;
   }
   return n;
+}
+
+int dmft_batched_set_concurrent(dmft_handle h, int mode) {
+  if (!h) return DMFT_EINVAL;
+  if (mode < -1 || mode > 1) return fail(h, DMFT_EINVAL, "unknown concurrency mode %d", mode);
+  h->b_conc_pref = mode;
+  return DMFT_OK;
+}
+
+int dmft_batched_concurrent(dmft_handle h) {
+  if (!h || h->iters.empty() || !h->b_lowrank) return -1;
+  return h->b_concurrent ? 1 : 0;
 }
 
 int dmft_batched_form(dmft_handle h) {

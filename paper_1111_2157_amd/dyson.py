@@ -287,6 +287,16 @@ class Context:
         """Form of the current batched plan (FORM_DENSE or FORM_LOWRANK), -1 without a plan."""
         return int(self.lib.dmft_batched_form(self.h))
 
+    def batched_set_concurrent(self, mode: int) -> None:
+        """Class kernels of later low-rank batched plans: 1 concurrent, 0 one after
+        another, -1 (default) whichever the plan times faster."""
+        check(self.h, self.lib.dmft_batched_set_concurrent(self.h, int(mode)))
+
+    def batched_concurrent(self) -> int:
+        """1 if the class kernels of the low-rank batched plan run concurrently,
+        0 if one after another, -1 without such a plan."""
+        return int(self.lib.dmft_batched_concurrent(self.h))
+
     def batched_classes(self):
         """Item classes of the low-rank batched plan: list of dicts with the
         padded size, inversion columns, item count and summed kernel ms since

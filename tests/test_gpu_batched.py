@@ -94,3 +94,52 @@ def test_batched_graph_replays(form):
     for a, b in zip(results[0], list(nks) + list(gls)):
         assert torch.equal(a, b)
     ctx.close()
+
+
+def test_batched_class_launch_orders_agree():
+    """The low-rank plan's class kernels run concurrently on side streams or one
+    after another on the pass's stream; both orders (eager and replayed from the
+    graph) give the same bits, since every class writes its own partials, and
+    they match the oracle."""
+    import torch
+    from paper_1111_2157_amd.dyson import FORM_LOWRANK, Context, Lattice, SelfEnergy
+
+    wl = synth.batched(nk=10, nb_lo=14, nb_hi=64, nw=24, n_iter=2)
+    lats = [Lattice.from_host(l) for l in wl.lattices]
+    sigs = [SelfEnergy.from_host(s) for s in wl.sigmas]
+    mus = [0.15, -0.2]
+    outs = {}
+    for mode in (1, 0, -1):
+        print("concurrency mode", mode, flush=True)
+        ctx = Context(0)
+        ctx.batched_set_form(FORM_LOWRANK)
+        ctx.batched_set_concurrent(mode)
+        ctx.batched_plan(lats, sigs, 2)
+        assert len(ctx.batched_classes()) > 1
+        if mode >= 0:
+            assert ctx.batched_concurrent() == mode
+        else:
+            assert ctx.batched_concurrent() in (0, 1)
+        mu_dev = torch.as_tensor(mus, dtype=torch.float64, device="cuda")
+        nks, gls = ctx.batched_outputs()
+        ctx.batched_pass(mu_dev, nks, gls)
+        torch.cuda.synchronize()
+        ctx.batched_sync_status()
+        eager = [x.clone() for x in list(nks) + list(gls)]
+        ctx.batched_graph_capture(mu_dev, nks, gls)
+        torch.cuda.synchronize()
+        ctx.batched_sync_status()
+        for a, b in zip(eager, list(nks) + list(gls)):
+            assert torch.equal(a, b)
+        outs[mode] = eager
+        ctx.close()
+    for a, b, c in zip(outs[1], outs[0], outs[-1]):
+        assert torch.equal(a, b) and torch.equal(a, c)
+    for s in range(2):
+        lat, sig = wl.lattices[s], wl.sigmas[s]
+        assert_nk_parity(_split(outs[0][s].cpu().numpy(), lat), lat, sig, mus[s])
+        assert_gloc_parity(outs[0][2 + s].cpu().numpy(), lat, sig, mus[s])
+    ctx = Context(0)
+    with pytest.raises(Exception):
+        ctx.batched_set_concurrent(2)
+    ctx.close()
