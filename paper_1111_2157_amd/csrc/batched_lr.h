@@ -5,11 +5,12 @@
 // the register allocation and occupancy of its own size only; 64-band items
 // run on two-wavefront work-groups (lowrank_pair_impl.h), the others on one
 // wavefront (lr_tile of lowrank_impl.h, with the variant that is fastest for
-// that size on its own).  The classes are launched one after another on one
+// that size on its own, or for nc <= 5 lr_p3_tile of lowrank_p3_impl.h).  The classes are launched one after another on one
 // stream, largest items first; every work-group pulls items until its queue
 // is empty, so each launch drains.
 #pragma once
 
+#include "lowrank_p3_impl.h"
 #include "lowrank_pair_impl.h"
 
 namespace dmft {
@@ -35,6 +36,24 @@ lr_class_kernel(const BatchItem* items, int n_items, const DysonArgs* args, int*
     const BatchItem b = items[it];
     const DysonArgs a = args[b.args];
     lr_tile<NBP, KIND_DENSITY, RL, M3, NC>(a, b.ktile, b.wtile, 0, sh, lane);
+  }
+}
+
+// Single-wavefront class for nc <= 5, three frequencies per matrix-core tile
+// (lowrank_p3_impl.h): NBP in {16, 32, 48}.
+template <int NBP, int RL, bool M3>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1)))
+lr_p3_class_kernel(const BatchItem* items, int n_items, const DysonArgs* args, int* counter) {
+  __shared__ LRP3Shared<NBP> sh;
+  const int lane = threadIdx.x;
+  for (;;) {
+    int it = 0;
+    if (lane == 0) it = atomicAdd(counter, 1);
+    it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
+    if (it >= n_items) break;
+    const BatchItem b = items[it];
+    const DysonArgs a = args[b.args];
+    lr_p3_tile<NBP, RL, M3>(a, b.ktile, b.wtile, sh, lane);
   }
 }
 

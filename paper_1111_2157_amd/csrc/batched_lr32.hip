@@ -1,5 +1,6 @@
 // Batched low-rank pass: persistent class kernels for band windows padded to 32
-// (see batched_lr.h), one per column count of the row-layout inversions.
+// (see batched_lr.h), one per column count of the row-layout inversions
+// (class 5: nc <= 5, three frequencies per matrix-core tile).
 #include "batched_lr.h"
 
 namespace dmft {
@@ -8,6 +9,9 @@ hipError_t launch_lr_class_32(int ncls, const void* items, int n_items, const Dy
                               int grid, hipStream_t s) {
   const BatchItem* it = reinterpret_cast<const BatchItem*>(items);
   switch (ncls) {
+    case 5:
+      hipLaunchKernelGGL((lr_p3_class_kernel<32, 0, true>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
+      break;
     case 8:
       hipLaunchKernelGGL((lr_class_kernel<32, 0, true, 8>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
       break;

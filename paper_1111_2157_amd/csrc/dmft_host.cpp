@@ -417,7 +417,15 @@ int run_dyson(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, con
       HIPCHK(h, launch_adjoint(b.nbp, adj.gen, a, adj.nbar, L.ragged ? (const int64_t*)(ws + L.meta_offn) : nullptr,
                                adj.gbar, (double*)(ws + L.xpart), (double*)(ws + L.tpart), b.n_ktiles, s));
     } else {
-      int var = choose_var(h, (mode & MODE_TRACE) ? KIND_TRACE : KIND_DENSITY, b.nbp);
+      const int kind = (mode & MODE_TRACE) ? KIND_TRACE : KIND_DENSITY;
+      int var = choose_var(h, kind, b.nbp);
+      // the three-frequency packing serves nc <= 5 only; the variant chosen for
+      // this size (by the autotuner on another shape, or by the caller) falls
+      // back to the size's default elsewhere
+      if (var == kLowrankP3Variant && !lowrank_p3_fits(b.nbp, lat->nc)) {
+        int v[16];
+        var = dyson_variants(b.nbp, kind, v, 16) > 0 ? v[0] : var;
+      }
       HIPCHK(h, launch_dyson(b.nbp, var, a, b.n_ktiles, s));
     }
     if (h->timing) {
@@ -1003,6 +1011,7 @@ int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
     char key[32];
     snprintf(key, sizeof key, "%d/%d", kind, nbp);
     for (int vi = 0; vi < nv; ++vi) {
+      if (vars[vi] == kLowrankP3Variant && !lowrank_p3_fits(nbp, nc)) continue;
       h->tvar[key] = vars[vi];
       for (const Tile& t : tiles) {
         Layout L;

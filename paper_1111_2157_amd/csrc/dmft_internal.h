@@ -91,6 +91,13 @@ struct EpilogueArgs {
 // (lowrank_impl.h; there bit 0 = projector fragments re-read at every use).  dyson_variants lists the
 // instantiated variants of a size and kind (kind 0 = density, 1 = trace); the
 // first one is the default.
+// Low-rank codes with bit 5 set: 40 = the two-wavefront kernel for 64-band
+// windows (lowrank_pair_impl.h), 42 = three frequencies per matrix-core tile for
+// nc <= 5 on windows of up to 48 bands (lowrank_p3_impl.h); both density kind
+// only.  A launch of either outside its shapes returns hipErrorInvalidValue.
+constexpr int kLowrankPairVariant = 40;
+constexpr int kLowrankP3Variant = 42;
+inline bool lowrank_p3_fits(int nbp, int nc) { return nc <= 5 && nbp <= 48; }
 hipError_t launch_dyson(int nbp, int var, const DysonArgs& a, int n_ktiles, hipStream_t s);
 int dyson_variants(int nbp, int kind, int* out, int max);
 bool dyson_supported(int nbp);

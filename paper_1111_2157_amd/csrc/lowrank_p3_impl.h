@@ -1,0 +1,371 @@
+// Low-rank density step for at most five correlated orbitals, three
+// frequencies per matrix-core tile (gfx950 / CDNA4).
+//
+// The step is the one of lowrank_impl.h (Woodbury form of the lattice Dyson
+// equation, embedding of the DMFT-loop section):
+//     X = S D S^dag,  Gl = (X^-1 - Sigma')^-1,  R = Sigma' + Sigma' Gl Sigma',
+//     sum_n G += D + (D S^dag)(R S D),   G_loc partial += w_k Gl.
+// With nc <= 5 an nc x nc matrix fills at most a 5 x 5 corner of a 16 x 16
+// tile, so here three frequencies share every tile, block-diagonally: packed
+// index p = 5 h + alpha (h = 0, 1, 2 the frequency of the slot, alpha < 5 the
+// orbital; p = 15 is unused).  Block-diagonal operands give block-diagonal
+// products, so one chain of 16x16x4 products serves three frequencies:
+//   X    A row p = S[alpha][r] d_h[r], B column beta = S[beta][r]^*  ->  row p, column
+//        beta holds X_h[alpha][beta]  (one product for three frequencies);
+//   V, R  Gl and Sigma' of the slot block-diagonal, contraction over the packed
+//        index: four steps for three frequencies;
+//   Q    = R S_3 D with S_3[5 h + beta][v] = S[beta][v] (the same projector for
+//        every block) and row p scaled by d_h[v];
+//   sum_n G += [D_0 S^dag | D_1 S^dag | D_2 S^dag] Q: the contraction over the
+//        packed index sums the three frequencies' updates at once.
+// Per three frequencies that is X T x 4, V 4, R 4, Q T x 4 and the running sum
+// T^2 x 4 steps (T = padded bands / 16), against three times X T x 2 and V 2,
+// R 2, Q T x 2, sum T^2 x 2 of the two-frequency packing of lowrank_impl.h: a
+// third fewer matrix-core products.
+//
+// A wavefront walks a (k-tile, frequency-tile) item twelve frequencies at a
+// time, in four slots of three:
+//   0. d_r of the twelve frequencies into LDS;
+//   1. X of the four slots (one packed product each) into LDS;
+//   2. row layout, three sub-sweeps: lane 16 g + i holds row i of X of the
+//      frequency 3 g + h of sub-sweep h; both Gauss-Jordan inversions of
+//      lowrank_impl.h (rsweep, five columns), the w_k Gl partial of G_loc
+//      added row by row, and Gl written back block-diagonally;
+//   3. per slot, in the output layout: V, R, Q, the running sum.
+// Frequencies past the tile's end repeat its last one in stages 0-2 (so every
+// inversion is of a valid matrix) and enter stage 3 with d = 0, which removes
+// them from Q and from the running sum.
+#pragma once
+
+#include "lowrank_impl.h"
+
+namespace dmft {
+
+template <int NBP>
+struct LRP3Shared {
+  double2 buf[4][16 * 17];  // per slot: X of its three frequencies, then their block-diagonal Gl
+  double2 dtab[12][NBP];    // d_r = 1 / (i w + mu - E_r) of the group's frequencies (zero past nb)
+};
+
+// S[c16 mod 5][r] from the lane's S[c16][r] when nc <= 5 (rows 5 .. 15 of S are
+// zero): the values five and ten lanes back along the 16-lane row (row_shr:5,
+// row_shr:10; lanes before the row's start read zero) are added.  Lane 15 gets
+// zero, as rows 5, 10 and 15 are zero.
+__device__ __forceinline__ double2 spread5(double2 s) {
+  const double x = s.x + __builtin_amdgcn_update_dpp(0.0, s.x, 0x115, 0xf, 0xf, true) +
+                   __builtin_amdgcn_update_dpp(0.0, s.x, 0x11a, 0xf, 0xf, true);
+  const double y = s.y + __builtin_amdgcn_update_dpp(0.0, s.y, 0x115, 0xf, 0xf, true) +
+                   __builtin_amdgcn_update_dpp(0.0, s.y, 0x11a, 0xf, 0xf, true);
+  return make_double2(x, y);
+}
+
+// Projector fragments of the X products: pt[t][i] = S[c16][16 t + 4 i + q] (B
+// operand, conjugated) and ps[t][i] = S[c16 mod 5][16 t + 4 i + q] (A operand).
+template <int T>
+__device__ __forceinline__ void p3_load_x(double2 (&pt)[T][4], double2 (&ps)[T][4], const double2* P, int nc, int nb,
+                                          int q, int c16) {
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      pt[t][i] = lr_proj(P, c16, 16 * t + 4 * i + q, nc, nb);
+      ps[t][i] = spread5(pt[t][i]);
+    }
+}
+// pk[j][b] = S[aj][16 b + c16]: B operand of R S_3, and (conjugated) of D S^dag.
+template <int T>
+__device__ __forceinline__ void p3_load_k(double2 (&pk)[4][T], const double2* P, const int (&hj)[4],
+                                          const int (&aj)[4], int nc, int nb, int c16) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int b = 0; b < T; ++b)
+      pk[j][b] = hj[j] < 3 ? lr_proj(P, aj[j], 16 * b + c16, nc, nb) : make_double2(0.0, 0.0);
+}
+
+// RL = 0: projector fragments kept in registers for the whole k; RL = 1: loaded
+// per group of twelve frequencies at the start of the stage that uses them
+// (48-band windows, whose fragments would not fit next to the running sum).
+template <int NBP, int RL, bool M3>
+__device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wtile, LRP3Shared<NBP>& sh, int lane) {
+  constexpr int T = NBP / 16;
+  constexpr int NDT = 12 * NBP / 64;  // resolvent-table entries per lane
+  const int q = lane >> 4, c16 = lane & 15;
+  const int g = q, ri = c16;  // row layout: slot g, row ri
+  const int n0 = wtile * a.wt;
+  const int n1 = min(n0 + a.wt, a.nw);
+  const int kk0 = ktile * a.kt;
+  const int kk1 = min(kk0 + a.kt, a.nklist);
+  const double mu = a.mu_ptr ? *a.mu_ptr : a.mu;
+  const int nc = a.nc;
+  // the dispatchers take this kernel for nc <= 5 only
+  __builtin_assume(nc >= 1 && nc <= 5);
+  const double beta = a.beta;
+  const bool want_s = (a.mode & MODE_S) != 0;
+  const bool want_x = (a.mode & MODE_GLOC) != 0;
+  const bool hasdiag = c16 >= q && ((c16 - q) & 3) == 0;
+  const int idg = (c16 - q) >> 2;
+  // packed index of the lane's output column (and A row): c16 = 5 hc + ac
+  const int hc = c16 / 5;  // 3 for c16 = 15: no block
+  const int ac = c16 - 5 * hc;
+  const bool cin = hc < 3 && ac < nc;
+  // packed index q + 4 j of the lane's contraction slot j: 5 hj + aj
+  int hj[4], aj[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    hj[j] = (q + 4 * j) / 5;
+    aj[j] = q + 4 * j - 5 * hj[j];
+  }
+  const double edc_c = cin ? a.e_dc[ac] : 0.0;
+  const double edc_r = ri < nc ? a.e_dc[ri] : 0.0;
+  int bad = 0, nonfinite = 0;
+
+  for (int kk = kk0; kk < kk1; ++kk) {
+    const int k = a.klist ? a.klist[kk] : kk;
+    const int nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
+    __builtin_assume(nb >= 1 && nb <= NBP);
+    // bucketed by padded size (checked on the host before any launch)
+    __builtin_assume(nb > NBP - 16);
+    const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
+    const double* eps = a.eps + ob;
+    double epl[NDT];
+#pragma unroll
+    for (int it = 0; it < NDT; ++it) {
+      const int r = (lane + 64 * it) % NBP;
+      epl[it] = r < nb ? eps[r] : 0.0;
+    }
+    const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
+    const double wk = a.wk[k];
+    double2 pt[T][4], ps[T][4], pk[4][T];
+    if constexpr (RL == 0) {
+      p3_load_x<T>(pt, ps, P, nc, nb, q, c16);
+      p3_load_k<T>(pk, P, hj, aj, nc, nb, c16);
+    }
+    CAcc<M3 && T * T <= 4> sacc[T][T];
+    double2 dsum[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      dsum[t] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int c = 0; c < T; ++c) sacc[t][c].zero();
+    }
+
+    for (int n = n0; n < n1; n += 12) {
+      // 0. d_r of the twelve frequencies (the last one of the tile repeated past n1)
+#pragma unroll
+      for (int it = 0; it < NDT; ++it) {
+        const int idx = lane + 64 * it;
+        const int f = idx / NBP, r = idx - f * NBP;
+        const int nf = min(n + f, n1 - 1);
+        const double wn = (double)(2 * nf + 1) * M_PI / beta;
+        sh.dtab[f][r] = r < nb ? inv_z_minus(mu, wn, epl[it]) : make_double2(0.0, 0.0);
+      }
+      // row ri of Sigma of the three frequencies of slot g, for stage 2 (rows
+      // past nc read row nc - 1 and are discarded there)
+      double2 sgr[3][5];
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        const double2* sp = reinterpret_cast<const double2*>(a.sigma) +
+                            (int64_t)min(n + 3 * g + h, n1 - 1) * nc * nc + min(ri, nc - 1) * nc;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) sgr[h][j] = j < nc ? sp[j] : make_double2(0.0, 0.0);
+      }
+      wave_sync();
+      // 1. X of the four slots, three frequencies per product
+      if constexpr (RL == 1) p3_load_x<T>(pt, ps, fresh(P), nc, nb, q, c16);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (n + 3 * c >= n1) break;
+        const int fa = 3 * c + min(hc, 2);  // frequency of this lane's A row (lane 15: its row is zero)
+        CAcc<M3> x;
+        x.zero();
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (16 * t + 4 * i >= nb) break;
+            const double2 dd = sh.dtab[fa][16 * t + 4 * i + q];
+            const double2 a1 = cmul(ps[t][i], dd);
+            x.mac_cb(a1.x, a1.y, pt[t][i].x, pt[t][i].y);
+          }
+        const v4d xr = x.re(), xi = x.im();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sh.buf[c][(q + 4 * i) * 17 + c16] = make_double2(xr[i], xi[i]);
+      }
+      wave_sync();
+      // 2. row layout: invert X, subtract Sigma', invert K -> Gl; G_loc partial;
+      //    Gl back into the slot's tile, block-diagonally
+      // (slots past the tile's end have no X: their lanes skip the stage, which
+      // leaves every 16-lane row either wholly active or wholly idle)
+      const bool rin = ri < nc;
+      const bool slot_ok = n + 3 * g < n1;
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        if (!slot_ok) break;
+        const int nf = n + 3 * g + h;
+        double rr[5], rim[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          const double2 v = (rin && j < nc) ? sh.buf[g][(5 * h + ri) * 17 + j] : make_double2(0.0, 0.0);
+          rr[j] = v.x;
+          rim[j] = v.y;
+        }
+        rsweep<0, 5>(rr, rim, ri, nc, bad);
+        // this row of the k-tile's G_loc partial (element (r, j) at (r / 4) 64 +
+        // 16 (r % 4) + j), read here so that the load overlaps the second sweep
+        const bool rmw = want_x && rin && nf < n1;
+        double2* prow = reinterpret_cast<double2*>(a.xpart) +
+                        ((int64_t)(a.ktile_base + ktile) * a.nw + min(nf, n1 - 1)) * 256 + (ri >> 2) * 64 +
+                        16 * (ri & 3);
+        double2 prev[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+          prev[j] = (rmw && kk != kk0 && j < nc) ? prow[j] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          if (j < nc) {
+            double2 v = sgr[h][j];
+            if (j == ri) v.x -= edc_r;
+            rr[j] -= rin ? v.x : 0.0;
+            rim[j] -= rin ? v.y : 0.0;
+          }
+        }
+        rsweep<0, 5>(rr, rim, ri, nc, bad);
+        if (rmw) {
+#pragma unroll
+          for (int j = 0; j < 5; ++j)
+            if (j < nc) prow[j] = make_double2(wk * rr[j] + prev[j].x, wk * rim[j] + prev[j].y);
+        }
+        if (ri < 5) {
+#pragma unroll
+          for (int col = 0; col < 16; ++col) {
+            const int j = col - 5 * h;
+            const bool in = j >= 0 && j < 5 && rin && j < nc;
+            double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int jj = 0; jj < 5; ++jj)
+              if (jj == j) v = make_double2(rr[jj], rim[jj]);
+            sh.buf[g][(5 * h + ri) * 17 + col] = in ? v : make_double2(0.0, 0.0);
+          }
+        }
+      }
+      wave_sync();
+      // 3. per slot: R, Q, the running sum of G
+      if constexpr (RL == 1) p3_load_k<T>(pk, fresh(P), hj, aj, nc, nb, c16);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int fb = n + 3 * c;
+        if (fb >= n1) break;
+        v4d glr, gli;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double2 v = sh.buf[c][(q + 4 * i) * 17 + c16];
+          glr[i] = v.x;
+          gli[i] = v.y;
+        }
+        // Sigma' of the slot, block-diagonal: sa[j] = Sigma'[c16][q + 4 j], sb[j] = Sigma'[q + 4 j][c16]
+        const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)min(fb + hc, n1 - 1) * nc * nc;
+        double sa_r[4], sa_i[4];
+        v4d sbr, sbi;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool in = cin && hj[j] == hc && aj[j] < nc;
+          double2 v = in ? sg[ac * nc + aj[j]] : make_double2(0.0, 0.0);
+          double2 u = in ? sg[aj[j] * nc + ac] : make_double2(0.0, 0.0);
+          if (in && aj[j] == ac) {
+            v.x -= edc_c;
+            u.x -= edc_c;
+          }
+          sa_r[j] = v.x;
+          sa_i[j] = v.y;
+          sbr[j] = u.x;
+          sbi[j] = u.y;
+        }
+        // V = Gl^T Sigma'^T, R^T = Sigma'^T + Sigma'^T V
+        CAcc<M3> va;
+        va.zero();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) va.mac(glr[j], gli[j], sa_r[j], sa_i[j]);
+        const v4d vr = va.re(), vi = va.im();
+        CAcc<M3> ra;
+        ra.set((v4d){sa_r[0], sa_r[1], sa_r[2], sa_r[3]}, (v4d){sa_i[0], sa_i[1], sa_i[2], sa_i[3]});
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ra.mac(sbr[j], sbi[j], vr[j], vi[j]);
+        const v4d rtr = ra.re(), rti = ra.im();
+        double chk = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
+        if (!__builtin_isfinite(chk)) nonfinite = 1;
+        // d of the slot's frequencies at band 16 t + c16, for contraction slot j
+        // (zero for frequencies past the tile's end)
+        double2 dk[4][T];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool ok = hj[j] < 3 && fb + hj[j] < n1;
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+            dk[j][t] = ok ? sh.dtab[3 * c + min(hj[j], 2)][16 * t + c16] : make_double2(0.0, 0.0);
+        }
+        // the D term of sum_n G, added to the diagonal once per k
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+          if (fb + h >= n1) break;
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            const double2 d = sh.dtab[3 * c + h][16 * t + c16];
+            dsum[t].x += d.x;
+            dsum[t].y += d.y;
+          }
+        }
+        if (want_s) {
+#pragma unroll
+          for (int b = 0; b < T; ++b) {
+            // Q = R S_3, row p scaled by d of its frequency at band 16 b + c16
+            CAcc<M3> qa;
+            qa.zero();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) qa.mac(rtr[j], rti[j], pk[j][b].x, pk[j][b].y);
+            v4d qr = qa.re(), qi = qa.im();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const double2 v = cmul(make_double2(qr[i], qi[i]), dk[i][b]);
+              qr[i] = v.x;
+              qi[i] = v.y;
+            }
+            // sum_n G (column tile b) += [D_h S^dag]_h Q
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                const double2 aa = cmul(dk[j][t], make_double2(pk[j][t].x, -pk[j][t].y));
+                sacc[t][b].mac(aa.x, aa.y, qr[j], qi[j]);
+              }
+          }
+        }
+      }
+      wave_sync();
+    }  // frequency groups
+
+    if (want_s) {
+      double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int c = 0; c < T; ++c)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int e = (t * T + c) * 4 + i;
+            double2 v = make_double2(sacc[t][c].re()[i], sacc[t][c].im()[i]);
+            if (t == c && hasdiag && idg == i) {
+              v.x += dsum[t].x;
+              v.y += dsum[t].y;
+            }
+            sp[e * 64 + lane] = v;
+          }
+    }
+  }  // k
+  if (bad) atomicOr(a.err, ERR_SINGULAR);
+  if (nonfinite) atomicOr(a.err, ERR_NONFINITE);
+}
+
+}  // namespace dmft
