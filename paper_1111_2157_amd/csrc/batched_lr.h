@@ -5,7 +5,8 @@
 // the register allocation and occupancy of its own size only; 64-band items
 // run on two-wavefront work-groups (lowrank_pair_impl.h), the others on one
 // wavefront (lr_tile of lowrank_impl.h, with the variant that is fastest for
-// that size on its own, or for nc <= 5 lr_p3_tile of lowrank_p3_impl.h).  The classes are launched one after another on one
+// that size on its own, or for nc <= 5 lr_p3_tile of lowrank_p3_impl.h; 64-band
+// items with nc <= 5 run on four wavefronts, lr_p3_quad_tile).  The classes are launched one after another on one
 // stream, largest items first; every work-group pulls items until its queue
 // is empty, so each launch drains.
 #pragma once
@@ -54,6 +55,27 @@ lr_p3_class_kernel(const BatchItem* items, int n_items, const DysonArgs* args, i
     const BatchItem b = items[it];
     const DysonArgs a = args[b.args];
     lr_p3_tile<NBP, RL, M3>(a, b.ktile, b.wtile, sh, lane);
+  }
+}
+
+// Four-wavefront class for 64-band windows and nc <= 5 (lr_p3_quad_tile; a
+// template so that the header defines no kernel of its own).
+template <int NBP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
+lr_p3_quad_class_kernel(const BatchItem* items, int n_items, const DysonArgs* args, int* counter) {
+  __shared__ LRP3QuadShared sh;
+  __shared__ int next;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();
+    if (it >= n_items) break;
+    const BatchItem b = items[it];
+    const DysonArgs a = args[b.args];
+    static_assert(NBP == 64, "four-wavefront items are 64-band windows");
+    lr_p3_quad_tile(a, b.ktile, b.wtile, sh, tid);
   }
 }
 

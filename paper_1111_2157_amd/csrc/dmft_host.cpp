@@ -1352,8 +1352,9 @@ int batched_build(dmft_handle h, int n_iter, const dmft_lattice* const* lat, con
       c.ncls = it->first.second;
       c.off = (int)items.size();
       c.count = (int)qv.size();
-      // one wavefront per SIMD: four single-wavefront or two pair work-groups per CU
-      c.grid = std::min(c.count, (c.nbp == 64 ? 2 : 4) * ncu);
+      // one wavefront per SIMD: four single-wavefront, two pair or one four-wavefront
+      // work-group per CU
+      c.grid = std::min(c.count, lr_class_wgs_per_cu(c.nbp, c.ncls) * ncu);
       for (auto& x : qv) items.push_back(x.it);
       h->b_cls.push_back(c);
     }

@@ -93,11 +93,11 @@ struct EpilogueArgs {
 // first one is the default.
 // Low-rank codes with bit 5 set: 40 = the two-wavefront kernel for 64-band
 // windows (lowrank_pair_impl.h), 42 = three frequencies per matrix-core tile for
-// nc <= 5 on windows of up to 48 bands (lowrank_p3_impl.h); both density kind
-// only.  A launch of either outside its shapes returns hipErrorInvalidValue.
+// nc <= 5 (lowrank_p3_impl.h; 64-band windows on four wavefronts); both density
+// kind only.  A launch of either outside its shapes returns hipErrorInvalidValue.
 constexpr int kLowrankPairVariant = 40;
 constexpr int kLowrankP3Variant = 42;
-inline bool lowrank_p3_fits(int nbp, int nc) { return nc <= 5 && nbp <= 48; }
+inline bool lowrank_p3_fits(int nbp, int nc) { return nc <= 5 && nbp <= 64; }
 hipError_t launch_dyson(int nbp, int var, const DysonArgs& a, int n_ktiles, hipStream_t s);
 int dyson_variants(int nbp, int kind, int* out, int max);
 bool dyson_supported(int nbp);
@@ -124,8 +124,9 @@ hipError_t launch_batched(const void* items, int n_big, int n_small, const Dyson
 // The low-rank form: one persistent kernel per class (padded size nbp, ncls
 // columns of the row-layout inversions, lr_nc_class) over items[0 .. n_items),
 // pulling from *counter (reset to 0 before the launch); grid work-groups of 64
-// threads, or 128 for nbp = 64 (two-wavefront items).
+// threads, or for nbp = 64 128 (two-wavefront items) or 256 (class 5, four).
 int lr_nc_class(int nbp, int nc);
+int lr_class_wgs_per_cu(int nbp, int ncls);  // resident work-groups per CU of a class kernel
 hipError_t launch_lr_class(int nbp, int ncls, const void* items, int n_items, const DysonArgs* args, int* counter,
                            int grid, hipStream_t s);
 hipError_t launch_copy_doubles(const double* src, double* dst, int n, hipStream_t s);

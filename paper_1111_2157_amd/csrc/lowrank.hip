@@ -51,14 +51,15 @@ int lowrank_variants(int nbp, int kind, int* out, int max) {
     case 64: {
       int n = lowrank_variants_64(kind, out, max);
       if (kind == 0 && n < max) out[n++] = kLowrankPairVariant;
+      if (kind == 0 && n < max) out[n++] = kLowrankP3Variant;
       return n;
     }
     default: return 0;
   }
 }
 
-// Column class of the batched kernels: 5 for nc <= 5 on windows of up to 48
-// bands (three frequencies per matrix-core tile), else nc rounded up to 8, 10
+// Column class of the batched kernels: 5 for nc <= 5 (three frequencies per
+// matrix-core tile), else nc rounded up to 8, 10
 // (32 bands), 12, 14 (32, 48 and 64 bands) or 16.  Every column costs a
 // broadcast and four FMAs in each of the nc pivot steps of both inversions,
 // which on small windows weighs as much as the matrix-core work.
@@ -70,6 +71,8 @@ int lr_nc_class(int nbp, int nc) {
   if (nbp >= 32 && nc <= 14) return 14;
   return 16;
 }
+
+int lr_class_wgs_per_cu(int nbp, int ncls) { return nbp < 64 ? 4 : ncls == 5 ? 1 : 2; }
 
 hipError_t launch_lr_class(int nbp, int ncls, const void* items, int n_items, const DysonArgs* args, int* counter,
                            int grid, hipStream_t s) {

@@ -34,10 +34,12 @@
 //   3. per slot, in the output layout: V, R, Q, the running sum.
 // Frequencies past the tile's end repeat its last one in stages 0-2 (so every
 // inversion is of a valid matrix) and enter stage 3 with d = 0, which removes
-// them from Q and from the running sum.
+// them from Q and from the running sum.  64-band windows run the same steps on
+// four wavefronts (lr_p3_quad_tile, below).
 #pragma once
 
 #include "lowrank_impl.h"
+#include "lowrank_pair_impl.h"  // mac3
 
 namespace dmft {
 
@@ -362,6 +364,307 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
             }
             sp[e * 64 + lane] = v;
           }
+    }
+  }  // k
+  if (bad) atomicOr(a.err, ERR_SINGULAR);
+  if (nonfinite) atomicOr(a.err, ERR_NONFINITE);
+}
+
+}  // namespace dmft
+
+namespace dmft {
+
+// 64-band windows on four wavefronts: the work-group (one per CU, 119 KB of
+// LDS) shares one item; each group of 48 frequencies is sixteen slots of
+// three.  Wavefront w runs stages 0-2 (d table, X, the inversions, the G_loc
+// partial) for slots 4 w .. 4 w + 3 and forms their R in place of Gl; a
+// work-group barrier publishes the sixteen R tiles, and then each wavefront
+// runs stage 3 for all sixteen slots on its own column tile w of the running
+// sum (all four row tiles, three products per complex product, 48 registers).
+// Two wavefronts owning two column tiles each would need twice the
+// accumulators, which do not fit next to the rest.
+struct LRP3QuadShared {
+  double2 buf[16][16 * 17];  // per slot: X of its three frequencies, then their Gl, then their R^T
+  double2 dtab[48][64];      // d_r of the group's frequencies (zero past nb)
+};
+
+__device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, int wtile, LRP3QuadShared& sh,
+                                                int tid) {
+  constexpr int T = 4;
+  const int w = tid >> 6, lane = tid & 63;
+  const int q = lane >> 4, c16 = lane & 15;
+  const int n0 = wtile * a.wt;
+  const int n1 = min(n0 + a.wt, a.nw);
+  const int kk0 = ktile * a.kt;
+  const int kk1 = min(kk0 + a.kt, a.nklist);
+  const double mu = a.mu_ptr ? *a.mu_ptr : a.mu;
+  const int nc = a.nc;
+  // the dispatchers take this kernel for nc <= 5 only
+  __builtin_assume(nc >= 1 && nc <= 5);
+  const double beta = a.beta;
+  const bool want_s = (a.mode & MODE_S) != 0;
+  const bool want_x = (a.mode & MODE_GLOC) != 0;
+  const bool hasdiag = c16 >= q && ((c16 - q) & 3) == 0;
+  const int idg = (c16 - q) >> 2;
+  const int hc = c16 / 5;
+  const int ac = c16 - 5 * hc;
+  const bool cin = hc < 3 && ac < nc;
+  int hj[4], aj[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    hj[j] = (q + 4 * j) / 5;
+    aj[j] = q + 4 * j - 5 * hj[j];
+  }
+  const double edc_c = cin ? a.e_dc[ac] : 0.0;
+  const double edc_r = c16 < nc ? a.e_dc[c16] : 0.0;
+  int bad = 0, nonfinite = 0;
+
+  for (int kk = kk0; kk < kk1; ++kk) {
+    const int k = a.klist ? a.klist[kk] : kk;
+    const int nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
+    // every k of a 64-band bucket has 48 < nb <= 64 (checked on the host)
+    __builtin_assume(nb > 48 && nb <= 64);
+    const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
+    const double el = lane < nb ? a.eps[ob + lane] : 0.0;
+    const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
+    const double wk = a.wk[k];
+    v4d s1[T], s2[T], s3[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) s1[t] = s2[t] = s3[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+    double2 dsum = make_double2(0.0, 0.0);
+
+    for (int n = n0; n < n1; n += 48) {
+      // ---- 0. d table of this wavefront's twelve frequencies (band = lane)
+      const int nw0 = n + 12 * w;
+#pragma unroll
+      for (int f = 0; f < 12; ++f) {
+        const int nf = min(nw0 + f, n1 - 1);
+        const double wn = (double)(2 * nf + 1) * M_PI / beta;
+        sh.dtab[12 * w + f][lane] = lane < nb ? inv_z_minus(mu, wn, el) : make_double2(0.0, 0.0);
+      }
+      const int g = q, ri = c16;  // row layout: this wavefront's slot g, row ri
+      const int sl = 4 * w + g;   // slot in the group
+      double2 sgr[3][5];
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        const double2* sp = reinterpret_cast<const double2*>(a.sigma) +
+                            (int64_t)min(n + 3 * sl + h, n1 - 1) * nc * nc + min(ri, nc - 1) * nc;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) sgr[h][j] = j < nc ? sp[j] : make_double2(0.0, 0.0);
+      }
+      wave_sync();
+      // ---- 1. X of this wavefront's four slots
+      {
+        double2 pt[T][4], ps[T][4];
+        p3_load_x<T>(pt, ps, fresh(P), nc, nb, q, c16);
+#pragma unroll 1
+        for (int c = 0; c < 4; ++c) {
+          const int s = 4 * w + c;
+          if (n + 3 * s >= n1) break;
+          const int fa = 3 * s + min(hc, 2);
+          CAcc<true> x;
+          x.zero();
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              if (16 * t + 4 * i >= nb) break;
+              const double2 dd = sh.dtab[fa][16 * t + 4 * i + q];
+              const double2 a1 = cmul(ps[t][i], dd);
+              x.mac_cb(a1.x, a1.y, pt[t][i].x, pt[t][i].y);
+            }
+          const v4d xr = x.re(), xi = x.im();
+#pragma unroll
+          for (int i = 0; i < 4; ++i) sh.buf[s][(q + 4 * i) * 17 + c16] = make_double2(xr[i], xi[i]);
+        }
+      }
+      wave_sync();
+      // ---- 2. row layout, three sub-sweeps per slot
+      {
+        const bool rin = ri < nc;
+        const bool slot_ok = n + 3 * sl < n1;
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+          if (!slot_ok) break;
+          const int nf = n + 3 * sl + h;
+          double rr[5], rim[5];
+#pragma unroll
+          for (int j = 0; j < 5; ++j) {
+            const double2 v = (rin && j < nc) ? sh.buf[sl][(5 * h + ri) * 17 + j] : make_double2(0.0, 0.0);
+            rr[j] = v.x;
+            rim[j] = v.y;
+          }
+          rsweep<0, 5>(rr, rim, ri, nc, bad);
+          const bool rmw = want_x && rin && nf < n1;
+          double2* prow = reinterpret_cast<double2*>(a.xpart) +
+                          ((int64_t)(a.ktile_base + ktile) * a.nw + min(nf, n1 - 1)) * 256 + (ri >> 2) * 64 +
+                          16 * (ri & 3);
+          double2 prev[5];
+#pragma unroll
+          for (int j = 0; j < 5; ++j)
+            prev[j] = (rmw && kk != kk0 && j < nc) ? prow[j] : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int j = 0; j < 5; ++j) {
+            if (j < nc) {
+              double2 v = sgr[h][j];
+              if (j == ri) v.x -= edc_r;
+              rr[j] -= rin ? v.x : 0.0;
+              rim[j] -= rin ? v.y : 0.0;
+            }
+          }
+          rsweep<0, 5>(rr, rim, ri, nc, bad);
+          if (rmw) {
+#pragma unroll
+            for (int j = 0; j < 5; ++j)
+              if (j < nc) prow[j] = make_double2(wk * rr[j] + prev[j].x, wk * rim[j] + prev[j].y);
+          }
+          if (ri < 5) {
+#pragma unroll
+            for (int col = 0; col < 16; ++col) {
+              const int j = col - 5 * h;
+              const bool in = j >= 0 && j < 5 && rin && j < nc;
+              double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+              for (int jj = 0; jj < 5; ++jj)
+                if (jj == j) v = make_double2(rr[jj], rim[jj]);
+              sh.buf[sl][(5 * h + ri) * 17 + col] = in ? v : make_double2(0.0, 0.0);
+            }
+          }
+        }
+      }
+      wave_sync();
+      // ---- 2b. R of this wavefront's four slots, in the output layout, in place of Gl
+#pragma unroll 1
+      for (int c = 0; c < 4; ++c) {
+        const int s = 4 * w + c;
+        const int fb = n + 3 * s;
+        if (fb >= n1) break;
+        v4d glr, gli;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double2 v = sh.buf[s][(q + 4 * i) * 17 + c16];
+          glr[i] = v.x;
+          gli[i] = v.y;
+        }
+        const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)min(fb + hc, n1 - 1) * nc * nc;
+        double sa_r[4], sa_i[4];
+        v4d sbr, sbi;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool in = cin && hj[j] == hc && aj[j] < nc;
+          double2 v = in ? sg[ac * nc + aj[j]] : make_double2(0.0, 0.0);
+          double2 u = in ? sg[aj[j] * nc + ac] : make_double2(0.0, 0.0);
+          if (in && aj[j] == ac) {
+            v.x -= edc_c;
+            u.x -= edc_c;
+          }
+          sa_r[j] = v.x;
+          sa_i[j] = v.y;
+          sbr[j] = u.x;
+          sbi[j] = u.y;
+        }
+        CAcc<true> va;
+        va.zero();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) va.mac(glr[j], gli[j], sa_r[j], sa_i[j]);
+        const v4d vr = va.re(), vi = va.im();
+        CAcc<true> ra;
+        ra.set((v4d){sa_r[0], sa_r[1], sa_r[2], sa_r[3]}, (v4d){sa_i[0], sa_i[1], sa_i[2], sa_i[3]});
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ra.mac(sbr[j], sbi[j], vr[j], vi[j]);
+        const v4d rtr = ra.re(), rti = ra.im();
+        double chk = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
+        if (!__builtin_isfinite(chk)) nonfinite = 1;
+        // each lane overwrites only the elements it has read
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sh.buf[s][(q + 4 * i) * 17 + c16] = make_double2(rtr[i], rti[i]);
+      }
+      __syncthreads();
+      // ---- 3. all sixteen slots: the owned column tile w of sum_n G
+      double2 pk[4][T], pw[4];
+      p3_load_k<T>(pk, fresh(P), hj, aj, nc, nb, c16);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        pw[j] = hj[j] < 3 ? lr_proj(fresh(P), aj[j], 16 * w + c16, nc, nb) : make_double2(0.0, 0.0);
+#pragma unroll 1
+      for (int s = 0; s < 16; ++s) {
+        const int fb = n + 3 * s;
+        if (fb >= n1) break;
+        v4d rtr, rti;  // R^T of the slot (R[c16][q + 4 i])
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double2 v = sh.buf[s][(q + 4 * i) * 17 + c16];
+          rtr[i] = v.x;
+          rti[i] = v.y;
+        }
+        if (!want_s) continue;
+        // d of the slot's frequency of contraction slot j at band 16 t + c16 is
+        // read from the table where it is used (zero for frequencies past the
+        // tile's end), which keeps it out of the registers
+        bool jok[4];
+        int jrow[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          jok[j] = hj[j] < 3 && fb + hj[j] < n1;
+          jrow[j] = 3 * s + min(hj[j], 2);
+        }
+        auto dkv = [&](int j, int t) -> double2 {
+          return jok[j] ? sh.dtab[jrow[j]][16 * t + c16] : make_double2(0.0, 0.0);
+        };
+        // the D term of the owned column tile
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+          if (fb + h >= n1) break;
+          const double2 d = sh.dtab[3 * s + h][16 * w + c16];
+          dsum.x += d.x;
+          dsum.y += d.y;
+        }
+        // Q_w = R S_3 for the owned column tile, rows scaled by d of their frequency
+        double qr[4], qi[4], qs[4];
+        {
+          CAcc<true> qa;
+          qa.zero();
+#pragma unroll
+          for (int j = 0; j < 4; ++j) qa.mac(rtr[j], rti[j], pw[j].x, pw[j].y);
+          const v4d xr = qa.re(), xi = qa.im();
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double2 v = cmul(make_double2(xr[i], xi[i]), dkv(i, w));
+            qr[i] = v.x;
+            qi[i] = v.y;
+            qs[i] = v.x + v.y;
+          }
+        }
+        // sum_n G[t][w] += [D_h S^dag]_h Q_w, contraction over the packed index
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            const double2 aa = cmul(dkv(j, t), make_double2(pk[j][t].x, -pk[j][t].y));
+            mac3(s1[t], s2[t], s3[t], aa.x, aa.y, aa.x + aa.y, qr[j], qi[j], qs[j]);
+          }
+      }
+      __syncthreads();
+    }  // frequency groups
+
+    if (want_s) {
+      double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const v4d re = s1[t] - s2[t], im = s3[t] - s1[t] - s2[t];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = (t * T + w) * 4 + i;  // address only: no register indexed by w
+          double2 v = make_double2(re[i], im[i]);
+          if (t == w && hasdiag && idg == i) {
+            v.x += dsum.x;
+            v.y += dsum.y;
+          }
+          sp[e * 64 + lane] = v;
+        }
+      }
     }
   }  // k
   if (bad) atomicOr(a.err, ERR_SINGULAR);

@@ -13,7 +13,8 @@ int dyson_variants(int nbp, int kind, int* out, int max) {
   out[0] = 8;
   return 1;
 }
-int lr_nc_class(int, int nc) { return nc <= 8 ? 8 : 16; }
+int lr_nc_class(int, int nc) { return nc <= 5 ? 5 : nc <= 8 ? 8 : 16; }
+int lr_class_wgs_per_cu(int nbp, int ncls) { return nbp < 64 ? 4 : ncls == 5 ? 1 : 2; }
 size_t pole_eig_lds_bytes(int nb, int np) { return (size_t)(nb + np + 1) * (nb + np + 1) * 16; }
 int pole_dos_kslices(int nk, int) { return nk < 8 ? nk : 8; }
 int pole_energy_parts(int nk, int) { return nk < 64 ? nk : 64; }

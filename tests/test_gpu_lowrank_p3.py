@@ -1,9 +1,10 @@
 """GPU parity of the low-rank density kernel that packs three frequencies into
-each matrix-core tile (variant code 42, nc <= 5, windows up to 48 bands)
-against the FP64 oracle: every padded size it serves, nc from 1 to 5, full
+each matrix-core tile (variant code 42, nc <= 5; 64-band windows on four
+wavefronts) against the FP64 oracle: every padded size, nc from 1 to 5, full
 self-energies with off-diagonal elements, frequency counts that leave a partial
-group of twelve (and fewer than twelve frequencies), ragged windows, skewed
-projectors, and its fallback to the size's default variant for nc > 5."""
+group (of twelve, or of 48 on 64-band windows) and counts below one group,
+ragged windows, skewed projectors, and the fallback to the size's default
+variant for nc > 5."""
 import numpy as np
 import pytest
 
@@ -20,10 +21,9 @@ def p3_context():
     from paper_1111_2157_amd.dyson import Context
 
     c = Context(0)
-    for nbp in (16, 32, 48):
+    for nbp in (16, 32, 48, 64):
         assert P3 in c.variants(0, nbp), nbp
         c.set_variant(0, nbp, P3)
-    assert P3 not in c.variants(0, 64)
     return c
 
 
@@ -44,6 +44,10 @@ CASES = {
     "nb9-nc2-nw7": (lambda: synth.plain(nk=5, nb=9, nc=2, nw=7), 0.0),
     "nb17-nc1": (lambda: synth.plain(nk=4, nb=17, nc=1, nw=30), 0.5),
     "nb33-nc5-nw12": (lambda: synth.plain(nk=4, nb=33, nc=5, nw=12), -1.0),
+    # 64-band windows: groups of 48 frequencies on four wavefronts
+    "nb64-nc5-full-sigma": (lambda: synth.f_shell(nk=5, nb=64, nc=5, nw=53, n_narrow=10), 0.25),
+    "nb57-nc3-nw30": (lambda: synth.plain(nk=4, nb=57, nc=3, nw=30), -0.5),
+    "nb49-nc1-nw100": (lambda: synth.plain(nk=3, nb=49, nc=1, nw=100), 0.7),
 }
 
 
@@ -60,8 +64,8 @@ def test_p3_density_and_gloc(ctx, name):
 
 @pytest.mark.parametrize("tail", [0, 2])
 def test_p3_ragged_windows(ctx, tail):
-    """Band windows 14..64 of a 5-orbital iterate: the 16-, 32- and 48-band
-    buckets run the packed kernel, the 64-band bucket its own default."""
+    """Band windows 14..64 of a 5-orbital iterate: every bucket runs the packed
+    kernel (the 64-band one on four wavefronts)."""
     wl = synth.batched(nk=24, nb_lo=14, nb_hi=64, nw=40, n_iter=1)
     lat = wl.lattices[0]
     assert lat.nc == 5
