@@ -227,8 +227,11 @@ int find_mu(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig, int t
  * hipGraph.  Per iterate s: nk_out[s] and gloc_out[s] (DEVICE, layouts as in
  * density_matrix; either may be NULL).  lat[s]/sig[s] must stay unchanged
  * between plan and pass.  The plan times the persistent launch for the dense
- * and the low-rank form of the step (see dmft_variants) and a few frequency-
- * tile sizes, and keeps the fastest; this runs the kernel several times. */
+ * and the low-rank form of the step (see dmft_variants) and a few k- and
+ * frequency-tile sizes, and keeps the fastest; this runs the kernel several
+ * times.  dmft_batched_workspace_size covers every tile the plan may take
+ * (smaller k-tiles hold more G_loc partials: for 8 iterates of Nk = 4096,
+ * Nw = 2048 it asks for a few tens of GB). */
 int dmft_batched_workspace_size(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
                                 const dmft_sigma* const* sig, size_t* bytes);
 int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,

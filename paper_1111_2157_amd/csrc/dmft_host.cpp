@@ -1389,6 +1389,33 @@ int batched_build(dmft_handle h, int n_iter, const dmft_lattice* const* lat, con
 
 extern "C" {
 
+// Tiles the batched plan times: the default tile of every iterate and the same
+// with the k-tile halved and quartered (more, smaller items balance the class
+// kernels' last round better, at the price of more G_loc partials), then the
+// frequency tile halved.
+std::vector<std::vector<Tile>> batched_tile_candidates(const std::vector<Tile>& base) {
+  std::vector<std::vector<Tile>> out;
+  for (int f : {1, 2, 4}) {
+    std::vector<Tile> c = base;
+    bool changed = f == 1;
+    for (auto& t : c) {
+      const int kt = std::max(1, t.kt / f);
+      changed |= kt != t.kt;
+      t.kt = kt;
+    }
+    if (changed) out.push_back(c);
+  }
+  std::vector<Tile> c = base;
+  bool changed = false;
+  for (auto& t : c) {
+    const int wt = std::max(4, t.wt / 2);
+    changed |= wt != t.wt;
+    t.wt = wt;
+  }
+  if (changed) out.push_back(c);
+  return out;
+}
+
 int dmft_batched_workspace_size(dmft_handle h, int n_iter, const dmft_lattice* const* lat, const dmft_sigma* const* sig,
                                 size_t* bytes) {
   if (!bytes) return fail(h, DMFT_EINVAL, "bytes is NULL");
@@ -1398,7 +1425,16 @@ int dmft_batched_workspace_size(dmft_handle h, int n_iter, const dmft_lattice* c
   int na, ni;
   int r = batched_layout(h, n_iter, lat, sig, Ls, base, nullptr, &total, &a, &b, &c, &d, &na, &ni);
   if (r) return r;
-  *bytes = total;
+  // room for every tile the plan times
+  std::vector<Tile> tiles;
+  for (auto& L : Ls) tiles.push_back(L.tile);
+  size_t most = total;
+  for (const auto& cand : batched_tile_candidates(tiles)) {
+    r = batched_layout(h, n_iter, lat, sig, Ls, base, &cand, &total, &a, &b, &c, &d, &na, &ni);
+    if (r) return r;
+    most = std::max(most, total);
+  }
+  *bytes = most;
   return DMFT_OK;
 }
 
@@ -1416,8 +1452,8 @@ int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
   }
   int r = batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, nullptr, false);
   if (r) return r;
-  // Autotune the form of the step (dense inversion or low-rank) and the
-  // frequency-tile size of the persistent launch: time the kernel for each
+  // Autotune the form of the step (dense inversion or low-rank) and the k- and
+  // frequency-tile sizes of the persistent launches: time the kernels for each
   // candidate that fits the workspace, keep the fastest plan.
   std::vector<Tile> base_tiles;
   for (auto& it : h->iters) base_tiles.push_back(it.lay.tile);
@@ -1434,10 +1470,8 @@ int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
   for (bool lr : {true, false}) {
     if (h->b_form_pref != DMFT_FORM_AUTO && lr != (h->b_form_pref == DMFT_FORM_LOWRANK)) continue;
     double first = -1.0;
-    for (int f : {1, 2, 4}) {
+    for (const std::vector<Tile>& cand : batched_tile_candidates(base_tiles)) {
       if (!lr && first > 1.5 * best_lowrank) break;
-      std::vector<Tile> cand = base_tiles;
-      for (int s = 0; s < n_iter; ++s) cand[s].wt = std::max(4, base_tiles[s].wt / f);
       std::vector<Layout> Ls;
       std::vector<size_t> bs;
       size_t total, a, b, c, d;
