@@ -456,15 +456,18 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
       wave_sync();
       // 2. row layout: invert X, subtract Sigma', invert K -> Gl, back to LDS
       {
+        // rows past nc start as zero rows and stay zero through both sweeps (the
+        // packed X of nc <= 8 leaves rows 8 .. 15 of the tile unwritten, and LDS
+        // keeps whatever an earlier work-group left there)
+        const bool rin = ri_ < nc;
         double rr[NC], rim[NC];
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          double2 v = sh.buf[g][ri_ * 17 + j];
+          const double2 v = rin ? sh.buf[g][ri_ * 17 + j] : make_double2(0.0, 0.0);
           rr[j] = v.x;
           rim[j] = v.y;
         }
         rsweep<0, NC>(rr, rim, ri_, nc, bad);
-        const bool rin = ri_ < nc;
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
           if (j < nc) {
@@ -477,6 +480,12 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
         rsweep<0, NC>(rr, rim, ri_, nc, bad);
 #pragma unroll
         for (int j = 0; j < NC; ++j) sh.buf[g][ri_ * 17 + j] = make_double2(rr[j], rim[j]);
+        // the packed X of nc <= 8 leaves rows 8 .. 15 unwritten: complete the
+        // tile, so that every element outside Gl's nc x nc corner read later is zero
+        if constexpr (NC <= 8) {
+#pragma unroll
+          for (int j = NC; j < 16; ++j) sh.buf[g][ri_ * 17 + j] = make_double2(0.0, 0.0);
+        }
       }
       wave_sync();
       // 3. per frequency: R, then the running sum / G_loc partial or the traces

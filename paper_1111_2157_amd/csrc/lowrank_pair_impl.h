@@ -192,15 +192,17 @@ __device__ __forceinline__ void lr_pair_tile(const DysonArgs& a, int ktile, int 
       {
         const int g = 4 * w + q, ri = c16;
         const int nfg = n + g;  // frequencies past n1 were clamped copies: no partial
+        // rows past nc start as zero rows and stay zero through both sweeps (the
+        // packed X of nc <= 8 leaves rows 8 .. 15 of the tile unwritten)
+        const bool rin = ri < nc;
         double rr[NC], rim[NC];
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          const double2 v = sh.buf[g][ri * 17 + j];
+          const double2 v = rin ? sh.buf[g][ri * 17 + j] : make_double2(0.0, 0.0);
           rr[j] = v.x;
           rim[j] = v.y;
         }
         rsweep<0, NC>(rr, rim, ri, nc, bad);
-        const bool rin = ri < nc;
         // this lane's row of the G_loc partial of frequency nfg: element
         // (ri, j) sits at (ri / 4) * 64 + 16 (ri % 4) + j in the partial's
         // matrix-core lane order; read now, used after the second inversion
@@ -224,6 +226,12 @@ __device__ __forceinline__ void lr_pair_tile(const DysonArgs& a, int ktile, int 
         rsweep<0, NC>(rr, rim, ri, nc, bad);
 #pragma unroll
         for (int j = 0; j < NC; ++j) sh.buf[g][ri * 17 + j] = make_double2(rr[j], rim[j]);
+        // the packed X of nc <= 8 leaves rows 8 .. 15 unwritten: complete the
+        // tile, so that every element outside Gl's nc x nc corner read later is zero
+        if constexpr (NC <= 8) {
+#pragma unroll
+          for (int j = NC; j < 16; ++j) sh.buf[g][ri * 17 + j] = make_double2(0.0, 0.0);
+        }
         if (gl_row) {
 #pragma unroll
           for (int j = 0; j < NC; ++j)

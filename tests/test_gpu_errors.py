@@ -139,3 +139,33 @@ def test_workspace_missing_misaligned_or_short(ctx):
     assert call(C.c_void_p(base), need) == 0
     torch.cuda.synchronize()
     ctx.sync_status()
+
+
+@pytest.mark.parametrize("nc", [3, 8])
+def test_nonfinite_pass_leaves_no_trace(nc):
+    """A pass whose self-energy holds NaN fills the LDS of every CU it ran on
+    with non-finite values; the next, regular pass of the same shape (nc <= 8:
+    two frequencies per X product, which leaves rows 8 .. 15 of the staged tile
+    unwritten) must report no error and match the oracle."""
+    from gpu_util import assert_gloc_parity, assert_nk_parity, gpu_density
+    from paper_1111_2157_amd._lib import DmftError
+    from paper_1111_2157_amd.dyson import Context, Lattice, SelfEnergy
+
+    wl = synth.f_shell(nk=384, nb=30, nc=nc, nw=64, n_narrow=6)
+    c = Context(0)
+    for nbp in (16, 32):
+        lr = [v for v in c.variants(0, nbp) if v & 8 and v != 42]
+        c.set_variant(0, nbp, lr[0])
+    bad = wl.sigma.sigma.copy()
+    bad[:, 0, 0] = np.nan
+    s_bad = synth.SelfEnergy(wl.sigma.nw, wl.sigma.beta, bad, wl.sigma.sigma_inf, wl.sigma.e_dc)
+    print("non-finite pass then regular pass, nc", nc, flush=True)
+    c.density_matrix(Lattice.from_host(wl.lattice), SelfEnergy.from_host(s_bad), 0.1)
+    with pytest.raises(DmftError) as e:
+        c.sync_status()
+    assert e.value.name == "DMFT_ENONFINITE"
+    mats, gl, sc = gpu_density(c, wl, 0.1)  # raises on a flagged error word
+    ks = list(range(0, wl.lattice.nk, 37))
+    assert_nk_parity(mats, wl.lattice, wl.sigma, 0.1, klist=ks)
+    assert_gloc_parity(gl, wl.lattice, wl.sigma, 0.1, nlist=[0, 1, 31, 63])
+    c.close()
