@@ -386,6 +386,8 @@ namespace dmft {
 struct LRP3QuadShared {
   double2 buf[16][16 * 17];  // per slot: X of its three frequencies, then their Gl, then their R^T
   double2 dtab[48][64];      // d_r of the group's frequencies (zero past nb)
+  double2 sproj[5][64];      // S of the k-point (zero outside nc x nb), staged once per k
+  double2 sgm[48][25];       // Sigma of the group's frequencies (nc x nc, row stride 5)
 };
 
 __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, int wtile, LRP3QuadShared& sh,
@@ -428,6 +430,17 @@ __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, i
     const double el = lane < nb ? a.eps[ob + lane] : 0.0;
     const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
     const double wk = a.wk[k];
+    // the projector into LDS: every fragment of the k is read from there, with
+    // LDS latency (the previous k, or item, ended with a work-group barrier)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int e = tid + 256 * m;
+      if (e < 5 * 64) {
+        const int al = e >> 6, r = e & 63;
+        sh.sproj[al][r] = lr_proj(P, al, r, nc, nb);
+      }
+    }
+    __syncthreads();
     v4d s1[T], s2[T], s3[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) s1[t] = s2[t] = s3[t] = (v4d){0.0, 0.0, 0.0, 0.0};
@@ -444,19 +457,30 @@ __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, i
       }
       const int g = q, ri = c16;  // row layout: this wavefront's slot g, row ri
       const int sl = 4 * w + g;   // slot in the group
-      double2 sgr[3][5];
+      // Sigma of the wavefront's twelve frequencies (12 x 25 positions, five per
+      // lane): loaded now, stored to LDS after the X products hide the latency
+      double2 sgl[5];
 #pragma unroll
-      for (int h = 0; h < 3; ++h) {
-        const double2* sp = reinterpret_cast<const double2*>(a.sigma) +
-                            (int64_t)min(n + 3 * sl + h, n1 - 1) * nc * nc + min(ri, nc - 1) * nc;
-#pragma unroll
-        for (int j = 0; j < 5; ++j) sgr[h][j] = j < nc ? sp[j] : make_double2(0.0, 0.0);
+      for (int m = 0; m < 5; ++m) {
+        const int e = lane + 64 * m;
+        const int f = e / 25, rem = e - 25 * f, ra = rem / 5, cb = rem - 5 * ra;
+        const int nf = min(nw0 + f, n1 - 1);
+        sgl[m] = (ra < nc && cb < nc)
+                     ? reinterpret_cast<const double2*>(a.sigma)[(int64_t)nf * nc * nc + ra * nc + cb]
+                     : make_double2(0.0, 0.0);
       }
       wave_sync();
       // ---- 1. X of this wavefront's four slots
       {
         double2 pt[T][4], ps[T][4];
-        p3_load_x<T>(pt, ps, fresh(P), nc, nb, q, c16);
+#pragma unroll
+        for (int t2 = 0; t2 < T; ++t2)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = 16 * t2 + 4 * i + q;
+            pt[t2][i] = c16 < 5 ? sh.sproj[c16][r] : make_double2(0.0, 0.0);
+            ps[t2][i] = c16 < 15 ? sh.sproj[ac][r] : make_double2(0.0, 0.0);
+          }
 #pragma unroll 1
         for (int c = 0; c < 4; ++c) {
           const int s = 4 * w + c;
@@ -477,6 +501,12 @@ __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, i
 #pragma unroll
           for (int i = 0; i < 4; ++i) sh.buf[s][(q + 4 * i) * 17 + c16] = make_double2(xr[i], xi[i]);
         }
+      }
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const int e = lane + 64 * m;
+        const int f = e / 25, rem = e - 25 * f;
+        sh.sgm[12 * w + f][rem] = sgl[m];
       }
       wave_sync();
       // ---- 2. row layout, three sub-sweeps per slot
@@ -506,7 +536,7 @@ __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, i
 #pragma unroll
           for (int j = 0; j < 5; ++j) {
             if (j < nc) {
-              double2 v = sgr[h][j];
+              double2 v = rin ? sh.sgm[3 * sl + h][ri * 5 + j] : make_double2(0.0, 0.0);
               if (j == ri) v.x -= edc_r;
               rr[j] -= rin ? v.x : 0.0;
               rim[j] -= rin ? v.y : 0.0;
@@ -546,14 +576,14 @@ __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, i
           glr[i] = v.x;
           gli[i] = v.y;
         }
-        const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)min(fb + hc, n1 - 1) * nc * nc;
+        const double2* sg = sh.sgm[3 * s + min(hc, 2)];  // this lane's frequency of the slot
         double sa_r[4], sa_i[4];
         v4d sbr, sbi;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const bool in = cin && hj[j] == hc && aj[j] < nc;
-          double2 v = in ? sg[ac * nc + aj[j]] : make_double2(0.0, 0.0);
-          double2 u = in ? sg[aj[j] * nc + ac] : make_double2(0.0, 0.0);
+          double2 v = in ? sg[ac * 5 + aj[j]] : make_double2(0.0, 0.0);
+          double2 u = in ? sg[aj[j] * 5 + ac] : make_double2(0.0, 0.0);
           if (in && aj[j] == ac) {
             v.x -= edc_c;
             u.x -= edc_c;
@@ -584,10 +614,13 @@ __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, i
       __syncthreads();
       // ---- 3. all sixteen slots: the owned column tile w of sum_n G
       double2 pk[4][T], pw[4];
-      p3_load_k<T>(pk, fresh(P), hj, aj, nc, nb, c16);
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        pw[j] = hj[j] < 3 ? lr_proj(fresh(P), aj[j], 16 * w + c16, nc, nb) : make_double2(0.0, 0.0);
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int t2 = 0; t2 < T; ++t2)
+          pk[j][t2] = hj[j] < 3 ? sh.sproj[aj[j]][16 * t2 + c16] : make_double2(0.0, 0.0);
+        pw[j] = hj[j] < 3 ? sh.sproj[aj[j]][16 * w + c16] : make_double2(0.0, 0.0);
+      }
 #pragma unroll 1
       for (int s = 0; s < 16; ++s) {
         const int fb = n + 3 * s;

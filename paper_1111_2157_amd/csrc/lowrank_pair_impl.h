@@ -20,15 +20,16 @@
 //      (rsweep), Gl_g = (X_g^-1 - Sigma'_g)^-1 back to LDS, and the lane's
 //      row of w_k Gl_g added to the G_loc partial (read during the second
 //      inversion);
-//   -- work-group barrier: the d tables, Sigma and Gl of all eight frequencies
-//      are now in LDS --
-//   3. for each of the eight frequencies, both wavefronts: R = Sigma' +
-//      Sigma' Gl Sigma' (recomputed by each: a few nc x nc products), and for
-//      the owned columns Q_b = (R S D)_b and sum_n G[t][b] += (D S^dag)_t Q_b
-//      for all four row tiles t.
+//   2b. R = Sigma' + Sigma' Gl Sigma' of its four frequencies (a few nc x nc
+//      products), written over Gl in the output layout;
+//   -- work-group barrier: the d tables and R of all eight frequencies are
+//      now in LDS --
+//   3. for each of the eight frequencies, both wavefronts: for the owned
+//      columns Q_b = (R S D)_b and sum_n G[t][b] += (D S^dag)_t Q_b for all
+//      four row tiles t.
 //   -- work-group barrier before the next group overwrites the LDS --
 //
-// so X and the inversions are computed once per frequency, and the running sum
+// so X, the inversions and R are computed once per frequency, and the running sum
 // uses three matrix-core products per complex product.  Results and partial
 // layouts are those of lr_tile (the same epilogues reduce them).
 #pragma once
@@ -238,27 +239,18 @@ __device__ __forceinline__ void lr_pair_tile(const DysonArgs& a, int ktile, int 
             if (j < nc) prow[j] = make_double2(wk * rr[j] + prev[j].x, wk * rim[j] + prev[j].y);
         }
       }
-      __syncthreads();
-      // ---- 3. all eight frequencies: R, the G_loc partial, the owned columns of sum_n G
-      // projector fragments S[q + 4 j][16 t + c16] for every row tile (A operands of
-      // (D S^dag)_t and, for the owned columns, B operands of Q)
-      double par[4][T], pai[4][T];
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-          const double2 v = lr_proj(fresh(P), q + 4 * j, 16 * t + c16, nc, nb);
-          par[j][t] = v.x;
-          pai[j][t] = v.y;
-        }
+      wave_sync();
+      // ---- 2b. R of this wavefront's four frequencies, in the output layout, in
+      //     place of Gl (each lane overwrites only the elements it has read), so
+      //     that stage 3 reads R instead of both wavefronts forming it
 #pragma unroll 1
-      for (int f8 = 0; f8 < 8; ++f8) {
-        const int nf = n + f8;
-        if (nf >= n1) break;
+      for (int f = 0; f < 4; ++f) {
+        const int g = 4 * w + f;
+        if (n + g >= n1) break;
         v4d glr, gli;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const double2 v = sh.buf[f8][(q + 4 * i) * 17 + c16];
+          const double2 v = sh.buf[g][(q + 4 * i) * 17 + c16];
           glr[i] = v.x;
           gli[i] = v.y;
         }
@@ -268,8 +260,8 @@ __device__ __forceinline__ void lr_pair_tile(const DysonArgs& a, int ktile, int 
         for (int j = 0; j < 4; ++j) {
           const int be = q + 4 * j;
           const bool in = c16 < nc && be < nc;
-          double2 v = in ? sh.sg[f8][c16 * 17 + be] : make_double2(0.0, 0.0);
-          double2 u = in ? sh.sg[f8][be * 17 + c16] : make_double2(0.0, 0.0);
+          double2 v = in ? sh.sg[g][c16 * 17 + be] : make_double2(0.0, 0.0);
+          double2 u = in ? sh.sg[g][be * 17 + c16] : make_double2(0.0, 0.0);
           if (in && be == c16) {
             v.x -= edc;
             u.x -= edc;
@@ -300,6 +292,33 @@ __device__ __forceinline__ void lr_pair_tile(const DysonArgs& a, int ktile, int 
 #pragma unroll
         for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
         if (!__builtin_isfinite(chk)) nonfinite = 1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sh.buf[g][(q + 4 * i) * 17 + c16] = make_double2(rtr[i], rti[i]);
+      }
+      __syncthreads();
+      // ---- 3. all eight frequencies: the owned columns of sum_n G
+      // projector fragments S[q + 4 j][16 t + c16] for every row tile (A operands of
+      // (D S^dag)_t and, for the owned columns, B operands of Q)
+      double par[4][T], pai[4][T];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const double2 v = lr_proj(fresh(P), q + 4 * j, 16 * t + c16, nc, nb);
+          par[j][t] = v.x;
+          pai[j][t] = v.y;
+        }
+#pragma unroll 1
+      for (int f8 = 0; f8 < 8; ++f8) {
+        const int nf = n + f8;
+        if (nf >= n1) break;
+        v4d rtr, rti;  // R^T of the frequency (R[c16][q + 4 i])
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double2 v = sh.buf[f8][(q + 4 * i) * 17 + c16];
+          rtr[i] = v.x;
+          rti[i] = v.y;
+        }
         if (!want_s) continue;
         // (register arrays are indexed by compile-time values only: the owned
         // column tiles 2w, 2w + 1 are picked by selects, not by indexing with w)
