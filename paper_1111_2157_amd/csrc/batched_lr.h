@@ -96,7 +96,7 @@ lr_pair_class_kernel(const BatchItem* items, int n_items, const DysonArgs* args,
     if (it >= n_items) break;
     const BatchItem b = items[it];
     const DysonArgs a = args[b.args];
-    lr_pair_tile<NC>(a, b.ktile, b.wtile, sh, tid);
+    lr_pair_tile<NC, (NC >= 12)>(a, b.ktile, b.wtile, sh, tid);
   }
 }
 

@@ -8,7 +8,7 @@ namespace dmft {
 template <int NC>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1))) lr_pair_kernel(DysonArgs a) {
   __shared__ LRPairShared sh;
-  lr_pair_tile<NC>(a, blockIdx.x / a.n_wtiles, blockIdx.x % a.n_wtiles, sh, threadIdx.x);
+  lr_pair_tile<NC, (NC >= 12)>(a, blockIdx.x / a.n_wtiles, blockIdx.x % a.n_wtiles, sh, threadIdx.x);
 }
 
 // Columns of the row-layout inversions: nc rounded up to 8, 12, 14 or 16.

@@ -1,0 +1,62 @@
+"""GPU parity of the partial-fraction running sum of the 64-band low-rank
+kernel (nc > 8) against the FP64 oracle, on band structures built to reach
+each of its branches: distinct bands (the divided form), exactly degenerate and
+nearly degenerate pairs (the directly summed close pair), a triple degeneracy
+(more than one close partner: the k-point takes the direct running sum), and
+pairs just outside the closeness threshold (the smallest divisors the divided
+form meets)."""
+import numpy as np
+import pytest
+
+from paper_1111_2157_amd import synth
+from gpu_util import assert_gloc_parity, assert_nk_parity, gpu_density
+
+pytestmark = pytest.mark.gpu
+
+
+def crafted(nc=14, nb=60, nk=8, nw=40, beta=40.0, seed=5):
+    """f-shell-like lattice whose k-points carry the degeneracy patterns above;
+    delta = pi / (8 beta) is the kernel's closeness threshold."""
+    wl = synth.f_shell(nk=nk, nb=nb, nc=nc, nw=nw, beta=beta, n_narrow=12, seed=seed)
+    lat = wl.lattice
+    eps = lat.eps.copy().reshape(nk, nb)
+    delta = np.pi / (8.0 * beta)
+    eps[0, 3] = eps[0, 7] = eps[0, nb - 20] = eps[0, 20]      # triple degeneracy: direct sum
+    eps[1, 5] = eps[1, 33]                                # exact pair
+    eps[2, 9] = eps[2, nb - 10] + 1e-4                         # near pair
+    eps[3, 2] = eps[3, 17] + 0.5 * delta                  # close pair, half the threshold
+    eps[4, 11] = eps[4, 44] + 2.0 * delta                 # just outside: divided form
+    eps[5, 0] = eps[5, nb - 1] + 1.001 * delta                # at the threshold
+    eps[6, 8] = eps[6, 9]                                 # exact pair in one column tile
+    eps[6, 24] = eps[6, 25] + 1e-9
+    lat2 = synth.Lattice(lat.nk, lat.nc, lat.nb, eps.ravel(), lat.wk, lat.proj)
+    return wl, lat2
+
+
+@pytest.mark.parametrize("nc", [9, 14, 16])
+def test_pf_degeneracy_patterns(nc):
+    from paper_1111_2157_amd.dyson import Context
+
+    wl, lat = crafted(nc=nc)
+    c = Context(0)
+    c.set_variant(0, 64, 40)  # the two-wavefront kernel
+    print("partial fractions, nc", nc, flush=True)
+    mats, gl, sc = gpu_density(c, wl, 0.05, lat=lat)
+    assert_nk_parity(mats, lat, wl.sigma, 0.05)
+    assert_gloc_parity(gl, lat, wl.sigma, 0.05)
+    c.close()
+
+
+@pytest.mark.parametrize("beta,nw", [(10.0, 30), (100.0, 200)])
+def test_pf_temperatures(beta, nw):
+    """The threshold scales with the first Matsubara frequency."""
+    from paper_1111_2157_amd.dyson import Context
+
+    wl, lat = crafted(nc=14, nb=56, nk=7, nw=nw, beta=beta, seed=9)
+    c = Context(0)
+    c.set_variant(0, 64, 40)
+    print("partial fractions, beta", beta, flush=True)
+    mats, gl, sc = gpu_density(c, wl, -0.1, lat=lat)
+    assert_nk_parity(mats, lat, wl.sigma, -0.1)
+    assert_gloc_parity(gl, lat, wl.sigma, -0.1)
+    c.close()
