@@ -23,11 +23,13 @@ struct BatchItem {
   int32_t wtile;  // frequency tile
 };
 
-// Single-wavefront class: NBP in {16, 32, 48}.
-template <int NBP, int RL, bool M3, int NC>
+// Single-wavefront class: NBP in {16, 32, 48}; PF: the partial-fraction form of
+// the running sum (lowrank_impl.h), with its LDS slots for close-pair sums.
+template <int NBP, int RL, bool M3, int NC, bool PF = false>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1)))
 lr_class_kernel(const BatchItem* items, int n_items, const DysonArgs* args, int* counter) {
   __shared__ LRShared sh;
+  __shared__ double2 pfc[PF ? NBP / 16 * 4 * 64 : 1];
   const int lane = threadIdx.x;
   for (;;) {
     int it = 0;
@@ -36,7 +38,7 @@ lr_class_kernel(const BatchItem* items, int n_items, const DysonArgs* args, int*
     if (it >= n_items) break;
     const BatchItem b = items[it];
     const DysonArgs a = args[b.args];
-    lr_tile<NBP, KIND_DENSITY, RL, M3, NC>(a, b.ktile, b.wtile, 0, sh, lane);
+    lr_tile<NBP, KIND_DENSITY, RL, M3, NC, PF>(a, b.ktile, b.wtile, 0, sh, lane, pfc);
   }
 }
 

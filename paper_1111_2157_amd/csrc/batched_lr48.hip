@@ -19,7 +19,7 @@ hipError_t launch_lr_class_48(int ncls, const void* items, int n_items, const Dy
       hipLaunchKernelGGL((lr_class_kernel<48, 1, true, 12>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
       break;
     case 14:
-      hipLaunchKernelGGL((lr_class_kernel<48, 1, true, 14>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
+      hipLaunchKernelGGL((lr_class_kernel<48, 1, true, 14, true>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
       break;
     case 16:
       hipLaunchKernelGGL((lr_class_kernel<48, 1, true, 16>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);

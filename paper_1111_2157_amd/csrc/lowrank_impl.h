@@ -64,6 +64,8 @@
 // and tr(E^2), E = R X2, takes one 16x16 transpose through LDS.
 #pragma once
 
+#include <type_traits>
+
 #include "dyson_impl.h"
 
 namespace dmft {
@@ -269,6 +271,43 @@ __device__ __forceinline__ double2 lower_rows8(double2 s) {
                       s.y + __builtin_amdgcn_update_dpp(0.0, s.y, 0x128, 0xf, 0xf, true));
 }
 
+// Partial-fraction form of the running sum (density kind, nc > 8).  The sum
+// needs F[v][v'] = sum_n d_v d_v' M_n[v][v'], M_n = S^dag R_n S,
+// d_v = 1 / (z_n - E_v).  Since d_v d_v' = (d_v - d_v') / (E_v - E_v') exactly,
+//     F[v][v'] = ((W S)[v][v'] - (S^dag Y)[v][v']) / (E_v - E_v')  (E_v != E_v'),
+//     W = sum_n D_n S^dag R_n  (nb x nc),   Y = sum_n R_n S D_n  (nc x nb),
+// so a frequency adds two rank-nc products instead of the nb x nb update
+// (D S^dag)(R S D), and the nb x nb products are formed once per k-point.  The
+// subtraction loses about |d| / |E_v - E_v'| digits, so the diagonal and pairs
+// closer than delta = pi / (8 beta) (an eighth of the first Matsubara
+// frequency) are summed directly per column: sum_n d_v'^2 (R_n S)[.][v'] and,
+// for at most one close partner v, sum_n d_v d_v' (R_n S)[.][v'], contracted
+// with S^dag at the end of the k-point.  A k-point on which a column has more
+// than one close partner takes the direct running sum.  (Relative errors on
+// the test and benchmark inputs are near 1e-13.)
+//
+// Close partners of the columns v' = 16 c + c16 of this lane; returns whether
+// the form applies (the same answer in every lane of the wavefront).
+template <int T>
+__device__ __forceinline__ bool lr_pf_pairs(const double* eps, int nb, int c16, double beta, int (&partner)[T]) {
+  const double delta = M_PI / (8.0 * beta);
+  int over = 0;
+#pragma unroll
+  for (int c = 0; c < T; ++c) {
+    const int vc = 16 * c + c16;
+    const double ec = vc < nb ? eps[vc] : 0.0;
+    int cnt = 0, pv = -1;
+    for (int v = 0; v < nb; ++v) {
+      const bool close = vc < nb && v != vc && __builtin_fabs(eps[v] - ec) < delta;
+      pv = close ? v : pv;
+      cnt += close ? 1 : 0;
+    }
+    partner[c] = pv;
+    over |= cnt > 1;
+  }
+  return !__any(over);
+}
+
 // X_f = S D_f S^dag of the four frequencies of a group when nc <= 8: two
 // frequencies per matrix-core product, stacked in the A rows (row 8 h + alpha
 // holds S[alpha][r] d_{2c + h}[r]); the B columns are S[beta][r]^* as before.
@@ -302,8 +341,14 @@ __device__ __forceinline__ void lr_x_packed(const Proj<NBP>& pr, const double2* 
   }
 }
 
-template <int NBP, int KIND, int RL, bool M3, int NC, int PART>
-__device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int wtile, LRShared& sh, int lane) {
+// PF: the running sum in the partial-fraction form on every k-point where it
+// applies (density kind with every column tile in the item); pfc then points
+// to the work-group's LDS slots for the close-pair sums (NBP / 16 x 4 x 64).
+template <int NBP, int KIND, int RL, bool M3, int NC, int PART, bool PF = false>
+__device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int wtile, LRShared& sh, int lane,
+                                             double2* pfc = nullptr) {
+  static_assert(!PF || (KIND == KIND_DENSITY && (NBP / 16) == lr_col_tiles<NBP, KIND>()),
+                "the partial-fraction form needs the density kind and every column tile");
   constexpr int T = NBP / 16;
   constexpr int CT = lr_col_tiles<NBP, KIND>();
   constexpr int b0 = PART * CT;
@@ -374,590 +419,748 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
         ntd[t] = (ntb && v < nb) ? 2.0 * ntb[(int64_t)v * nb + v].x : 0.0;
       }
     }
-    // projector fragments: RL = 0 kept in registers for the whole k; RL = 1
-    // loaded per group of four frequencies at the start of the stage that
-    // uses them, so that they do not occupy registers in the other stages;
-    // RL = 2 re-read at every use (fewest live registers)
-    Proj<NBP> pr;
-    if constexpr (RL == 0) {
-      lr_load_pa<NBP>(pr, P, nc, nb, q, c16);
-      lr_load_pt<NBP>(pr, P, nc, nb, q, c16);
-    }
-    // running sum of G, column tiles b0 .. b0 + CT; the three-product form
-    // needs three accumulators per tile, so it is used here only up to four tiles
-    CAcc<M3 && T * CT <= 4> sacc[T][CT];
-    // sum over frequencies of d at band 16 t + c16: the D term of sum_n G,
-    // added to the diagonal once per k so that the running sum above is
-    // touched only by the matrix cores inside the frequency loop
-    double2 dsum[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) dsum[t] = make_double2(0.0, 0.0);
-    if (want_s) {
-#pragma unroll
-      for (int t = 0; t < T; ++t)
-#pragma unroll
-        for (int c = 0; c < CT; ++c) sacc[t][c].zero();
-    }
-    double trg = 0.0, trg2 = 0.0, mub = 0.0;
-
-    for (int n = n0; n < n1; n += 4) {
-      // 0. d_r of the four frequencies, each computed once and read from LDS by
-      //    every lane that needs it (a lane would otherwise redo the complex
-      //    reciprocal for each band it touches, the same value 4 to 16 times
-      //    across the wavefront)
-#pragma unroll
-      for (int it = 0; it < NDT; ++it) {
-        const int idx = lane + 64 * it;  // < 4 NBP: NBP is a multiple of 16
-        const int f = idx / NBP, r = idx - f * NBP;
-        const int nf = min(n + f, n1 - 1);
-        const double wn = (double)(2 * nf + 1) * M_PI / beta;
-        sh.dtab[f][r] = r < nb ? inv_z_minus(mu, wn, EPL ? epl[it] : eps[r]) : make_double2(0.0, 0.0);
+    // close partners of the columns, for the partial-fraction form
+    int partner[PF ? T : 1];
+    bool pfk = false;
+    if constexpr (PF) pfk = want_s && lr_pf_pairs<T>(eps, nb, c16, beta, partner);
+    // one k-point, with the running sum in the direct (PFK false) or the
+    // partial-fraction form; the two instantiations keep separate registers
+    auto k_body = [&](auto pf_tag) {
+      constexpr bool PFK = decltype(pf_tag)::value;
+      // projector fragments: RL = 0 kept in registers for the whole k; RL = 1
+      // loaded per group of four frequencies at the start of the stage that
+      // uses them, so that they do not occupy registers in the other stages;
+      // RL = 2 re-read at every use (fewest live registers)
+      Proj<NBP> pr;
+      if constexpr (RL == 0) {
+        lr_load_pa<NBP>(pr, P, nc, nb, q, c16);
+        lr_load_pt<NBP>(pr, P, nc, nb, q, c16);
       }
-      // row ri_ of Sigma(i w) of frequency n + g, for the subtraction in stage
-      // 2 (rows past nc read row nc - 1, in bounds, and discard it there).
-      // Up to 14 columns it is loaded here, so that the loads are in flight
-      // during stage 1; 16 columns would not fit in the registers of the
-      // two-wavefront variants, which load it in stage 2.
-      constexpr bool SG_EARLY = NC <= 14;
-      const double2* sgp =
-          reinterpret_cast<const double2*>(a.sigma) + (int64_t)min(n + g, n1 - 1) * nc * nc + min(ri_, nc - 1) * nc;
-      double2 sgrow[NC];
-      if constexpr (SG_EARLY) {
+      // running sum of G, column tiles b0 .. b0 + CT; the three-product form
+      // needs three accumulators per tile, so it is used here only up to four tiles
+      CAcc<M3 && T * CT <= 4> sacc[T][CT];
+      // partial-fraction form (see lr_pf_pairs): W of every row tile (three
+      // products up to two tiles), and per column tile Y, the diagonal and the
+      // close-pair sums in the output layout of R S (register i: orbital q + 4 i)
+      CAcc<M3 && T <= 2> pw[PFK ? T : 1];
+      v4d yr[PFK ? T : 1], yi[PFK ? T : 1], gr[PFK ? T : 1], gi[PFK ? T : 1];
+      // close-pair sums in LDS (lane-private slots), kept only for column tiles
+      // where some lane has a close partner
+      bool anyc[PFK ? T : 1];
+      if constexpr (PFK) {
 #pragma unroll
-        for (int j = 0; j < NC; ++j) sgrow[j] = j < nc ? sgp[j] : make_double2(0.0, 0.0);
-      }
-      wave_sync();
-      // 1. X of the four frequencies n .. n+3 (repeating the last one past n1)
-      //    into LDS, in the output layout of the matrix core
-      if constexpr (RL == 1) lr_load_pt<NBP>(pr, fresh(P), nc, nb, q, c16);
-      if constexpr (NC <= 8) {
-        lr_x_packed<NBP, RL, M3>(pr, P, nc, nb, sh, q, c16);
-      } else {
+        for (int t = 0; t < T; ++t) {
+          pw[t].zero();
+          yr[t] = yi[t] = gr[t] = gi[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+          anyc[t] = __any(partner[t] >= 0);
+          if (anyc[t]) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-          CAcc<M3> x;
-          x.zero();
-#pragma unroll
-          for (int t = 0; t < T; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              if (16 * t + 4 * i >= nb) break;
-              const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
-                                        : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
-              const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
-              double2 a1 = cmul(s, dd);
-              x.mac_cb(a1.x, a1.y, s.x, s.y);
-            }
-          const v4d xr = x.re(), xi = x.im();
-#pragma unroll
-          for (int i = 0; i < 4; ++i) sh.buf[f][(q + 4 * i) * 17 + c16] = make_double2(xr[i], xi[i]);
-        }
-      }
-      wave_sync();
-      // 2. row layout: invert X, subtract Sigma', invert K -> Gl, back to LDS
-      {
-        // rows past nc start as zero rows and stay zero through both sweeps (the
-        // packed X of nc <= 8 leaves rows 8 .. 15 of the tile unwritten, and LDS
-        // keeps whatever an earlier work-group left there)
-        const bool rin = ri_ < nc;
-        double rr[NC], rim[NC];
-#pragma unroll
-        for (int j = 0; j < NC; ++j) {
-          const double2 v = rin ? sh.buf[g][ri_ * 17 + j] : make_double2(0.0, 0.0);
-          rr[j] = v.x;
-          rim[j] = v.y;
-        }
-        rsweep<0, NC>(rr, rim, ri_, nc, bad);
-#pragma unroll
-        for (int j = 0; j < NC; ++j) {
-          if (j < nc) {
-            double2 v = SG_EARLY ? sgrow[j] : sgp[j];
-            if (j == ri_) v.x -= edc;
-            rr[j] -= rin ? v.x : 0.0;
-            rim[j] -= rin ? v.y : 0.0;
+            for (int i = 0; i < 4; ++i) pfc[(t * 4 + i) * 64 + lane] = make_double2(0.0, 0.0);
           }
         }
-        rsweep<0, NC>(rr, rim, ri_, nc, bad);
-#pragma unroll
-        for (int j = 0; j < NC; ++j) sh.buf[g][ri_ * 17 + j] = make_double2(rr[j], rim[j]);
-        // the packed X of nc <= 8 leaves rows 8 .. 15 unwritten: complete the
-        // tile, so that every element outside Gl's nc x nc corner read later is zero
+      }
+      // sum over frequencies of d at band 16 t + c16: the D term of sum_n G,
+      // added to the diagonal once per k so that the running sum above is
+      // touched only by the matrix cores inside the frequency loop
+      double2 dsum[T];
+  #pragma unroll
+      for (int t = 0; t < T; ++t) dsum[t] = make_double2(0.0, 0.0);
+      if (want_s) {
+  #pragma unroll
+        for (int t = 0; t < T; ++t)
+  #pragma unroll
+          for (int c = 0; c < CT; ++c) sacc[t][c].zero();
+      }
+      double trg = 0.0, trg2 = 0.0, mub = 0.0;
+
+      for (int n = n0; n < n1; n += 4) {
+        // 0. d_r of the four frequencies, each computed once and read from LDS by
+        //    every lane that needs it (a lane would otherwise redo the complex
+        //    reciprocal for each band it touches, the same value 4 to 16 times
+        //    across the wavefront)
+  #pragma unroll
+        for (int it = 0; it < NDT; ++it) {
+          const int idx = lane + 64 * it;  // < 4 NBP: NBP is a multiple of 16
+          const int f = idx / NBP, r = idx - f * NBP;
+          const int nf = min(n + f, n1 - 1);
+          const double wn = (double)(2 * nf + 1) * M_PI / beta;
+          sh.dtab[f][r] = r < nb ? inv_z_minus(mu, wn, EPL ? epl[it] : eps[r]) : make_double2(0.0, 0.0);
+        }
+        // row ri_ of Sigma(i w) of frequency n + g, for the subtraction in stage
+        // 2 (rows past nc read row nc - 1, in bounds, and discard it there).
+        // Up to 14 columns it is loaded here, so that the loads are in flight
+        // during stage 1; 16 columns would not fit in the registers of the
+        // two-wavefront variants, which load it in stage 2.
+        constexpr bool SG_EARLY = NC <= 14;
+        const double2* sgp =
+            reinterpret_cast<const double2*>(a.sigma) + (int64_t)min(n + g, n1 - 1) * nc * nc + min(ri_, nc - 1) * nc;
+        double2 sgrow[NC];
+        if constexpr (SG_EARLY) {
+  #pragma unroll
+          for (int j = 0; j < NC; ++j) sgrow[j] = j < nc ? sgp[j] : make_double2(0.0, 0.0);
+        }
+        wave_sync();
+        // 1. X of the four frequencies n .. n+3 (repeating the last one past n1)
+        //    into LDS, in the output layout of the matrix core
+        if constexpr (RL == 1) lr_load_pt<NBP>(pr, fresh(P), nc, nb, q, c16);
         if constexpr (NC <= 8) {
-#pragma unroll
-          for (int j = NC; j < 16; ++j) sh.buf[g][ri_ * 17 + j] = make_double2(0.0, 0.0);
-        }
-      }
-      wave_sync();
-      // 3. per frequency: R, then the running sum / G_loc partial or the traces
-      if constexpr (RL == 1) {
-        if constexpr (KIND == KIND_DENSITY)
-          lr_load_pa<NBP>(pr, fresh(P), nc, nb, q, c16);
-        else
-          lr_load_pt<NBP>(pr, fresh(P), nc, nb, q, c16);
-      }
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const int nf = n + f;
-        if (nf >= n1) break;
-        const double wn = (double)(2 * nf + 1) * M_PI / beta;
-        // the k-tile partial this frequency adds to (G_loc, or S G^2 S^dag for
-        // the adjoint kind): read here, so that its latency overlaps the
-        // products below (the compiler cannot move it above the previous
-        // frequency's stores)
-        double2* part = reinterpret_cast<double2*>(a.xpart) + ((int64_t)(a.ktile_base + ktile) * a.nw + nf) * 256;
-        const bool part_rmw = kk != kk0 && ((KIND == KIND_DENSITY && want_x) || KIND == KIND_ADJ || KIND == KIND_GEN);
-        double2 prev[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          prev[i] = (part_rmw && q + 4 * i < nc && c16 < nc) ? part[i * 64 + lane] : make_double2(0.0, 0.0);
-        double2 dcol[T];
-#pragma unroll
-        for (int t = 0; t < T; ++t) dcol[t] = sh.dtab[f][16 * t + c16];
-        if (want_s) {
-#pragma unroll
-          for (int t = 0; t < T; ++t) {
-            dsum[t].x += dcol[t].x;
-            dsum[t].y += dcol[t].y;
-          }
-        }
-        v4d glr, gli, gltr, glti;  // Gl and (adjoint kinds) Gl^T in the output layout
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          double2 v = sh.buf[f][(q + 4 * i) * 17 + c16];
-          glr[i] = v.x;
-          gli[i] = v.y;
-          if constexpr (KIND == KIND_ADJ || KIND == KIND_GEN) {
-            double2 u = sh.buf[f][c16 * 17 + q + 4 * i];
-            gltr[i] = u.x;
-            glti[i] = u.y;
-          }
-        }
-        const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)nf * nc * nc;
-        double sa_r[4], sa_i[4];
-        v4d sbr, sbi;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          int be = q + 4 * j;
-          bool in = c16 < nc && be < nc;
-          double2 v = in ? sg[c16 * nc + be] : make_double2(0.0, 0.0);
-          double2 u = in ? sg[be * nc + c16] : make_double2(0.0, 0.0);
-          if (c16 == be && in) {
-            v.x -= edc;
-            u.x -= edc;
-          }
-          sa_r[j] = v.x;
-          sa_i[j] = v.y;
-          sbr[j] = u.x;
-          sbi[j] = u.y;
-        }
-        // V = Gl^T Sigma'^T, R^T = Sigma'^T + Sigma'^T V
-        CAcc<M3> va;
-        va.zero();
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (j >= kc) break;
-          va.mac(glr[j], gli[j], sa_r[j], sa_i[j]);
-        }
-        const v4d vr = va.re(), vi = va.im();
-        CAcc<M3> ra;
-        ra.set((v4d){sa_r[0], sa_r[1], sa_r[2], sa_r[3]}, (v4d){sa_i[0], sa_i[1], sa_i[2], sa_i[3]});
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (j >= kc) break;
-          ra.mac(sbr[j], sbi[j], vr[j], vi[j]);
-        }
-        const v4d rtr = ra.re(), rti = ra.im();
-
-        if constexpr (KIND == KIND_DENSITY) {
-          double chk = 0.0;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
-          if (!__builtin_isfinite(chk)) nonfinite = 1;
-          if (want_s) {
-#pragma unroll
-            for (int c = 0; c < CT; ++c) {
-              const int b = b0 + c;
-              if (16 * b >= nb) break;
-              CAcc<M3> qa;
-              qa.zero();
-#pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                if (j >= kc) break;
-                const double2 s = RL == 2 ? lr_proj(fresh(P), q + 4 * j, 16 * b + c16, nc, nb)
-                                          : make_double2(pr.pa_r[j][b], pr.pa_i[j][b]);
-                qa.mac(rtr[j], rti[j], s.x, s.y);
-              }
-              v4d qr = qa.re(), qi = qa.im();
-              const double2 db = dcol[b];
-#pragma unroll
+          lr_x_packed<NBP, RL, M3>(pr, P, nc, nb, sh, q, c16);
+        } else {
+  #pragma unroll
+          for (int f = 0; f < 4; ++f) {
+            CAcc<M3> x;
+            x.zero();
+  #pragma unroll
+            for (int t = 0; t < T; ++t)
+  #pragma unroll
               for (int i = 0; i < 4; ++i) {
-                double2 v = cmul(make_double2(qr[i], qi[i]), db);
-                qr[i] = v.x;
-                qi[i] = v.y;
+                if (16 * t + 4 * i >= nb) break;
+                const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
+                                          : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
+                const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
+                double2 a1 = cmul(s, dd);
+                x.mac_cb(a1.x, a1.y, s.x, s.y);
               }
-#pragma unroll
+            const v4d xr = x.re(), xi = x.im();
+  #pragma unroll
+            for (int i = 0; i < 4; ++i) sh.buf[f][(q + 4 * i) * 17 + c16] = make_double2(xr[i], xi[i]);
+          }
+        }
+        wave_sync();
+        // 2. row layout: invert X, subtract Sigma', invert K -> Gl, back to LDS
+        {
+          // rows past nc start as zero rows and stay zero through both sweeps (the
+          // packed X of nc <= 8 leaves rows 8 .. 15 of the tile unwritten, and LDS
+          // keeps whatever an earlier work-group left there)
+          const bool rin = ri_ < nc;
+          double rr[NC], rim[NC];
+  #pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            const double2 v = rin ? sh.buf[g][ri_ * 17 + j] : make_double2(0.0, 0.0);
+            rr[j] = v.x;
+            rim[j] = v.y;
+          }
+          rsweep<0, NC>(rr, rim, ri_, nc, bad);
+  #pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            if (j < nc) {
+              double2 v = SG_EARLY ? sgrow[j] : sgp[j];
+              if (j == ri_) v.x -= edc;
+              rr[j] -= rin ? v.x : 0.0;
+              rim[j] -= rin ? v.y : 0.0;
+            }
+          }
+          rsweep<0, NC>(rr, rim, ri_, nc, bad);
+  #pragma unroll
+          for (int j = 0; j < NC; ++j) sh.buf[g][ri_ * 17 + j] = make_double2(rr[j], rim[j]);
+          // the packed X of nc <= 8 leaves rows 8 .. 15 unwritten: complete the
+          // tile, so that every element outside Gl's nc x nc corner read later is zero
+          if constexpr (NC <= 8) {
+  #pragma unroll
+            for (int j = NC; j < 16; ++j) sh.buf[g][ri_ * 17 + j] = make_double2(0.0, 0.0);
+          }
+        }
+        wave_sync();
+        // 3. per frequency: R, then the running sum / G_loc partial or the traces
+        if constexpr (RL == 1) {
+          if constexpr (KIND == KIND_DENSITY)
+            lr_load_pa<NBP>(pr, fresh(P), nc, nb, q, c16);
+          else
+            lr_load_pt<NBP>(pr, fresh(P), nc, nb, q, c16);
+        }
+  #pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const int nf = n + f;
+          if (nf >= n1) break;
+          const double wn = (double)(2 * nf + 1) * M_PI / beta;
+          // the k-tile partial this frequency adds to (G_loc, or S G^2 S^dag for
+          // the adjoint kind): read here, so that its latency overlaps the
+          // products below (the compiler cannot move it above the previous
+          // frequency's stores)
+          double2* part = reinterpret_cast<double2*>(a.xpart) + ((int64_t)(a.ktile_base + ktile) * a.nw + nf) * 256;
+          const bool part_rmw = kk != kk0 && ((KIND == KIND_DENSITY && want_x) || KIND == KIND_ADJ || KIND == KIND_GEN);
+          double2 prev[4];
+  #pragma unroll
+          for (int i = 0; i < 4; ++i)
+            prev[i] = (part_rmw && q + 4 * i < nc && c16 < nc) ? part[i * 64 + lane] : make_double2(0.0, 0.0);
+          double2 dcol[T];
+  #pragma unroll
+          for (int t = 0; t < T; ++t) dcol[t] = sh.dtab[f][16 * t + c16];
+          if (want_s) {
+  #pragma unroll
+            for (int t = 0; t < T; ++t) {
+              dsum[t].x += dcol[t].x;
+              dsum[t].y += dcol[t].y;
+            }
+          }
+          v4d glr, gli, gltr, glti;  // Gl and (adjoint kinds) Gl^T in the output layout
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            double2 v = sh.buf[f][(q + 4 * i) * 17 + c16];
+            glr[i] = v.x;
+            gli[i] = v.y;
+            if constexpr (KIND == KIND_ADJ || KIND == KIND_GEN) {
+              double2 u = sh.buf[f][c16 * 17 + q + 4 * i];
+              gltr[i] = u.x;
+              glti[i] = u.y;
+            }
+          }
+          const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)nf * nc * nc;
+          double sa_r[4], sa_i[4];
+          v4d sbr, sbi;
+  #pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            int be = q + 4 * j;
+            bool in = c16 < nc && be < nc;
+            double2 v = in ? sg[c16 * nc + be] : make_double2(0.0, 0.0);
+            double2 u = in ? sg[be * nc + c16] : make_double2(0.0, 0.0);
+            if (c16 == be && in) {
+              v.x -= edc;
+              u.x -= edc;
+            }
+            sa_r[j] = v.x;
+            sa_i[j] = v.y;
+            sbr[j] = u.x;
+            sbi[j] = u.y;
+          }
+          // V = Gl^T Sigma'^T, R^T = Sigma'^T + Sigma'^T V
+          CAcc<M3> va;
+          va.zero();
+  #pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (j >= kc) break;
+            va.mac(glr[j], gli[j], sa_r[j], sa_i[j]);
+          }
+          const v4d vr = va.re(), vi = va.im();
+          CAcc<M3> ra;
+          ra.set((v4d){sa_r[0], sa_r[1], sa_r[2], sa_r[3]}, (v4d){sa_i[0], sa_i[1], sa_i[2], sa_i[3]});
+  #pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (j >= kc) break;
+            ra.mac(sbr[j], sbi[j], vr[j], vi[j]);
+          }
+          const v4d rtr = ra.re(), rti = ra.im();
+
+          if constexpr (KIND == KIND_DENSITY) {
+            double chk = 0.0;
+  #pragma unroll
+            for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
+            if (!__builtin_isfinite(chk)) nonfinite = 1;
+            if constexpr (PFK) {
+              // R in the output layout (R[q + 4 i][c16]) from R^T through this
+              // frequency's LDS tile, which every lane has read Gl from
+              v4d rnr, rni;
+              wave_sync();
+              tile_transpose(rtr, rti, rnr, rni, sh.buf[f], q, c16);
+  #pragma unroll
+              for (int c = 0; c < T; ++c) {
+                // Q = (R S)_c;  Y += Q d_v',  diagonal += Q d_v'^2,  close += Q d_p d_v'
+                CAcc<M3> qa;
+                qa.zero();
+  #pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  if (j >= kc) break;
+                  const double2 s = RL == 2 ? lr_proj(fresh(P), q + 4 * j, 16 * c + c16, nc, nb)
+                                            : make_double2(pr.pa_r[j][c], pr.pa_i[j][c]);
+                  qa.mac(rtr[j], rti[j], s.x, s.y);
+                }
+                const v4d xr = qa.re(), xi = qa.im();
+                const double2 d = dcol[c], d2 = cmul(d, d);
+                const double2 dp = partner[c] >= 0 ? cmul(d, sh.dtab[f][partner[c]]) : make_double2(0.0, 0.0);
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  const double2 x = make_double2(xr[i], xi[i]);
+                  const double2 y = cmul(x, d), g = cmul(x, d2), pp = cmul(x, dp);
+                  yr[c][i] += y.x;
+                  yi[c][i] += y.y;
+                  gr[c][i] += g.x;
+                  gi[c][i] += g.y;
+                  if (anyc[c]) {
+                    double2* slot = &pfc[(c * 4 + i) * 64 + lane];
+                    const double2 o = *slot;
+                    *slot = make_double2(o.x + pp.x, o.y + pp.y);
+                  }
+                }
+              }
+              // W_t += (D S^dag)_t R
+  #pragma unroll
               for (int t = 0; t < T; ++t) {
-                if (16 * t >= nb) break;
                 const double2 dt = dcol[t];
-#pragma unroll
+  #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                   if (j >= kc) break;
                   const double2 s = RL == 2 ? lr_proj(fresh(P), q + 4 * j, 16 * t + c16, nc, nb)
                                             : make_double2(pr.pa_r[j][t], pr.pa_i[j][t]);
-                  double2 aa = cmul(dt, make_double2(s.x, -s.y));
-                  sacc[t][c].mac(aa.x, aa.y, qr[j], qi[j]);
+                  const double2 aa = cmul(dt, make_double2(s.x, -s.y));
+                  pw[t].mac(aa.x, aa.y, rnr[j], rni[j]);
                 }
               }
-            }
-          }
-          if (want_x) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if (q + 4 * i < nc && c16 < nc)
-                part[i * 64 + lane] = make_double2(wk * glr[i] + prev[i].x, wk * gli[i] + prev[i].y);
-          }
-        } else if constexpr (KIND == KIND_GEN) {
-          double chk = 0.0;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
-          if (!__builtin_isfinite(chk)) nonfinite = 1;
-          auto ptf = [&](int t, int i) -> double2 {
-            return RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
-                           : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
-          };
-          // every lane has read Gl of this frequency: its LDS tile is free for transposes
-          wave_sync();
-          // Rr = I + Sigma' Gl
-          CAcc<M3> rra;
-          {
-            v4d id = {0.0, 0.0, 0.0, 0.0}, z = id;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) id[i] = (hasdiag && idg == i) ? 1.0 : 0.0;
-            rra.set(id, z);
-          }
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            if (j >= kc) break;
-            rra.mac(sa_r[j], sa_i[j], glr[j], gli[j]);
-          }
-          const v4d rrr = rra.re(), rri = rra.im();
-          // X2 = S D^2 S^dag
-          CAcc<M3> x2a;
-          x2a.zero();
-#pragma unroll
-          for (int t = 0; t < T; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              if (16 * t + 4 * i >= nb) break;
-              const double2 s = ptf(t, i);
-              const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
-              const double2 a2 = cmul(cmul(s, dd), dd);
-              x2a.mac_cb(a2.x, a2.y, s.x, s.y);
-            }
-          const v4d x2r = x2a.re(), x2i = x2a.im();
-          // this k's share of Sigmabar_n^dag
-          CAcc<M3> phi;
-          phi.zero();
-          if (ntb) {
-            // Y1 = Nt D S^dag and Y2 = Nt D^2 S^dag, one 16-row tile at a time, each
-            // tile contracted at once into P1 = S D Y1 and P2 = S D Y2 + S D^2 Y1
-            const double2* nt = fresh(ntb);
-            CAcc<M3> p1a, p2a;
-            p1a.zero();
-            p2a.zero();
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-              if (16 * t >= nb) break;
-              const int row = 16 * t + c16;
-              CAcc<M3> y1a, y2a;
-              y1a.zero();
-              y2a.zero();
-#pragma unroll
-              for (int b = 0; b < T; ++b)
-#pragma unroll
+            } else if (want_s) {
+  #pragma unroll
+              for (int c = 0; c < CT; ++c) {
+                const int b = b0 + c;
+                if (16 * b >= nb) break;
+                CAcc<M3> qa;
+                qa.zero();
+  #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                  if (16 * b + 4 * j >= nb) break;
-                  const int col = 16 * b + 4 * j + q;
-                  double2 ntv = make_double2(0.0, 0.0);
-                  if (row < nb && col < nb) {
-                    const double2 u = nt[row * nb + col], v = nt[col * nb + row];
-                    ntv = make_double2(u.x + v.x, u.y - v.y);
-                  }
-                  const double2 s = ptf(b, j);
-                  const double2 dd = sh.dtab[f][col];
-                  const double2 b1 = cmul(dd, make_double2(s.x, -s.y));
-                  const double2 b2 = cmul(dd, b1);
-                  y1a.mac(ntv.x, ntv.y, b1.x, b1.y);
-                  y2a.mac(ntv.x, ntv.y, b2.x, b2.y);
+                  if (j >= kc) break;
+                  const double2 s = RL == 2 ? lr_proj(fresh(P), q + 4 * j, 16 * b + c16, nc, nb)
+                                            : make_double2(pr.pa_r[j][b], pr.pa_i[j][b]);
+                  qa.mac(rtr[j], rti[j], s.x, s.y);
                 }
-              const v4d y1r = y1a.re(), y1i = y1a.im(), y2r = y2a.re(), y2i = y2a.im();
-#pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                if (16 * t + 4 * i >= nb) break;
-                const double2 s = ptf(t, i);
-                const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
-                const double2 a1 = cmul(s, dd), a2 = cmul(a1, dd);
-                p1a.mac(a1.x, a1.y, y1r[i], y1i[i]);
-                p2a.mac(a1.x, a1.y, y2r[i], y2i[i]);
-                p2a.mac(a2.x, a2.y, y1r[i], y1i[i]);
+                v4d qr = qa.re(), qi = qa.im();
+                const double2 db = dcol[b];
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  double2 v = cmul(make_double2(qr[i], qi[i]), db);
+                  qr[i] = v.x;
+                  qi[i] = v.y;
+                }
+  #pragma unroll
+                for (int t = 0; t < T; ++t) {
+                  if (16 * t >= nb) break;
+                  const double2 dt = dcol[t];
+  #pragma unroll
+                  for (int j = 0; j < 4; ++j) {
+                    if (j >= kc) break;
+                    const double2 s = RL == 2 ? lr_proj(fresh(P), q + 4 * j, 16 * t + c16, nc, nb)
+                                              : make_double2(pr.pa_r[j][t], pr.pa_i[j][t]);
+                    double2 aa = cmul(dt, make_double2(s.x, -s.y));
+                    sacc[t][c].mac(aa.x, aa.y, qr[j], qi[j]);
+                  }
+                }
               }
             }
-            const v4d p1r = p1a.re(), p1i = p1a.im(), p2r = p2a.re(), p2i = p2a.im();
-            // Re tr(Nt G^2) = sum_v Nt_vv Re d_v^2 + Re tr(R P2) + Re tr(E F),
-            // E = R X2, F = R P1 (formed transposed: F^T = P1^T R^T)
-            CAcc<M3> ea, fta;
-            ea.zero();
-            fta.zero();
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              ea.mac(rtr[j], rti[j], x2r[j], x2i[j]);
-              fta.mac(p1r[j], p1i[j], rtr[j], rti[j]);
+            if (want_x) {
+  #pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (q + 4 * i < nc && c16 < nc)
+                  part[i * 64 + lane] = make_double2(wk * glr[i] + prev[i].x, wk * gli[i] + prev[i].y);
             }
-            double tn = re_dot4(rtr, rti, p2r, p2i) + re_dot4(ea.re(), ea.im(), fta.re(), fta.im());
-            if (q == 0) {
-#pragma unroll
-              for (int t = 0; t < T; ++t) tn += ntd[t] * (dcol[t].x * dcol[t].x - dcol[t].y * dcol[t].y);
-            }
-            mub -= tn / beta;
-            // Rl (P1 / beta) Rr = Y + Gl (Sigma' Y),  Y = (P1 / beta) Rr
-            const double ib = 1.0 / beta;
-            v4d p1tr, p1ti;
-            tile_transpose(p1r * ib, p1i * ib, p1tr, p1ti, sh.buf[f], q, c16);
-            CAcc<M3> ya;
-            ya.zero();
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              ya.mac(p1tr[j], p1ti[j], rrr[j], rri[j]);
-            }
-            const v4d yr = ya.re(), yi = ya.im();
-            CAcc<M3> za;
-            za.zero();
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              za.mac(sa_r[j], sa_i[j], yr[j], yi[j]);
-            }
-            const v4d zr = za.re(), zi = za.im();
-            phi.set(yr, yi);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              phi.mac(gltr[j], glti[j], zr[j], zi[j]);
-            }
-          }
-          if (a.gbar) {
-            const double2* gb = reinterpret_cast<const double2*>(a.gbar) + (int64_t)nf * nc * nc;
-            // M = S G^2 S^dag = Rl X2 Rr = Y + Gl (Sigma' Y),  Y = X2 Rr; mubar takes -w_k Re<Gbar, M>
-            v4d x2tr, x2ti;
-            tile_transpose(x2r, x2i, x2tr, x2ti, sh.buf[f], q, c16);
-            CAcc<M3> ya;
-            ya.zero();
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              ya.mac(x2tr[j], x2ti[j], rrr[j], rri[j]);
-            }
-            const v4d yr = ya.re(), yi = ya.im();
-            CAcc<M3> za;
-            za.zero();
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              za.mac(sa_r[j], sa_i[j], yr[j], yi[j]);
-            }
-            const v4d zr = za.re(), zi = za.im();
-            CAcc<M3> ma;
-            ma.set(yr, yi);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              ma.mac(gltr[j], glti[j], zr[j], zi[j]);
-            }
-            const v4d mr = ma.re(), mi = ma.im();
-            double gm = 0.0;
-            double hb_r[4], hb_i[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int al = q + 4 * i;
-              const bool in = al < nc && c16 < nc;
-              const double2 v = in ? gb[al * nc + c16] : make_double2(0.0, 0.0);
-              gm += v.x * mr[i] + v.y * mi[i];
-              // w_k conj(Gbar)[c16][q + 4 i]: registers of (w_k conj(Gbar))^T
-              const double2 u = in ? gb[c16 * nc + al] : make_double2(0.0, 0.0);
-              hb_r[i] = wk * u.x;
-              hb_i[i] = -wk * u.y;
-            }
-            mub -= wk * gm;
-            // + w_k Gl Gbar^dag Gl = H Gl,  H^T = w_k conj(Gbar) Gl^T
-            CAcc<M3> ha;
-            ha.zero();
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              ha.mac(hb_r[j], hb_i[j], gltr[j], glti[j]);
-            }
-            const v4d htr = ha.re(), hti = ha.im();
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              phi.mac(htr[j], hti[j], glr[j], gli[j]);
-            }
-          }
-          // stored as Sigmabar_n = (share)^dag, the dense adjoint's partial layout
-          v4d ftr, fti;
-          tile_transpose(phi.re(), phi.im(), ftr, fti, sh.buf[f], q, c16);
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (q + 4 * i < nc && c16 < nc) part[i * 64 + lane] = make_double2(ftr[i] + prev[i].x, prev[i].y - fti[i]);
-        } else {
-          // X2 = S D^2 S^dag, X3 = S D^3 S^dag of this frequency
-          CAcc<M3> x2a, x3a;
-          x2a.zero();
-          x3a.zero();
-#pragma unroll
-          for (int t = 0; t < T; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              if (16 * t + 4 * i >= nb) break;
-              const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
-                                      : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
-              const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
-              double2 a2 = cmul(cmul(s, dd), dd);
-              x2a.mac_cb(a2.x, a2.y, s.x, s.y);
-              double2 a3 = cmul(a2, dd);
-              x3a.mac_cb(a3.x, a3.y, s.x, s.y);
-            }
-          const v4d x2r = x2a.re(), x2i = x2a.im(), x3r = x3a.re(), x3i = x3a.im();
-          CAcc<M3> ea_;
-          ea_.zero();
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            if (j >= kc) break;
-            ea_.mac(rtr[j], rti[j], x2r[j], x2i[j]);
-          }
-          const v4d er = ea_.re(), ei = ea_.im();
-          v4d etr, eti;
-          wave_sync();
-          tile_transpose(er, ei, etr, eti, sh.buf[f], q, c16);
-          double t2 = re_dot4(rtr, rti, x2r, x2i);
-          double t3 = re_dot4(rtr, rti, x3r, x3i);
-          double ee = re_dot4(er, ei, etr, eti);
-          double sd = 0.0, sd2 = 0.0;
-          if (q == 0) {
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-              sd += dcol[t].x;
-              sd2 += dcol[t].x * dcol[t].x - dcol[t].y * dcol[t].y;
-            }
-          }
-          trg += sd + t2;
-          trg2 += sd2 + 2.0 * t3 + ee;
-          if constexpr (KIND == KIND_ADJ) {
-            // M = S G^2 S^dag = (I + Gl Sigma') X2 (I + Sigma' Gl), as
-            // Rr = I + Sigma' Gl, Y = X2 Rr, M = Y + Gl (Sigma' Y)
+          } else if constexpr (KIND == KIND_GEN) {
+            double chk = 0.0;
+  #pragma unroll
+            for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
+            if (!__builtin_isfinite(chk)) nonfinite = 1;
+            auto ptf = [&](int t, int i) -> double2 {
+              return RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
+                             : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
+            };
+            // every lane has read Gl of this frequency: its LDS tile is free for transposes
+            wave_sync();
+            // Rr = I + Sigma' Gl
             CAcc<M3> rra;
             {
               v4d id = {0.0, 0.0, 0.0, 0.0}, z = id;
-#pragma unroll
+  #pragma unroll
               for (int i = 0; i < 4; ++i) id[i] = (hasdiag && idg == i) ? 1.0 : 0.0;
               rra.set(id, z);
             }
-#pragma unroll
+  #pragma unroll
             for (int j = 0; j < 4; ++j) {
               if (j >= kc) break;
               rra.mac(sa_r[j], sa_i[j], glr[j], gli[j]);
             }
             const v4d rrr = rra.re(), rri = rra.im();
-            v4d x2tr, x2ti;
-            tile_transpose(x2r, x2i, x2tr, x2ti, sh.buf[f], q, c16);
-            CAcc<M3> ya;
-            ya.zero();
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              ya.mac(x2tr[j], x2ti[j], rrr[j], rri[j]);
+            // X2 = S D^2 S^dag
+            CAcc<M3> x2a;
+            x2a.zero();
+  #pragma unroll
+            for (int t = 0; t < T; ++t)
+  #pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if (16 * t + 4 * i >= nb) break;
+                const double2 s = ptf(t, i);
+                const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
+                const double2 a2 = cmul(cmul(s, dd), dd);
+                x2a.mac_cb(a2.x, a2.y, s.x, s.y);
+              }
+            const v4d x2r = x2a.re(), x2i = x2a.im();
+            // this k's share of Sigmabar_n^dag
+            CAcc<M3> phi;
+            phi.zero();
+            if (ntb) {
+              // Y1 = Nt D S^dag and Y2 = Nt D^2 S^dag, one 16-row tile at a time, each
+              // tile contracted at once into P1 = S D Y1 and P2 = S D Y2 + S D^2 Y1
+              const double2* nt = fresh(ntb);
+              CAcc<M3> p1a, p2a;
+              p1a.zero();
+              p2a.zero();
+  #pragma unroll
+              for (int t = 0; t < T; ++t) {
+                if (16 * t >= nb) break;
+                const int row = 16 * t + c16;
+                CAcc<M3> y1a, y2a;
+                y1a.zero();
+                y2a.zero();
+  #pragma unroll
+                for (int b = 0; b < T; ++b)
+  #pragma unroll
+                  for (int j = 0; j < 4; ++j) {
+                    if (16 * b + 4 * j >= nb) break;
+                    const int col = 16 * b + 4 * j + q;
+                    double2 ntv = make_double2(0.0, 0.0);
+                    if (row < nb && col < nb) {
+                      const double2 u = nt[row * nb + col], v = nt[col * nb + row];
+                      ntv = make_double2(u.x + v.x, u.y - v.y);
+                    }
+                    const double2 s = ptf(b, j);
+                    const double2 dd = sh.dtab[f][col];
+                    const double2 b1 = cmul(dd, make_double2(s.x, -s.y));
+                    const double2 b2 = cmul(dd, b1);
+                    y1a.mac(ntv.x, ntv.y, b1.x, b1.y);
+                    y2a.mac(ntv.x, ntv.y, b2.x, b2.y);
+                  }
+                const v4d y1r = y1a.re(), y1i = y1a.im(), y2r = y2a.re(), y2i = y2a.im();
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  if (16 * t + 4 * i >= nb) break;
+                  const double2 s = ptf(t, i);
+                  const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
+                  const double2 a1 = cmul(s, dd), a2 = cmul(a1, dd);
+                  p1a.mac(a1.x, a1.y, y1r[i], y1i[i]);
+                  p2a.mac(a1.x, a1.y, y2r[i], y2i[i]);
+                  p2a.mac(a2.x, a2.y, y1r[i], y1i[i]);
+                }
+              }
+              const v4d p1r = p1a.re(), p1i = p1a.im(), p2r = p2a.re(), p2i = p2a.im();
+              // Re tr(Nt G^2) = sum_v Nt_vv Re d_v^2 + Re tr(R P2) + Re tr(E F),
+              // E = R X2, F = R P1 (formed transposed: F^T = P1^T R^T)
+              CAcc<M3> ea, fta;
+              ea.zero();
+              fta.zero();
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                ea.mac(rtr[j], rti[j], x2r[j], x2i[j]);
+                fta.mac(p1r[j], p1i[j], rtr[j], rti[j]);
+              }
+              double tn = re_dot4(rtr, rti, p2r, p2i) + re_dot4(ea.re(), ea.im(), fta.re(), fta.im());
+              if (q == 0) {
+  #pragma unroll
+                for (int t = 0; t < T; ++t) tn += ntd[t] * (dcol[t].x * dcol[t].x - dcol[t].y * dcol[t].y);
+              }
+              mub -= tn / beta;
+              // Rl (P1 / beta) Rr = Y + Gl (Sigma' Y),  Y = (P1 / beta) Rr
+              const double ib = 1.0 / beta;
+              v4d p1tr, p1ti;
+              tile_transpose(p1r * ib, p1i * ib, p1tr, p1ti, sh.buf[f], q, c16);
+              CAcc<M3> ya;
+              ya.zero();
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                ya.mac(p1tr[j], p1ti[j], rrr[j], rri[j]);
+              }
+              const v4d yr = ya.re(), yi = ya.im();
+              CAcc<M3> za;
+              za.zero();
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                za.mac(sa_r[j], sa_i[j], yr[j], yi[j]);
+              }
+              const v4d zr = za.re(), zi = za.im();
+              phi.set(yr, yi);
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                phi.mac(gltr[j], glti[j], zr[j], zi[j]);
+              }
             }
-            const v4d yr = ya.re(), yi = ya.im();
-            CAcc<M3> za;
-            za.zero();
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              za.mac(sa_r[j], sa_i[j], yr[j], yi[j]);
+            if (a.gbar) {
+              const double2* gb = reinterpret_cast<const double2*>(a.gbar) + (int64_t)nf * nc * nc;
+              // M = S G^2 S^dag = Rl X2 Rr = Y + Gl (Sigma' Y),  Y = X2 Rr; mubar takes -w_k Re<Gbar, M>
+              v4d x2tr, x2ti;
+              tile_transpose(x2r, x2i, x2tr, x2ti, sh.buf[f], q, c16);
+              CAcc<M3> ya;
+              ya.zero();
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                ya.mac(x2tr[j], x2ti[j], rrr[j], rri[j]);
+              }
+              const v4d yr = ya.re(), yi = ya.im();
+              CAcc<M3> za;
+              za.zero();
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                za.mac(sa_r[j], sa_i[j], yr[j], yi[j]);
+              }
+              const v4d zr = za.re(), zi = za.im();
+              CAcc<M3> ma;
+              ma.set(yr, yi);
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                ma.mac(gltr[j], glti[j], zr[j], zi[j]);
+              }
+              const v4d mr = ma.re(), mi = ma.im();
+              double gm = 0.0;
+              double hb_r[4], hb_i[4];
+  #pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int al = q + 4 * i;
+                const bool in = al < nc && c16 < nc;
+                const double2 v = in ? gb[al * nc + c16] : make_double2(0.0, 0.0);
+                gm += v.x * mr[i] + v.y * mi[i];
+                // w_k conj(Gbar)[c16][q + 4 i]: registers of (w_k conj(Gbar))^T
+                const double2 u = in ? gb[c16 * nc + al] : make_double2(0.0, 0.0);
+                hb_r[i] = wk * u.x;
+                hb_i[i] = -wk * u.y;
+              }
+              mub -= wk * gm;
+              // + w_k Gl Gbar^dag Gl = H Gl,  H^T = w_k conj(Gbar) Gl^T
+              CAcc<M3> ha;
+              ha.zero();
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                ha.mac(hb_r[j], hb_i[j], gltr[j], glti[j]);
+              }
+              const v4d htr = ha.re(), hti = ha.im();
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                phi.mac(htr[j], hti[j], glr[j], gli[j]);
+              }
             }
-            const v4d zr = za.re(), zi = za.im();
-            CAcc<M3> ma;
-            ma.set(yr, yi);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j >= kc) break;
-              ma.mac(gltr[j], glti[j], zr[j], zi[j]);
-            }
-            const v4d mr = ma.re(), mi = ma.im();
-#pragma unroll
+            // stored as Sigmabar_n = (share)^dag, the dense adjoint's partial layout
+            v4d ftr, fti;
+            tile_transpose(phi.re(), phi.im(), ftr, fti, sh.buf[f], q, c16);
+  #pragma unroll
             for (int i = 0; i < 4; ++i)
-              if (q + 4 * i < nc && c16 < nc)
-                part[i * 64 + lane] = make_double2(wk * mr[i] + prev[i].x, wk * mi[i] + prev[i].y);
+              if (q + 4 * i < nc && c16 < nc) part[i * 64 + lane] = make_double2(ftr[i] + prev[i].x, prev[i].y - fti[i]);
+          } else {
+            // X2 = S D^2 S^dag, X3 = S D^3 S^dag of this frequency
+            CAcc<M3> x2a, x3a;
+            x2a.zero();
+            x3a.zero();
+  #pragma unroll
+            for (int t = 0; t < T; ++t)
+  #pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if (16 * t + 4 * i >= nb) break;
+                const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
+                                        : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
+                const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
+                double2 a2 = cmul(cmul(s, dd), dd);
+                x2a.mac_cb(a2.x, a2.y, s.x, s.y);
+                double2 a3 = cmul(a2, dd);
+                x3a.mac_cb(a3.x, a3.y, s.x, s.y);
+              }
+            const v4d x2r = x2a.re(), x2i = x2a.im(), x3r = x3a.re(), x3i = x3a.im();
+            CAcc<M3> ea_;
+            ea_.zero();
+  #pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              ea_.mac(rtr[j], rti[j], x2r[j], x2i[j]);
+            }
+            const v4d er = ea_.re(), ei = ea_.im();
+            v4d etr, eti;
+            wave_sync();
+            tile_transpose(er, ei, etr, eti, sh.buf[f], q, c16);
+            double t2 = re_dot4(rtr, rti, x2r, x2i);
+            double t3 = re_dot4(rtr, rti, x3r, x3i);
+            double ee = re_dot4(er, ei, etr, eti);
+            double sd = 0.0, sd2 = 0.0;
+            if (q == 0) {
+  #pragma unroll
+              for (int t = 0; t < T; ++t) {
+                sd += dcol[t].x;
+                sd2 += dcol[t].x * dcol[t].x - dcol[t].y * dcol[t].y;
+              }
+            }
+            trg += sd + t2;
+            trg2 += sd2 + 2.0 * t3 + ee;
+            if constexpr (KIND == KIND_ADJ) {
+              // M = S G^2 S^dag = (I + Gl Sigma') X2 (I + Sigma' Gl), as
+              // Rr = I + Sigma' Gl, Y = X2 Rr, M = Y + Gl (Sigma' Y)
+              CAcc<M3> rra;
+              {
+                v4d id = {0.0, 0.0, 0.0, 0.0}, z = id;
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) id[i] = (hasdiag && idg == i) ? 1.0 : 0.0;
+                rra.set(id, z);
+              }
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                rra.mac(sa_r[j], sa_i[j], glr[j], gli[j]);
+              }
+              const v4d rrr = rra.re(), rri = rra.im();
+              v4d x2tr, x2ti;
+              tile_transpose(x2r, x2i, x2tr, x2ti, sh.buf[f], q, c16);
+              CAcc<M3> ya;
+              ya.zero();
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                ya.mac(x2tr[j], x2ti[j], rrr[j], rri[j]);
+              }
+              const v4d yr = ya.re(), yi = ya.im();
+              CAcc<M3> za;
+              za.zero();
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                za.mac(sa_r[j], sa_i[j], yr[j], yi[j]);
+              }
+              const v4d zr = za.re(), zi = za.im();
+              CAcc<M3> ma;
+              ma.set(yr, yi);
+  #pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if (j >= kc) break;
+                ma.mac(gltr[j], glti[j], zr[j], zi[j]);
+              }
+              const v4d mr = ma.re(), mi = ma.im();
+  #pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (q + 4 * i < nc && c16 < nc)
+                  part[i * 64 + lane] = make_double2(wk * mr[i] + prev[i].x, wk * mi[i] + prev[i].y);
+            }
           }
         }
-      }
-      wave_sync();
-    }  // frequency groups
+        wave_sync();
+      }  // frequency groups
 
-    if (want_s) {
-      double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
-#pragma unroll
-      for (int t = 0; t < T; ++t)
-#pragma unroll
-        for (int c = 0; c < CT; ++c)
-#pragma unroll
+      if constexpr (PFK) {
+        double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
+        // W through LDS (row v, column beta at v * 17 + beta; the tiles are free
+        // after the last group), read back as the A operand of W S
+        double2* wl = &sh.buf[0][0];
+  #pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const v4d re = pw[t].re(), im = pw[t].im();
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) wl[(16 * t + q + 4 * i) * 17 + c16] = make_double2(re[i], im[i]);
+        }
+        wave_sync();
+        double2 srow[4][T];  // S[q + 4 j][16 t + c16]
+  #pragma unroll
+        for (int j = 0; j < 4; ++j)
+  #pragma unroll
+          for (int t = 0; t < T; ++t) srow[j][t] = lr_proj(P, q + 4 * j, 16 * t + c16, nc, nb);
+  #pragma unroll
+        for (int c = 0; c < T; ++c) {
+          const int vc = 16 * c + c16;
+          const double ec = vc < nb ? eps[vc] : 0.0;
+          // the diagonal and the close pair: over the orbitals q + 4 i (this lane's
+          // registers, then the four lanes of the column)
+          double2 dg = make_double2(0.0, 0.0), cl = make_double2(0.0, 0.0);
+          const int pv = partner[c];
+  #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            int e = (t * T + b0 + c) * 4 + i;
-            double2 v = make_double2(sacc[t][c].re()[i], sacc[t][c].im()[i]);
-            if (t == b0 + c && hasdiag && idg == i) {
-              v.x += dsum[t].x;
-              v.y += dsum[t].y;
-            }
-            sp[e * 64 + lane] = v;
+            const double2 sc = make_double2(srow[i][c].x, -srow[i][c].y);
+            const double2 gd = cmul(sc, make_double2(gr[c][i], gi[c][i]));
+            dg.x += gd.x;
+            dg.y += gd.y;
+            const double2 spv = pv >= 0 ? lr_proj(P, q + 4 * i, pv, nc, nb) : make_double2(0.0, 0.0);
+            const double2 cv = anyc[c] ? pfc[(c * 4 + i) * 64 + lane] : make_double2(0.0, 0.0);
+            const double2 cd = cmul(make_double2(spv.x, -spv.y), cv);
+            cl.x += cd.x;
+            cl.y += cd.y;
           }
-    }
-    if constexpr (KIND == KIND_GEN) {
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) mub += __shfl_xor(mub, off);
-      if (!__builtin_isfinite(mub)) nonfinite = 1;
-      if (lane == 0) {
-        // [unused, unused, mubar share] in the adjoint layout
-        double* tp = a.tpart + ((int64_t)wtile * a.nk + k) * 3;
-        tp[0] = 0.0;
-        tp[1] = 0.0;
-        tp[2] = mub;
+  #pragma unroll
+          for (int off = 16; off <= 32; off <<= 1) {
+            dg.x += __shfl_xor(dg.x, off);
+            dg.y += __shfl_xor(dg.y, off);
+            cl.x += __shfl_xor(cl.x, off);
+            cl.y += __shfl_xor(cl.y, off);
+          }
+  #pragma unroll
+          for (int t = 0; t < T; ++t) {
+            // W S - S^dag Y for tile (t, c)
+            CAcc<M3 && T <= 2> acc;
+            acc.zero();
+  #pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j >= kc) break;
+              const double2 wv = wl[(16 * t + c16) * 17 + q + 4 * j];
+              acc.mac(wv.x, wv.y, srow[j][c].x, srow[j][c].y);
+              acc.mac(-srow[j][t].x, srow[j][t].y, yr[c][j], yi[c][j]);
+            }
+            const v4d fr = acc.re(), fi = acc.im();
+  #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int v = 16 * t + q + 4 * i;
+              const double ev = v < nb ? eps[v] : 0.0;
+              double2 val;
+              if (t == c && v == vc) {
+                val = make_double2(dg.x + dsum[c].x, dg.y + dsum[c].y);
+              } else if (v == pv) {
+                val = cl;
+              } else {
+                const double inv = (v < nb && vc < nb) ? 1.0 / (ev - ec) : 0.0;
+                val = make_double2(fr[i] * inv, fi[i] * inv);
+              }
+              sp[((t * T + c) * 4 + i) * 64 + lane] = val;
+            }
+          }
+        }
+        wave_sync();  // W's LDS is the next k-point's X tiles
+      } else if (want_s) {
+        double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
+  #pragma unroll
+        for (int t = 0; t < T; ++t)
+  #pragma unroll
+          for (int c = 0; c < CT; ++c)
+  #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              int e = (t * T + b0 + c) * 4 + i;
+              double2 v = make_double2(sacc[t][c].re()[i], sacc[t][c].im()[i]);
+              if (t == b0 + c && hasdiag && idg == i) {
+                v.x += dsum[t].x;
+                v.y += dsum[t].y;
+              }
+              sp[e * 64 + lane] = v;
+            }
       }
-    } else if constexpr (KIND != KIND_DENSITY) {
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        trg += __shfl_xor(trg, off);
-        trg2 += __shfl_xor(trg2, off);
+      if constexpr (KIND == KIND_GEN) {
+  #pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) mub += __shfl_xor(mub, off);
+        if (!__builtin_isfinite(mub)) nonfinite = 1;
+        if (lane == 0) {
+          // [unused, unused, mubar share] in the adjoint layout
+          double* tp = a.tpart + ((int64_t)wtile * a.nk + k) * 3;
+          tp[0] = 0.0;
+          tp[1] = 0.0;
+          tp[2] = mub;
+        }
+      } else if constexpr (KIND != KIND_DENSITY) {
+  #pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          trg += __shfl_xor(trg, off);
+          trg2 += __shfl_xor(trg2, off);
+        }
+        if (!__builtin_isfinite(trg) || !__builtin_isfinite(trg2)) nonfinite = 1;
+        if (lane == 0) {
+          // trace kind: [Re tr G, Re tr G^2]; adjoint kind: the same and a zero mubar share
+          constexpr int stride = KIND == KIND_ADJ ? 3 : 2;
+          double* tp = a.tpart + ((int64_t)wtile * a.nk + k) * stride;
+          tp[0] = trg;
+          tp[1] = trg2;
+          if constexpr (KIND == KIND_ADJ) tp[2] = 0.0;
+        }
       }
-      if (!__builtin_isfinite(trg) || !__builtin_isfinite(trg2)) nonfinite = 1;
-      if (lane == 0) {
-        // trace kind: [Re tr G, Re tr G^2]; adjoint kind: the same and a zero mubar share
-        constexpr int stride = KIND == KIND_ADJ ? 3 : 2;
-        double* tp = a.tpart + ((int64_t)wtile * a.nk + k) * stride;
-        tp[0] = trg;
-        tp[1] = trg2;
-        if constexpr (KIND == KIND_ADJ) tp[2] = 0.0;
-      }
-    }
+    };
+    if (PF && pfk)
+      k_body(std::true_type{});
+    else
+      k_body(std::false_type{});
   }  // k
   if (bad) atomicOr(a.err, ERR_SINGULAR);
   if (nonfinite) atomicOr(a.err, ERR_NONFINITE);
 }
 
 // NC: columns kept in the row-layout inversions, nc rounded up to 4, 8, 12 or 16.
-template <int NBP, int KIND, int RL, bool M3, int NC>
-__device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile, int part, LRShared& sh, int lane) {
+template <int NBP, int KIND, int RL, bool M3, int NC, bool PF = false>
+__device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile, int part, LRShared& sh, int lane,
+                                        double2* pfc = nullptr) {
   constexpr int NP = (NBP / 16) / lr_col_tiles<NBP, KIND>();
   if constexpr (NP > 1) {
     if (part) {
@@ -965,7 +1168,7 @@ __device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile
       return;
     }
   }
-  lr_tile_part<NBP, KIND, RL, M3, NC, 0>(a, ktile, wtile, sh, lane);
+  lr_tile_part<NBP, KIND, RL, M3, NC, 0, PF>(a, ktile, wtile, sh, lane, pfc);
 }
 
 // Grid: (k tiles x frequency tiles) x column parts, the column part fastest.
