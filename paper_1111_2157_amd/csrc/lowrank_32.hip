@@ -3,7 +3,7 @@
 #include "lowrank_impl.h"
 
 namespace dmft {
-using LD32 = LRSet<32, KIND_DENSITY, 10, 8, 24, 26, 9, 11>;
+using LD32 = LRSet<32, KIND_DENSITY, 10, 8, 24, 26, 9, 11, 74>;
 using LA32 = LRSet<32, KIND_ADJ, 10, 8, 26>;
 using LG32 = LRSet<32, KIND_GEN, 8, 9, 24>;
 using LT32 = LRSet<32, KIND_TRACE, 14, 12, 28, 30, 13, 15>;

@@ -3,7 +3,7 @@
 #include "lowrank_impl.h"
 
 namespace dmft {
-using LD48 = LRSet<48, KIND_DENSITY, 8, 24, 26, 9, 11>;
+using LD48 = LRSet<48, KIND_DENSITY, 8, 24, 26, 9, 11, 90>;
 using LA48 = LRSet<48, KIND_ADJ, 10, 8, 26>;
 using LG48 = LRSet<48, KIND_GEN, 8, 9, 24>;
 using LT48 = LRSet<48, KIND_TRACE, 15, 13, 8, 10, 24, 26>;

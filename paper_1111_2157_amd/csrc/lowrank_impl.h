@@ -1172,20 +1172,23 @@ __device__ __forceinline__ void lr_tile(const DysonArgs& a, int ktile, int wtile
 }
 
 // Grid: (k tiles x frequency tiles) x column parts, the column part fastest.
-template <int NBP, int KIND, int RL, bool M3, int NC, int OCC>
+template <int NBP, int KIND, int RL, bool M3, int NC, int OCC, bool PF = false>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) lr_kernel(DysonArgs a) {
   __shared__ LRShared sh;
+  __shared__ double2 pfc[PF ? NBP / 16 * 4 * 64 : 1];
   constexpr int NP = (NBP / 16) / lr_col_tiles<NBP, KIND>();
   const int item = blockIdx.x / NP, part = blockIdx.x % NP;
-  lr_tile<NBP, KIND, RL, M3, NC>(a, item / a.n_wtiles, item % a.n_wtiles, part, sh, threadIdx.x);
+  lr_tile<NBP, KIND, RL, M3, NC, PF>(a, item / a.n_wtiles, item % a.n_wtiles, part, sh, threadIdx.x, pfc);
 }
 
 // Variant id of the low-rank kernel: bit 3 set; projector fragments kept in
 // registers for the whole k-point (bits 0 and 4 clear), re-read at every use
 // (bit 0) or loaded once per four-frequency group at the start of each stage
 // (bit 4); bit 1 = three-product complex arithmetic on the matrix cores;
-// bit 2 = two wavefronts per SIMD.  An LRSet lists the variants one
-// instantiation unit compiles for one size and kind.
+// bit 2 = two wavefronts per SIMD; bit 6 = the running sum in the
+// partial-fraction form (density kind, nc > 8; the other column counts run
+// the direct form).  An LRSet lists the variants one instantiation unit
+// compiles for one size and kind.
 template <int NBP, int KIND, int... VARS>
 struct LRSet {
   template <int VAR>
@@ -1194,6 +1197,8 @@ struct LRSet {
     constexpr int rl = (VAR & 16) ? 1 : (VAR & 1) ? 2 : 0;
     constexpr bool m3 = (VAR & 2) != 0;
     constexpr int occ = (VAR & 4) ? 2 : 1;
+    constexpr bool pf = (VAR & 64) != 0;
+    static_assert(!pf || (KIND == KIND_DENSITY && occ == 1 && parts == 1), "partial fractions: density, one part");
     grid.x *= parts;
     // columns of the row-layout inversions: nc rounded up to 8, 12 or 16, with
     // exact 10 (32-band windows) and 14 (48-band windows) for the
@@ -1205,21 +1210,21 @@ struct LRSet {
     }
     if constexpr (NBP == 32) {
       if (a.nc <= 10) {
-        hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 10, occ>), grid, dim3(64), 0, s, a);
+        hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 10, occ, pf>), grid, dim3(64), 0, s, a);
         return hipGetLastError();
       }
     }
     if (a.nc <= 12) {
-      hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 12, occ>), grid, dim3(64), 0, s, a);
+      hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 12, occ, pf>), grid, dim3(64), 0, s, a);
       return hipGetLastError();
     }
     if constexpr (NBP == 48) {
       if (a.nc <= 14) {
-        hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 14, occ>), grid, dim3(64), 0, s, a);
+        hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 14, occ, pf>), grid, dim3(64), 0, s, a);
         return hipGetLastError();
       }
     }
-    hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 16, occ>), grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL((lr_kernel<NBP, KIND, rl, m3, 16, occ, pf>), grid, dim3(64), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t launch(int var, const DysonArgs& a, dim3 grid, hipStream_t s) {

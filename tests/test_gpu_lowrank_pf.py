@@ -1,5 +1,7 @@
-"""GPU parity of the partial-fraction running sum of the 64-band low-rank
-kernel (nc > 8) against the FP64 oracle, on band structures built to reach
+"""GPU parity of the partial-fraction running sum of the low-rank kernels
+(nc > 8: the two-wavefront kernel of 64-band windows, variant 40, and the
+single-wavefront kernel's variants 74 and 90 on 32- and 48-band windows)
+against the FP64 oracle, on band structures built to reach
 each of its branches: distinct bands (the divided form), exactly degenerate and
 nearly degenerate pairs (the directly summed close pair), a triple degeneracy
 (more than one close partner: the k-point takes the direct running sum), and
@@ -22,25 +24,29 @@ def crafted(nc=14, nb=60, nk=8, nw=40, beta=40.0, seed=5):
     eps = lat.eps.copy().reshape(nk, nb)
     delta = np.pi / (8.0 * beta)
     eps[0, 3] = eps[0, 7] = eps[0, nb - 20] = eps[0, 20]      # triple degeneracy: direct sum
-    eps[1, 5] = eps[1, 33]                                # exact pair
+    eps[1, 5] = eps[1, nb - 7]                                # exact pair
     eps[2, 9] = eps[2, nb - 10] + 1e-4                         # near pair
     eps[3, 2] = eps[3, 17] + 0.5 * delta                  # close pair, half the threshold
-    eps[4, 11] = eps[4, 44] + 2.0 * delta                 # just outside: divided form
+    eps[4, 11] = eps[4, nb - 3] + 2.0 * delta                 # just outside: divided form
     eps[5, 0] = eps[5, nb - 1] + 1.001 * delta                # at the threshold
     eps[6, 8] = eps[6, 9]                                 # exact pair in one column tile
     eps[6, 24] = eps[6, 25] + 1e-9
+    assert nb >= 26
     lat2 = synth.Lattice(lat.nk, lat.nc, lat.nb, eps.ravel(), lat.wk, lat.proj)
     return wl, lat2
 
 
+@pytest.mark.parametrize("nb,var", [(60, 40), (44, 90), (30, 74)])
 @pytest.mark.parametrize("nc", [9, 14, 16])
-def test_pf_degeneracy_patterns(nc):
+def test_pf_degeneracy_patterns(nc, nb, var):
     from paper_1111_2157_amd.dyson import Context
 
-    wl, lat = crafted(nc=nc)
+    wl, lat = crafted(nc=nc, nb=nb)
     c = Context(0)
-    c.set_variant(0, 64, 40)  # the two-wavefront kernel
-    print("partial fractions, nc", nc, flush=True)
+    nbp = 16 * ((nb + 15) // 16)
+    assert var in c.variants(0, nbp)
+    c.set_variant(0, nbp, var)
+    print("partial fractions, nc", nc, "nb", nb, "variant", var, flush=True)
     mats, gl, sc = gpu_density(c, wl, 0.05, lat=lat)
     assert_nk_parity(mats, lat, wl.sigma, 0.05)
     assert_gloc_parity(gl, lat, wl.sigma, 0.05)
