@@ -50,14 +50,22 @@ LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
 # was measured on (their SHA-256) and the same workload, form and item classes
 # (padded size, inversion columns, items); otherwise "traffic" is null.
 TRAFFIC_SOURCES = ["paper_1111_2157_amd/csrc/lowrank_impl.h", "paper_1111_2157_amd/csrc/lowrank_pair_impl.h",
+                   "paper_1111_2157_amd/csrc/lowrank_p3_impl.h",
                    "paper_1111_2157_amd/csrc/batched_lr.h", "paper_1111_2157_amd/csrc/dyson_impl.h",
                    "paper_1111_2157_amd/csrc/batched_lr16.hip", "paper_1111_2157_amd/csrc/batched_lr32.hip",
                    "paper_1111_2157_amd/csrc/batched_lr48.hip", "paper_1111_2157_amd/csrc/batched_lr64.hip"]
-TRAFFIC = {}
+TRAFFIC = {
+    ("batched-Nk4096-Nb20..64-x8-Nw2048", "low-rank",
+     ((32, 5, 4672), (32, 14, 4672), (48, 5, 5824), (48, 14, 5824), (64, 5, 5920), (64, 14, 5920))): {
+        "bytes": 381.53e9,  # FETCH 247.46 GB + WRITE 134.07 GB
+        "profile": "profiles/batched_cfg4.md",
+        "sources_sha256": "a18a506419b5934ca92d21c9335ce3a9eb42913167cddcac94dddbb41610eadc",
+    },
+}
 
 
 def class_key(classes):
-    return tuple((c["nbp"], c["ncls"], c["items"]) for c in classes)
+    return tuple(sorted((c["nbp"], c["ncls"], c["items"]) for c in classes))
 
 
 def sources_sha256():

@@ -260,7 +260,8 @@ int dmft_batched_form(dmft_handle h);
  * class is one persistent launch.  The launches of a pass run either
  * concurrently on side streams of the handle (joined back into the pass's
  * stream, also inside a captured graph) or one after another on the pass's
- * stream, whichever the plan timed faster (dmft_batched_set_concurrent(h, 1)
+ * stream, whichever the plan timed faster, in the order (by cost, or the
+ * widest work-groups first) it timed faster (dmft_batched_set_concurrent(h, 1)
  * or (h, 0) fixes it for later plans instead, (h, -1) restores the timing;
  * DMFT_EINVAL for another value); dmft_batched_concurrent returns 1 for the
  * first, 0 for the second and -1 without a low-rank plan.  Writes up

@@ -1505,22 +1505,43 @@ int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
   // time both and keep the faster (the later of two timings of each, the first
   // pass after a rebuild warming the caches)
   h->b_concurrent = h->b_conc_pref != 0;
-  if (best_lr && h->b_cls.size() > 1 && h->b_conc_pref < 0) {
+  if (best_lr && h->b_cls.size() > 1) {
+    // launch orders: by cost (as built), or the widest work-groups first, so
+    // that a class whose work-group takes a whole CU is not starved by the
+    // narrower ones filling every CU partly; with the concurrency fixed by
+    // the caller only the orders are timed
+    std::vector<dmft_handle_s::LRClassPlan> orders[2];
+    orders[0] = h->b_cls;
+    orders[1] = h->b_cls;
+    auto width = [](const dmft_handle_s::LRClassPlan& c) { return 64 * (4 / lr_class_wgs_per_cu(c.nbp, c.ncls)); };
+    std::stable_sort(orders[1].begin(), orders[1].end(),
+                     [&](const auto& x, const auto& y) { return width(x) > width(y); });
     HIPCHK(h, hipMemcpy(w + h->b_mu, mu0.data(), sizeof(double) * n_iter, hipMemcpyHostToDevice));
-    double t[2] = {0.0, 0.0};
+    double t[2][2] = {{1e300, 1e300}, {1e300, 1e300}};
     for (int rep = 0; rep < 2; ++rep)
-      for (int conc = 0; conc < 2; ++conc) {
-        h->b_concurrent = conc != 0;
-        HIPCHK(h, hipEventRecord(e0, stream));
-        r = batched_pass_impl(h, (const double*)(w + h->b_mu), nullptr, nullptr, ws, ws_bytes, stream, true);
-        if (r) return r;
-        HIPCHK(h, hipEventRecord(e1, stream));
-        HIPCHK(h, hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
-        t[conc] = ms;
-      }
-    h->b_concurrent = t[1] <= t[0];
+      for (int o = 0; o < 2; ++o)
+        for (int conc = 0; conc < 2; ++conc) {
+          if (h->b_conc_pref >= 0 && conc != h->b_conc_pref) continue;
+          h->b_cls = orders[o];
+          h->b_concurrent = conc != 0;
+          HIPCHK(h, hipEventRecord(e0, stream));
+          r = batched_pass_impl(h, (const double*)(w + h->b_mu), nullptr, nullptr, ws, ws_bytes, stream, true);
+          if (r) return r;
+          HIPCHK(h, hipEventRecord(e1, stream));
+          HIPCHK(h, hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+          t[o][conc] = ms;  // the second repetition's time is kept
+        }
+    int bo = 0, bc = h->b_conc_pref >= 0 ? h->b_conc_pref : 1;
+    for (int o = 0; o < 2; ++o)
+      for (int conc = 0; conc < 2; ++conc)
+        if (t[o][conc] < t[bo][bc]) {
+          bo = o;
+          bc = conc;
+        }
+    h->b_cls = orders[bo];
+    h->b_concurrent = bc != 0;
     // the timing passes may have flagged the error word (mu = 0 need not suit
     // the inputs): the plan starts clean, as batched_build leaves it
     int zero = 0;
