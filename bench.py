@@ -126,9 +126,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU oracle sample time")
     ap.add_argument("--extra", action="store_true",
                     help="also time the general VJP, the pole route, the self-consistency step and the atom")
-    ap.add_argument("--section", choices=["pole", "sc", "atom", "adj"], default=None,
+    ap.add_argument("--section", choices=["pole", "sc", "atom", "adj", "d-shell", "f-shell"], default=None,
                     help="time only the pole route, the self-consistency step, the atom and energy "
-                         "sums or the two adjoint passes, and print that record")
+                         "sums, the two adjoint passes or the autotuned density pass of the d-shell "
+                         "or f-shell workload, and print that record")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (use the default variants)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device three times (reference for the HBM byte counters)")
@@ -606,9 +607,14 @@ def main():
 
     ctx = Context(0)
     if args.section:
+        from paper_1111_2157_amd import synth as _synth
+
         rec = {"pole": lambda: pole_route(ctx, not args.no_tune), "sc": lambda: self_consistency(ctx),
                "atom": lambda: atom_section(ctx),
-               "adj": lambda: adjoint_section(ctx, not args.no_tune)}[args.section]()
+               "adj": lambda: adjoint_section(ctx, not args.no_tune),
+               "d-shell": lambda: density_workload(ctx, _synth.d_shell(), args.steps, not args.no_tune),
+               "f-shell": lambda: density_workload(ctx, _synth.f_shell(), args.steps, not args.no_tune),
+               }[args.section]()
         print(json.dumps({"section": args.section, "result": rec}), flush=True)
         return
     from paper_1111_2157_amd import synth
