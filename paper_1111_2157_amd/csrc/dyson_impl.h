@@ -248,6 +248,24 @@ __device__ __forceinline__ const T* fresh(const T* p) {
   return p;
 }
 
+// A value the caller knows to be the same in every lane, moved to scalar
+// registers (the compiler cannot prove it for values loaded through a generic
+// pointer, and keeps such values in vector registers otherwise).
+__device__ __forceinline__ double uniform_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int64_t uniform_l(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // Projector fragments are re-read (from L1/L2) where they are used, so that they
 // do not occupy registers during the Gauss-Jordan sweep.  The volatile access
 // also pins each load to its place in the program order (each one is waited

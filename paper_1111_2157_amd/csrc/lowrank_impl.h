@@ -179,6 +179,15 @@ __device__ __forceinline__ double2 lr_proj(const double2* P, int al, int bd, int
   return (al < nc && bd < nb) ? P[al * nb + bd] : make_double2(0.0, 0.0);
 }
 
+// The same fragment, loaded where the call is: the row index is hidden from
+// the optimizer, so neither the load nor its address is moved out of the
+// enclosing loop (a hoisted address is a 64-bit register pair per load, kept
+// or spilled across the loop), and the load is not merged with an earlier one.
+__device__ __forceinline__ double2 lr_proj_here(const double2* P, int al, int bd, int nc, int nb) {
+  asm volatile("" : "+v"(al));
+  return lr_proj(P, al, bd, nc, nb);
+}
+
 // The two projector fragment sets of a lane: pa = S[q + 4 j][16 b + c16]
 // (B operand of R S, A operand of D S^dag) and pt = S[c16][16 t + 4 i + q]
 // (both operands of S D S^dag).
@@ -188,7 +197,7 @@ __device__ __forceinline__ void lr_load_pa(Proj<NBP>& pr, const double2* P, int 
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int b = 0; b < NBP / 16; ++b) {
-      double2 v = lr_proj(P, q + 4 * j, 16 * b + c16, nc, nb);
+      double2 v = lr_proj_here(P, q + 4 * j, 16 * b + c16, nc, nb);
       pr.pa_r[j][b] = v.x;
       pr.pa_i[j][b] = v.y;
     }
@@ -199,7 +208,7 @@ __device__ __forceinline__ void lr_load_pt(Proj<NBP>& pr, const double2* P, int 
   for (int t = 0; t < NBP / 16; ++t)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      double2 v = lr_proj(P, c16, 16 * t + 4 * i + q, nc, nb);
+      double2 v = lr_proj_here(P, c16, 16 * t + 4 * i + q, nc, nb);
       pr.pt_r[t][i] = v.x;
       pr.pt_i[t][i] = v.y;
     }
@@ -327,7 +336,7 @@ __device__ __forceinline__ void lr_x_packed(const Proj<NBP>& pr, const double2* 
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         if (16 * t + 4 * i >= nb) break;
-        const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
+        const double2 s = RL == 2 ? lr_proj_here(P, c16, 16 * t + 4 * i + q, nc, nb)
                                   : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
         const double2 sa = lower_rows8(s);
         const double2 dd = sh.dtab[fa][16 * t + 4 * i + q];
@@ -358,7 +367,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   const int n1 = min(n0 + a.wt, a.nw);
   const int kk0 = ktile * a.kt;
   const int kk1 = min(kk0 + a.kt, a.nklist);
-  const double mu = a.mu_ptr ? *a.mu_ptr : a.mu;
+  const double mu = uniform_d(a.mu_ptr ? *a.mu_ptr : a.mu);
   const int nc = a.nc;
   const int kc = (nc + 3) >> 2;
   // nc >= 1 (and nb >= nc below): the first chunk of every contraction over
@@ -381,8 +390,8 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   int bad = 0, nonfinite = 0;
 
   for (int kk = kk0; kk < kk1; ++kk) {
-    const int k = a.klist ? a.klist[kk] : kk;
-    const int nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
+    const int k = uniform_i(a.klist ? a.klist[kk] : kk);
+    const int nb = uniform_i(a.nb_uniform > 0 ? a.nb_uniform : a.nb[k]);
     __builtin_assume(nb >= 1 && nb <= NBP);
     // k-points are bucketed by padded size: NBP - 16 < nb, so every chunk but
     // those of the last 16 bands is full.  This is a promise to the compiler,
@@ -391,7 +400,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
     // bucket before any launch.  The adjoint kinds, whose unrolled bodies
     // would then outgrow the registers, are not told.
     if constexpr (KIND == KIND_DENSITY || KIND == KIND_TRACE) __builtin_assume(nb > NBP - 16);
-    const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
+    const int64_t ob = uniform_l(a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k]);
     const double* eps = a.eps + ob;
     // band energies this lane enters into the resolvent table of every
     // frequency group (band (lane + 64 it) mod NBP), read once per k; for
@@ -406,7 +415,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
       epl[it] = (EPL && r < nb) ? eps[r] : 0.0;
     }
     const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
-    const double wk = a.wk[k];
+    const double wk = uniform_d(a.wk[k]);
     // general product: Nbar_k (row-major) and the real diagonal of Nt = Nbar + Nbar^dag at
     // band 16 t + c16
     const double2* ntb = nullptr;
@@ -502,7 +511,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
         wave_sync();
         // 1. X of the four frequencies n .. n+3 (repeating the last one past n1)
         //    into LDS, in the output layout of the matrix core
-        if constexpr (RL == 1) lr_load_pt<NBP>(pr, fresh(P), nc, nb, q, c16);
+        if constexpr (RL == 1) lr_load_pt<NBP>(pr, P, nc, nb, q, c16);
         if constexpr (NC <= 8) {
           lr_x_packed<NBP, RL, M3>(pr, P, nc, nb, sh, q, c16);
         } else {
@@ -515,7 +524,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   #pragma unroll
               for (int i = 0; i < 4; ++i) {
                 if (16 * t + 4 * i >= nb) break;
-                const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
+                const double2 s = RL == 2 ? lr_proj_here(P, c16, 16 * t + 4 * i + q, nc, nb)
                                           : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
                 const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
                 double2 a1 = cmul(s, dd);
@@ -564,9 +573,9 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
         // 3. per frequency: R, then the running sum / G_loc partial or the traces
         if constexpr (RL == 1) {
           if constexpr (KIND == KIND_DENSITY)
-            lr_load_pa<NBP>(pr, fresh(P), nc, nb, q, c16);
+            lr_load_pa<NBP>(pr, P, nc, nb, q, c16);
           else
-            lr_load_pt<NBP>(pr, fresh(P), nc, nb, q, c16);
+            lr_load_pt<NBP>(pr, P, nc, nb, q, c16);
         }
   #pragma unroll
         for (int f = 0; f < 4; ++f) {
@@ -660,7 +669,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                   if (j >= kc) break;
-                  const double2 s = RL == 2 ? lr_proj(fresh(P), q + 4 * j, 16 * c + c16, nc, nb)
+                  const double2 s = RL == 2 ? lr_proj_here(P, q + 4 * j, 16 * c + c16, nc, nb)
                                             : make_double2(pr.pa_r[j][c], pr.pa_i[j][c]);
                   qa.mac(rtr[j], rti[j], s.x, s.y);
                 }
@@ -689,7 +698,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                   if (j >= kc) break;
-                  const double2 s = RL == 2 ? lr_proj(fresh(P), q + 4 * j, 16 * t + c16, nc, nb)
+                  const double2 s = RL == 2 ? lr_proj_here(P, q + 4 * j, 16 * t + c16, nc, nb)
                                             : make_double2(pr.pa_r[j][t], pr.pa_i[j][t]);
                   const double2 aa = cmul(dt, make_double2(s.x, -s.y));
                   pw[t].mac(aa.x, aa.y, rnr[j], rni[j]);
@@ -705,7 +714,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                   if (j >= kc) break;
-                  const double2 s = RL == 2 ? lr_proj(fresh(P), q + 4 * j, 16 * b + c16, nc, nb)
+                  const double2 s = RL == 2 ? lr_proj_here(P, q + 4 * j, 16 * b + c16, nc, nb)
                                             : make_double2(pr.pa_r[j][b], pr.pa_i[j][b]);
                   qa.mac(rtr[j], rti[j], s.x, s.y);
                 }
@@ -724,7 +733,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   #pragma unroll
                   for (int j = 0; j < 4; ++j) {
                     if (j >= kc) break;
-                    const double2 s = RL == 2 ? lr_proj(fresh(P), q + 4 * j, 16 * t + c16, nc, nb)
+                    const double2 s = RL == 2 ? lr_proj_here(P, q + 4 * j, 16 * t + c16, nc, nb)
                                               : make_double2(pr.pa_r[j][t], pr.pa_i[j][t]);
                     double2 aa = cmul(dt, make_double2(s.x, -s.y));
                     sacc[t][c].mac(aa.x, aa.y, qr[j], qi[j]);
@@ -744,7 +753,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
             for (int i = 0; i < 4; ++i) chk += glr[i] + gli[i] + rtr[i] + rti[i];
             if (!__builtin_isfinite(chk)) nonfinite = 1;
             auto ptf = [&](int t, int i) -> double2 {
-              return RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
+              return RL == 2 ? lr_proj_here(P, c16, 16 * t + 4 * i + q, nc, nb)
                              : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
             };
             // every lane has read Gl of this frequency: its LDS tile is free for transposes
@@ -943,7 +952,7 @@ __device__ __forceinline__ void lr_tile_part(const DysonArgs& a, int ktile, int 
   #pragma unroll
               for (int i = 0; i < 4; ++i) {
                 if (16 * t + 4 * i >= nb) break;
-                const double2 s = RL == 2 ? lr_proj(fresh(P), c16, 16 * t + 4 * i + q, nc, nb)
+                const double2 s = RL == 2 ? lr_proj_here(P, c16, 16 * t + 4 * i + q, nc, nb)
                                         : make_double2(pr.pt_r[t][i], pr.pt_i[t][i]);
                 const double2 dd = sh.dtab[f][16 * t + 4 * i + q];
                 double2 a2 = cmul(cmul(s, dd), dd);

@@ -70,7 +70,7 @@ __device__ __forceinline__ void p3_load_x(double2 (&pt)[T][4], double2 (&ps)[T][
   for (int t = 0; t < T; ++t)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      pt[t][i] = lr_proj(P, c16, 16 * t + 4 * i + q, nc, nb);
+      pt[t][i] = lr_proj_here(P, c16, 16 * t + 4 * i + q, nc, nb);
       ps[t][i] = spread5(pt[t][i]);
     }
 }
@@ -82,7 +82,7 @@ __device__ __forceinline__ void p3_load_k(double2 (&pk)[4][T], const double2* P,
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int b = 0; b < T; ++b)
-      pk[j][b] = hj[j] < 3 ? lr_proj(P, aj[j], 16 * b + c16, nc, nb) : make_double2(0.0, 0.0);
+      pk[j][b] = hj[j] < 3 ? lr_proj_here(P, aj[j], 16 * b + c16, nc, nb) : make_double2(0.0, 0.0);
 }
 
 // RL = 0: projector fragments kept in registers for the whole k; RL = 1: loaded
@@ -98,7 +98,7 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
   const int n1 = min(n0 + a.wt, a.nw);
   const int kk0 = ktile * a.kt;
   const int kk1 = min(kk0 + a.kt, a.nklist);
-  const double mu = a.mu_ptr ? *a.mu_ptr : a.mu;
+  const double mu = uniform_d(a.mu_ptr ? *a.mu_ptr : a.mu);
   const int nc = a.nc;
   // the dispatchers take this kernel for nc <= 5 only
   __builtin_assume(nc >= 1 && nc <= 5);
@@ -123,21 +123,24 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
   int bad = 0, nonfinite = 0;
 
   for (int kk = kk0; kk < kk1; ++kk) {
-    const int k = a.klist ? a.klist[kk] : kk;
-    const int nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
+    const int k = uniform_i(a.klist ? a.klist[kk] : kk);
+    const int nb = uniform_i(a.nb_uniform > 0 ? a.nb_uniform : a.nb[k]);
     __builtin_assume(nb >= 1 && nb <= NBP);
     // bucketed by padded size (checked on the host before any launch)
     __builtin_assume(nb > NBP - 16);
-    const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
+    const int64_t ob = uniform_l(a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k]);
     const double* eps = a.eps + ob;
-    double epl[NDT];
+    // band of table entry lane + 64 it: (lane + 64 it) mod NBP takes NE distinct
+    // values per lane (64 it mod 48 = 16 (it mod 3); one value for 16 and 32)
+    constexpr int NE = NBP == 48 ? 3 : 1;
+    double epl[NE];
 #pragma unroll
-    for (int it = 0; it < NDT; ++it) {
+    for (int it = 0; it < NE; ++it) {
       const int r = (lane + 64 * it) % NBP;
       epl[it] = r < nb ? eps[r] : 0.0;
     }
     const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
-    const double wk = a.wk[k];
+    const double wk = uniform_d(a.wk[k]);
     double2 pt[T][4], ps[T][4], pk[4][T];
     if constexpr (RL == 0) {
       p3_load_x<T>(pt, ps, P, nc, nb, q, c16);
@@ -160,7 +163,7 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
         const int f = idx / NBP, r = idx - f * NBP;
         const int nf = min(n + f, n1 - 1);
         const double wn = (double)(2 * nf + 1) * M_PI / beta;
-        sh.dtab[f][r] = r < nb ? inv_z_minus(mu, wn, epl[it]) : make_double2(0.0, 0.0);
+        sh.dtab[f][r] = r < nb ? inv_z_minus(mu, wn, epl[it % NE]) : make_double2(0.0, 0.0);
       }
       // row ri of Sigma of the three frequencies of slot g, for stage 2 (rows
       // past nc read row nc - 1 and are discarded there)
@@ -174,7 +177,7 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
       }
       wave_sync();
       // 1. X of the four slots, three frequencies per product
-      if constexpr (RL == 1) p3_load_x<T>(pt, ps, fresh(P), nc, nb, q, c16);
+      if constexpr (RL == 1) p3_load_x<T>(pt, ps, P, nc, nb, q, c16);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (n + 3 * c >= n1) break;
@@ -253,7 +256,7 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
       }
       wave_sync();
       // 3. per slot: R, Q, the running sum of G
-      if constexpr (RL == 1) p3_load_k<T>(pk, fresh(P), hj, aj, nc, nb, c16);
+      if constexpr (RL == 1) p3_load_k<T>(pk, P, hj, aj, nc, nb, c16);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int fb = n + 3 * c;
@@ -399,7 +402,7 @@ __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, i
   const int n1 = min(n0 + a.wt, a.nw);
   const int kk0 = ktile * a.kt;
   const int kk1 = min(kk0 + a.kt, a.nklist);
-  const double mu = a.mu_ptr ? *a.mu_ptr : a.mu;
+  const double mu = uniform_d(a.mu_ptr ? *a.mu_ptr : a.mu);
   const int nc = a.nc;
   // the dispatchers take this kernel for nc <= 5 only
   __builtin_assume(nc >= 1 && nc <= 5);
@@ -422,14 +425,14 @@ __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, i
   int bad = 0, nonfinite = 0;
 
   for (int kk = kk0; kk < kk1; ++kk) {
-    const int k = a.klist ? a.klist[kk] : kk;
-    const int nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
+    const int k = uniform_i(a.klist ? a.klist[kk] : kk);
+    const int nb = uniform_i(a.nb_uniform > 0 ? a.nb_uniform : a.nb[k]);
     // every k of a 64-band bucket has 48 < nb <= 64 (checked on the host)
     __builtin_assume(nb > 48 && nb <= 64);
-    const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
+    const int64_t ob = uniform_l(a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k]);
     const double el = lane < nb ? a.eps[ob + lane] : 0.0;
     const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
-    const double wk = a.wk[k];
+    const double wk = uniform_d(a.wk[k]);
     // the projector into LDS: every fragment of the k is read from there, with
     // LDS latency (the previous k, or item, ended with a work-group barrier)
 #pragma unroll

@@ -251,13 +251,13 @@ __device__ __forceinline__ void pf_finish(v4d (&s1)[4][2], v4d (&s2)[4][2], v4d 
 template <int NC, bool PF = false>
 __device__ __forceinline__ void lr_pair_tile(const DysonArgs& a, int ktile, int wtile, LRPairShared& sh, int tid) {
   constexpr int NBP = 64, T = 4;
-  const int w = tid >> 6, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int q = lane >> 4, c16 = lane & 15;
   const int n0 = wtile * a.wt;
   const int n1 = min(n0 + a.wt, a.nw);
   const int kk0 = ktile * a.kt;
   const int kk1 = min(kk0 + a.kt, a.nklist);
-  const double mu = a.mu_ptr ? *a.mu_ptr : a.mu;
+  const double mu = uniform_d(a.mu_ptr ? *a.mu_ptr : a.mu);
   const int nc = a.nc;
   const int kc = (nc + 3) >> 2;
   // the launch keeps nc <= NC columns and takes more than 8 only for nc > 8
@@ -274,14 +274,14 @@ __device__ __forceinline__ void lr_pair_tile(const DysonArgs& a, int ktile, int 
   int bad = 0, nonfinite = 0;
 
   for (int kk = kk0; kk < kk1; ++kk) {
-    const int k = a.klist ? a.klist[kk] : kk;
-    const int nb = a.nb_uniform > 0 ? a.nb_uniform : a.nb[k];
+    const int k = uniform_i(a.klist ? a.klist[kk] : kk);
+    const int nb = uniform_i(a.nb_uniform > 0 ? a.nb_uniform : a.nb[k]);
     // every k of a 64-band bucket has 48 < nb <= 64 (checked on the host)
     __builtin_assume(nb > NBP - 16 && nb <= NBP);
-    const int64_t ob = a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k];
+    const int64_t ob = uniform_l(a.nb_uniform > 0 ? (int64_t)k * nb : a.off_b[k]);
     const double* eps = a.eps + ob;
     const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
-    const double wk = a.wk[k];
+    const double wk = uniform_d(a.wk[k]);
     // partial-fraction form: the close partner (if any) of each owned column,
     // and whether every column of the work-group has at most one
     int partner[2] = {-1, -1};
@@ -304,27 +304,35 @@ __device__ __forceinline__ void lr_pair_tile(const DysonArgs& a, int ktile, int 
       for (int n = n0; n < n1; n += 8) {
         // ---- 0. resolvent table and Sigma of this wavefront's four frequencies
         const int nw0 = n + 4 * w;
+        {
+          const double er = lane < nb ? eps[lane] : 0.0;  // band lane of the table
   #pragma unroll
-        for (int it = 0; it < 4; ++it) {
-          const int f = it, r = lane;  // 4 x 64 entries: frequency it, band lane
-          const int nf = min(nw0 + f, n1 - 1);
-          const double wn = (double)(2 * nf + 1) * M_PI / beta;
-          sh.dtab[4 * w + f][r] = r < nb ? inv_z_minus(mu, wn, eps[r]) : make_double2(0.0, 0.0);
+          for (int f = 0; f < 4; ++f) {
+            const int nf = min(nw0 + f, n1 - 1);
+            const double wn = (double)(2 * nf + 1) * M_PI / beta;
+            sh.dtab[4 * w + f][lane] = lane < nb ? inv_z_minus(mu, wn, er) : make_double2(0.0, 0.0);
+          }
         }
         // Sigma of the four frequencies, NC x NC positions each, loaded now and
         // stored to LDS after the X products (their latency hides behind them)
         constexpr int NPOS = 4 * NC * NC;
         constexpr int NLD = (NPOS + 63) / 64;
+        // The positions come from a lane index the compiler cannot see through:
+        // hoisted out of the frequency loop they would be kept (and spilled) as
+        // one 64-bit address per load, each reloaded before its load.
+        int lane_l = lane;
+        asm volatile("" : "+v"(lane_l));
+        // One base address per group (uniform) and 32-bit offsets per load.
+        const double2* sgb = reinterpret_cast<const double2*>(a.sigma) + (int64_t)nw0 * nc * nc;
+        const int flast = n1 - 1 - nw0;
         double2 sgl[NLD];
   #pragma unroll
         for (int m = 0; m < NLD; ++m) {
-          const int idx = lane + 64 * m;
+          const int idx = lane_l + 64 * m;
           const int f = idx / (NC * NC), rem = idx - f * (NC * NC);
           const int ra = rem / NC, cb = rem - ra * NC;
-          const int nf = min(nw0 + f, n1 - 1);
           const bool in = idx < NPOS && ra < nc && cb < nc;
-          sgl[m] = in ? reinterpret_cast<const double2*>(a.sigma)[(int64_t)nf * nc * nc + ra * nc + cb]
-                      : make_double2(0.0, 0.0);
+          sgl[m] = in ? sgb[min(f, flast) * nc * nc + ra * nc + cb] : make_double2(0.0, 0.0);
         }
         wave_sync();
         // ---- 1. X_f = S D_f S^dag of the four frequencies into LDS
