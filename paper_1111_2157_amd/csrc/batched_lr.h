@@ -77,7 +77,7 @@ lr_p3_quad_class_kernel(const BatchItem* items, int n_items, const DysonArgs* ar
     const BatchItem b = items[it];
     const DysonArgs a = args[b.args];
     static_assert(NBP == 64, "four-wavefront items are 64-band windows");
-    lr_p3_quad_tile(a, b.ktile, b.wtile, sh, tid);
+    lr_p3_quad_tile<true>(a, b.ktile, b.wtile, sh, tid);
   }
 }
 

@@ -14,7 +14,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) lr
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1))) lr_p3_quad_kernel(DysonArgs a) {
   __shared__ LRP3QuadShared sh;
-  lr_p3_quad_tile(a, blockIdx.x / a.n_wtiles, blockIdx.x % a.n_wtiles, sh, threadIdx.x);
+  lr_p3_quad_tile<true>(a, blockIdx.x / a.n_wtiles, blockIdx.x % a.n_wtiles, sh, threadIdx.x);
 }
 
 hipError_t launch_lowrank_p3(int nbp, const DysonArgs& a, dim3 grid, hipStream_t s) {

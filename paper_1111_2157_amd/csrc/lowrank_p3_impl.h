@@ -393,6 +393,170 @@ struct LRP3QuadShared {
   double2 sgm[48][25];       // Sigma of the group's frequencies (nc x nc, row stride 5)
 };
 
+// Partial-fraction form of the running sum on four wavefronts (the identity of
+// lowrank_pair_impl.h: F[v][v'] = ((W S - S^dag Y) / (E_v - E_v'))[v][v'] with
+// W = sum_n D_n S^dag R_n and Y = sum_n R_n S D_n, the diagonal and at most one
+// close partner per column summed directly).  In the packed index the slot's R
+// is block-diagonal, so per slot
+//     P = S^dag_w R  (rows: bands of tile w; column p' = 5 h + alpha'),
+//     Q = R S_w      (rows p = 5 h + alpha; columns: bands of tile w),
+// two products of four steps each in place of the T + T^2 products of Q and
+// the running sum, and the frequency of a packed index scales its row (Q) or
+// column (P) with d:
+//     W[v][p']  += d_h(p')(v) P[v][p'],        Y[p][v'] += d_h(p)(v') Q[p][v'],
+//     diag[p][v'] += d^2 Q[p][v'],             close[p][v'] += d(partner) d Q[p][v'].
+// W and Y keep the three frequencies of a slot in their own blocks of the
+// packed index; the products W S_3 and S_3^dag Y over the packed index at the
+// end of the k-point add them up (S_3[5 h + beta][v] = S[beta][v]).
+
+// Close partner of the owned column vc; whether the partial-fraction form
+// applies to the k-point (every column of the work-group has at most one).
+__device__ __forceinline__ bool p3q_pairs(const double* eps, int nb, int vc, double beta, int& partner) {
+  const double delta = M_PI / (8.0 * beta);
+  const double ec = vc < nb ? eps[vc] : 0.0;
+  int cnt = 0, pv = -1;
+  for (int v = 0; v < nb; ++v) {
+    const bool close = vc < nb && v != vc && __builtin_fabs(eps[v] - ec) < delta;
+    pv = close ? v : pv;
+    cnt += close ? 1 : 0;
+  }
+  partner = pv;
+  return !__syncthreads_or(cnt > 1);
+}
+
+// One slot (three frequencies, the first fb) of the partial-fraction sums of
+// wavefront w.  Register map (re, im):
+//   W, rows 16 w + q + 4 i, column c16           s1[0], s1[1]
+//   Y, rows q + 4 i, column 16 w + c16           s1[2], s1[3]
+//   diagonal sums (same layout as Y)             s2[0], s2[1]
+//   close-pair sums (same layout as Y)           s2[2], s2[3]
+// rtr/rti: R[c16][q + 4 i] of the slot; pw[j] = S[alpha_j][16 w + c16] for the
+// packed index q + 4 j (zero for p = 15).
+template <class Shared>
+__device__ __forceinline__ void p3q_pf_step(v4d (&s1)[4], v4d (&s2)[4], const v4d& rtr, const v4d& rti,
+                                            const Shared& sh, const double2 (&pw)[4], const int (&hj)[4], int s,
+                                            int fb, int n1, int partner, int w, int q, int c16, double2& dsum) {
+  const int vc = 16 * w + c16;
+  const int hc = c16 / 5;
+  v4d rnr, rni;  // R[q + 4 i][c16], read transposed from the tile that holds R^T
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 v = sh.buf[s][c16 * 17 + q + 4 * i];
+    rnr[i] = v.x;
+    rni[i] = v.y;
+  }
+  // the D term of the owned column
+#pragma unroll
+  for (int h = 0; h < 3; ++h) {
+    if (fb + h >= n1) break;
+    const double2 d = sh.dtab[3 * s + h][vc];
+    dsum.x += d.x;
+    dsum.y += d.y;
+  }
+  CAcc<true> qa, pa;
+  qa.zero();
+  pa.zero();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    qa.mac(rtr[j], rti[j], pw[j].x, pw[j].y);
+    pa.mac(pw[j].x, -pw[j].y, rnr[j], rni[j]);
+  }
+  const v4d xr = qa.re(), xi = qa.im();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int h = hj[i];
+    const bool ok = h < 3 && fb + h < n1;
+    const int row = 3 * s + (h < 3 ? h : 2);
+    const double2 d = ok ? sh.dtab[row][vc] : make_double2(0.0, 0.0);
+    const double2 dp = (ok && partner >= 0) ? sh.dtab[row][partner] : make_double2(0.0, 0.0);
+    const double2 y = cmul(make_double2(xr[i], xi[i]), d);
+    s1[2][i] += y.x;
+    s1[3][i] += y.y;
+    const double2 g = cmul(y, d), c = cmul(y, dp);
+    s2[0][i] += g.x;
+    s2[1][i] += g.y;
+    s2[2][i] += c.x;
+    s2[3][i] += c.y;
+  }
+  const v4d pr = pa.re(), pi = pa.im();
+  const bool okc = hc < 3 && fb + hc < n1;
+  const int rowc = 3 * s + (hc < 3 ? hc : 2);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 dv = okc ? sh.dtab[rowc][16 * w + q + 4 * i] : make_double2(0.0, 0.0);
+    const double2 x = cmul(make_double2(pr[i], pi[i]), dv);
+    s1[0][i] += x.x;
+    s1[1][i] += x.y;
+  }
+}
+
+// End of a k-point: W of the four wavefronts through LDS, then for the owned
+// column tile w and every row tile F = (W S_3 - S_3^dag Y) / (E_v - E_v'), the
+// diagonal and the close pair from their direct sums, plus the D term on the
+// diagonal; stored in the running sum's partial layout.
+template <class Shared>
+__device__ __forceinline__ void p3q_pf_finish(const v4d (&s1)[4], const v4d (&s2)[4], const double2& dsum,
+                                              Shared& sh, const double* eps, int nb, int partner, double2* sp, int w,
+                                              int q, int c16, const int (&hj)[4], const int (&aj)[4], int tid) {
+  constexpr int T = 4;
+  const int vc = 16 * w + c16;
+  // the frequency loop ended with a work-group barrier: the slot tiles are free
+  double2* wl = &sh.buf[0][0];  // W[v][p'] at v * 17 + p' (64 x 17 < 16 x 16 x 17)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) wl[(16 * w + q + 4 * i) * 17 + c16] = make_double2(s1[0][i], s1[1][i]);
+  __syncthreads();
+  double2 pw[4];  // S_3[q + 4 j][vc]
+#pragma unroll
+  for (int j = 0; j < 4; ++j) pw[j] = hj[j] < 3 ? sh.sproj[aj[j]][vc] : make_double2(0.0, 0.0);
+  // the diagonal and the close pair: S^dag contracted over the packed rows of
+  // this lane, then over the four lanes of the column
+  double2 dg = make_double2(0.0, 0.0), cl = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 sq = (hj[i] < 3 && partner >= 0) ? sh.sproj[aj[i]][partner] : make_double2(0.0, 0.0);
+    dg = cadd(dg, cmul(make_double2(pw[i].x, -pw[i].y), make_double2(s2[0][i], s2[1][i])));
+    cl = cadd(cl, cmul(make_double2(sq.x, -sq.y), make_double2(s2[2][i], s2[3][i])));
+  }
+#pragma unroll
+  for (int off = 16; off <= 32; off <<= 1) {
+    dg.x += __shfl_xor(dg.x, off);
+    dg.y += __shfl_xor(dg.y, off);
+    cl.x += __shfl_xor(cl.x, off);
+    cl.y += __shfl_xor(cl.y, off);
+  }
+  const double ec = vc < nb ? eps[vc] : 0.0;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    CAcc<true> acc;
+    acc.zero();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double2 wv = wl[(16 * t + c16) * 17 + q + 4 * j];  // W[16 t + c16][q + 4 j]
+      acc.mac(wv.x, wv.y, pw[j].x, pw[j].y);
+      const double2 st = hj[j] < 3 ? sh.sproj[aj[j]][16 * t + c16] : make_double2(0.0, 0.0);
+      acc.mac(-st.x, st.y, s1[2][j], s1[3][j]);  // - S_3^dag Y
+    }
+    const v4d fr = acc.re(), fi = acc.im();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int v = 16 * t + q + 4 * i;
+      double2 val;
+      if (v == vc) {
+        val = make_double2(dg.x + dsum.x, dg.y + dsum.y);
+      } else if (v == partner) {
+        val = cl;
+      } else {
+        const double ev = v < nb ? eps[v] : 0.0;
+        const double inv = (v < nb && vc < nb) ? 1.0 / (ev - ec) : 0.0;
+        val = make_double2(fr[i] * inv, fi[i] * inv);
+      }
+      sp[((t * T + w) * 4 + i) * 64 + (tid & 63)] = val;
+    }
+  }
+  __syncthreads();  // the W tile is the next k-point's slot tiles
+}
+
+template <bool PF = false>
 __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, int wtile, LRP3QuadShared& sh,
                                                 int tid) {
   constexpr int T = 4;
@@ -444,6 +608,17 @@ __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, i
       }
     }
     __syncthreads();
+    // partial-fraction form: the close partner (if any) of the owned column, and
+    // whether every column of the work-group has at most one
+    int partner = -1;
+    bool pfk = false;
+    if constexpr (PF) pfk = p3q_pairs(a.eps + ob, nb, 16 * w + c16, beta, partner);
+    // one k-point, with the running sum in the direct (PFK false) or the
+    // partial-fraction form; the two instantiations keep separate registers
+    auto k_body = [&](auto pf_tag) {
+    constexpr bool PFK = decltype(pf_tag)::value;
+    // direct form: the owned column tile of sum_n G, all four row tiles (three
+    // products); partial-fraction form: see p3q_pf_step
     v4d s1[T], s2[T], s3[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) s1[t] = s2[t] = s3[t] = (v4d){0.0, 0.0, 0.0, 0.0};
@@ -636,6 +811,10 @@ __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, i
           rti[i] = v.y;
         }
         if (!want_s) continue;
+        if constexpr (PFK) {
+          p3q_pf_step(s1, s2, rtr, rti, sh, pw, hj, s, fb, n1, partner, w, q, c16, dsum);
+          continue;
+        }
         // d of the slot's frequency of contraction slot j at band 16 t + c16 is
         // read from the table where it is used (zero for frequencies past the
         // tile's end), which keeps it out of the registers
@@ -685,7 +864,10 @@ __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, i
       __syncthreads();
     }  // frequency groups
 
-    if (want_s) {
+    if (want_s && PFK) {
+      double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
+      p3q_pf_finish(s1, s2, dsum, sh, a.eps + ob, nb, partner, sp, w, q, c16, hj, aj, tid);
+    } else if (want_s) {
       double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
 #pragma unroll
       for (int t = 0; t < T; ++t) {
@@ -702,6 +884,11 @@ __device__ __forceinline__ void lr_p3_quad_tile(const DysonArgs& a, int ktile, i
         }
       }
     }
+    };
+    if (pfk)
+      k_body(std::true_type{});
+    else
+      k_body(std::false_type{});
   }  // k
   if (bad) atomicOr(a.err, ERR_SINGULAR);
   if (nonfinite) atomicOr(a.err, ERR_NONFINITE);

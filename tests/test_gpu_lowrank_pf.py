@@ -1,7 +1,8 @@
 """GPU parity of the partial-fraction running sum of the low-rank kernels
 (nc > 8: the two-wavefront kernel of 64-band windows, variant 40, and the
-single-wavefront kernel's variants 74 and 90 on 32- and 48-band windows)
-against the FP64 oracle, on band structures built to reach
+single-wavefront kernel's variants 74 and 90 on 32- and 48-band windows;
+nc <= 5: the four-wavefront kernel of 64-band windows that packs three
+frequencies per tile, variant 42) against the FP64 oracle, on band structures built to reach
 each of its branches: distinct bands (the divided form), exactly degenerate and
 nearly degenerate pairs (the directly summed close pair), a triple degeneracy
 (more than one close partner: the k-point takes the direct running sum), and
@@ -65,4 +66,23 @@ def test_pf_temperatures(beta, nw):
     mats, gl, sc = gpu_density(c, wl, -0.1, lat=lat)
     assert_nk_parity(mats, lat, wl.sigma, -0.1)
     assert_gloc_parity(gl, lat, wl.sigma, -0.1)
+    c.close()
+
+
+@pytest.mark.parametrize("nc", [1, 3, 5])
+@pytest.mark.parametrize("beta", [40.0, 100.0])
+def test_pf_packed_four_wavefronts(nc, beta):
+    """Three frequencies per tile on 64-band windows (nb = 60 and 52), with the
+    same degeneracy patterns; 100 frequencies leave a partial group of 48."""
+    from paper_1111_2157_amd.dyson import Context
+
+    c = Context(0)
+    assert 42 in c.variants(0, 64)
+    c.set_variant(0, 64, 42)
+    for nb in (60, 52):
+        wl, lat = crafted(nc=nc, nb=nb, nw=100, beta=beta, seed=11 + nc)
+        print("partial fractions, packed, nc", nc, "nb", nb, "beta", beta, flush=True)
+        mats, gl, sc = gpu_density(c, wl, 0.15, lat=lat)
+        assert_nk_parity(mats, lat, wl.sigma, 0.15)
+        assert_gloc_parity(gl, lat, wl.sigma, 0.15)
     c.close()
