@@ -43,11 +43,13 @@ lr_class_kernel(const BatchItem* items, int n_items, const DysonArgs* args, int*
 }
 
 // Single-wavefront class for nc <= 5, three frequencies per matrix-core tile
-// (lowrank_p3_impl.h): NBP in {16, 32, 48}.
-template <int NBP, int RL, bool M3>
+// (lowrank_p3_impl.h): NBP in {16, 32, 48}; PF: the partial-fraction form of
+// the running sum, with its LDS slots for close-pair sums.
+template <int NBP, int RL, bool M3, bool PF = false>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1)))
 lr_p3_class_kernel(const BatchItem* items, int n_items, const DysonArgs* args, int* counter) {
   __shared__ LRP3Shared<NBP> sh;
+  __shared__ double2 pfc[PF ? NBP / 16 * 4 * 64 : 1];
   const int lane = threadIdx.x;
   for (;;) {
     int it = 0;
@@ -56,7 +58,7 @@ lr_p3_class_kernel(const BatchItem* items, int n_items, const DysonArgs* args, i
     if (it >= n_items) break;
     const BatchItem b = items[it];
     const DysonArgs a = args[b.args];
-    lr_p3_tile<NBP, RL, M3>(a, b.ktile, b.wtile, sh, lane);
+    lr_p3_tile<NBP, RL, M3, PF>(a, b.ktile, b.wtile, sh, lane, pfc);
   }
 }
 

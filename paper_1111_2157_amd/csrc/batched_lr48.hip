@@ -10,7 +10,7 @@ hipError_t launch_lr_class_48(int ncls, const void* items, int n_items, const Dy
   const BatchItem* it = reinterpret_cast<const BatchItem*>(items);
   switch (ncls) {
     case 5:
-      hipLaunchKernelGGL((lr_p3_class_kernel<48, 1, true>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
+      hipLaunchKernelGGL((lr_p3_class_kernel<48, 1, true, true>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);
       break;
     case 8:
       hipLaunchKernelGGL((lr_class_kernel<48, 1, true, 8>), dim3(grid), dim3(64), 0, s, it, n_items, args, counter);

@@ -88,8 +88,9 @@ __device__ __forceinline__ void p3_load_k(double2 (&pk)[4][T], const double2* P,
 // RL = 0: projector fragments kept in registers for the whole k; RL = 1: loaded
 // per group of twelve frequencies at the start of the stage that uses them
 // (48-band windows, whose fragments would not fit next to the running sum).
-template <int NBP, int RL, bool M3>
-__device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wtile, LRP3Shared<NBP>& sh, int lane) {
+template <int NBP, int RL, bool M3, bool PF = false>
+__device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wtile, LRP3Shared<NBP>& sh, int lane,
+                                           double2* pfc = nullptr) {
   constexpr int T = NBP / 16;
   constexpr int NDT = 12 * NBP / 64;  // resolvent-table entries per lane
   const int q = lane >> 4, c16 = lane & 15;
@@ -141,18 +142,51 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
     }
     const double2* P = reinterpret_cast<const double2*>(a.proj) + ob * nc;
     const double wk = uniform_d(a.wk[k]);
+    // partial-fraction form: the close partner (if any) of each owned column,
+    // and whether every column has at most one
+    int partner[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) partner[t] = -1;
+    bool pfk = false;
+    if constexpr (PF) pfk = want_s && lr_pf_pairs<T>(eps, nb, c16, beta, partner);
+    // one k-point, with the running sum in the direct (PFK false) or the
+    // partial-fraction form; the two instantiations keep separate registers
+    auto k_body = [&](auto pf_tag) {
+    constexpr bool PFK = decltype(pf_tag)::value;
     double2 pt[T][4], ps[T][4], pk[4][T];
     if constexpr (RL == 0) {
       p3_load_x<T>(pt, ps, P, nc, nb, q, c16);
       p3_load_k<T>(pk, P, hj, aj, nc, nb, c16);
     }
-    CAcc<M3 && T * T <= 4> sacc[T][T];
+    // direct form: the running sum; partial-fraction form: W (rows 16 t + q + 4 i,
+    // packed column c16), Y (packed rows q + 4 i, column 16 t + c16), this
+    // lane's part of the diagonal sum of column 16 t + c16 (already contracted
+    // with S_3^dag over its packed rows), the close-pair sums in the LDS slots pfc
+    CAcc<M3 && T * T <= 4> sacc[PFK ? 1 : T][PFK ? 1 : T];
+    CAcc<M3 && T <= 2> pw[PFK ? T : 1];
+    v4d yr[PFK ? T : 1], yi[PFK ? T : 1];
+    double2 dgl[PFK ? T : 1];
+    bool anyc[PFK ? T : 1];
     double2 dsum[T];
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      dsum[t] = make_double2(0.0, 0.0);
+    for (int t = 0; t < T; ++t) dsum[t] = make_double2(0.0, 0.0);
+    if constexpr (PFK) {
 #pragma unroll
-      for (int c = 0; c < T; ++c) sacc[t][c].zero();
+      for (int t = 0; t < T; ++t) {
+        pw[t].zero();
+        yr[t] = yi[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+        dgl[t] = make_double2(0.0, 0.0);
+        anyc[t] = __any(partner[t] >= 0);
+        if (anyc[t]) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) pfc[(t * 4 + i) * 64 + lane] = make_double2(0.0, 0.0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int c = 0; c < T; ++c) sacc[t][c].zero();
     }
 
     for (int n = n0; n < n1; n += 12) {
@@ -268,16 +302,26 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
           glr[i] = v.x;
           gli[i] = v.y;
         }
-        // Sigma' of the slot, block-diagonal: sa[j] = Sigma'[c16][q + 4 j], sb[j] = Sigma'[q + 4 j][c16]
-        const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)min(fb + hc, n1 - 1) * nc * nc;
+        // Sigma' of the slot, block-diagonal: sa[j] = Sigma'[c16][q + 4 j], sb[j] =
+        // Sigma'[q + 4 j][c16].  With RL = 1 the positions come from a lane index
+        // the compiler cannot see through, from the slot's (uniform) base: hoisted
+        // out of the loops they would be kept, or spilled, as one 64-bit offset per
+        // load next to the 48-band running sum.
+        int lo = lane;
+        if constexpr (RL == 1) asm volatile("" : "+v"(lo));
+        const int co = lo & 15, qo = lo >> 4;
+        const int hco = co / 5, aco = co - 5 * hco;
+        const double2* sg = reinterpret_cast<const double2*>(a.sigma) + (int64_t)fb * nc * nc;
+        const int fo = (min(fb + hco, n1 - 1) - fb) * nc * nc;
         double sa_r[4], sa_i[4];
         v4d sbr, sbi;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const bool in = cin && hj[j] == hc && aj[j] < nc;
-          double2 v = in ? sg[ac * nc + aj[j]] : make_double2(0.0, 0.0);
-          double2 u = in ? sg[aj[j] * nc + ac] : make_double2(0.0, 0.0);
-          if (in && aj[j] == ac) {
+          const int hjo = (qo + 4 * j) / 5, ajo = qo + 4 * j - 5 * hjo;
+          const bool in = hco < 3 && aco < nc && hjo == hco && ajo < nc;
+          double2 v = in ? sg[fo + aco * nc + ajo] : make_double2(0.0, 0.0);
+          double2 u = in ? sg[fo + ajo * nc + aco] : make_double2(0.0, 0.0);
+          if (in && ajo == aco) {
             v.x -= edc_c;
             u.x -= edc_c;
           }
@@ -322,7 +366,48 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
             dsum[t].y += d.y;
           }
         }
-        if (want_s) {
+        if constexpr (PFK) {
+          // R[q + 4 i][c16] from R^T through the slot's LDS tile, which every
+          // lane has read Gl from
+          v4d rnr, rni;
+          wave_sync();
+          tile_transpose(rtr, rti, rnr, rni, sh.buf[c], q, c16);
+#pragma unroll
+          for (int b = 0; b < T; ++b) {
+            // Q = R S_3 for column tile b, row p scaled by d of its frequency:
+            // Y += Q, diagonal += S_3^dag Q d, close += Q d(partner)
+            CAcc<M3> qa;
+            qa.zero();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) qa.mac(rtr[j], rti[j], pk[j][b].x, pk[j][b].y);
+            const v4d xr = qa.re(), xi = qa.im();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const double2 y = cmul(make_double2(xr[i], xi[i]), dk[i][b]);
+              yr[b][i] += y.x;
+              yi[b][i] += y.y;
+              const double2 g = cmul(y, dk[i][b]);
+              dgl[b] = cadd(dgl[b], cmul(make_double2(pk[i][b].x, -pk[i][b].y), g));
+              if (anyc[b]) {
+                const bool ok = partner[b] >= 0 && hj[i] < 3 && fb + hj[i] < n1;
+                const double2 dp =
+                    ok ? sh.dtab[3 * c + min(hj[i], 2)][max(partner[b], 0)] : make_double2(0.0, 0.0);
+                const double2 pp = cmul(y, dp);
+                double2* slot = &pfc[(b * 4 + i) * 64 + lane];
+                const double2 o = *slot;
+                *slot = make_double2(o.x + pp.x, o.y + pp.y);
+              }
+            }
+          }
+          // W_t += [D_h S^dag]_h R over the packed index
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const double2 aa = cmul(dk[j][t], make_double2(pk[j][t].x, -pk[j][t].y));
+              pw[t].mac(aa.x, aa.y, rnr[j], rni[j]);
+            }
+        } else if (want_s) {
 #pragma unroll
           for (int b = 0; b < T; ++b) {
             // Q = R S_3, row p scaled by d of its frequency at band 16 b + c16
@@ -351,7 +436,74 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
       wave_sync();
     }  // frequency groups
 
-    if (want_s) {
+    if constexpr (PFK) {
+      double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
+      // S_3 of the k-point (the frequency loop reloads it per group when RL = 1)
+      double2 sk[4][T];
+      p3_load_k<T>(sk, P, hj, aj, nc, nb, c16);
+      // W through LDS (row v, packed column p' at v * 17 + p'; the slot tiles
+      // are free after the last group), read back as the A operand of W S_3
+      double2* wl = &sh.buf[0][0];
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const v4d re = pw[t].re(), im = pw[t].im();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wl[(16 * t + q + 4 * i) * 17 + c16] = make_double2(re[i], im[i]);
+      }
+      wave_sync();
+#pragma unroll
+      for (int c = 0; c < T; ++c) {
+        const int vc = 16 * c + c16;
+        const double ec = vc < nb ? eps[vc] : 0.0;
+        // the diagonal and the close pair: S_3^dag over the packed rows of this
+        // lane, then over the four lanes of the column
+        double2 dg = dgl[c], cl = make_double2(0.0, 0.0);
+        const int pv = partner[c];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (anyc[c]) {
+            const double2 spv = (pv >= 0 && hj[i] < 3) ? lr_proj(P, aj[i], pv, nc, nb) : make_double2(0.0, 0.0);
+            cl = cadd(cl, cmul(make_double2(spv.x, -spv.y), pfc[(c * 4 + i) * 64 + lane]));
+          }
+        }
+#pragma unroll
+        for (int off = 16; off <= 32; off <<= 1) {
+          dg.x += __shfl_xor(dg.x, off);
+          dg.y += __shfl_xor(dg.y, off);
+          cl.x += __shfl_xor(cl.x, off);
+          cl.y += __shfl_xor(cl.y, off);
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          // W S_3 - S_3^dag Y for tile (t, c), contraction over the packed index
+          CAcc<M3 && T <= 2> acc;
+          acc.zero();
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const double2 wv = wl[(16 * t + c16) * 17 + q + 4 * j];
+            acc.mac(wv.x, wv.y, sk[j][c].x, sk[j][c].y);
+            acc.mac(-sk[j][t].x, sk[j][t].y, yr[c][j], yi[c][j]);
+          }
+          const v4d fr = acc.re(), fi = acc.im();
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int v = 16 * t + q + 4 * i;
+            double2 val;
+            if (t == c && v == vc) {
+              val = make_double2(dg.x + dsum[c].x, dg.y + dsum[c].y);
+            } else if (v == pv) {
+              val = cl;
+            } else {
+              const double ev = v < nb ? eps[v] : 0.0;
+              const double inv = (v < nb && vc < nb) ? 1.0 / (ev - ec) : 0.0;
+              val = make_double2(fr[i] * inv, fi[i] * inv);
+            }
+            sp[((t * T + c) * 4 + i) * 64 + lane] = val;
+          }
+        }
+      }
+      wave_sync();  // the W tile is the next k-point's slot tiles
+    } else if (want_s) {
       double2* sp = reinterpret_cast<double2*>(a.spart) + (int64_t)wtile * a.s_stride + a.off_s[k];
 #pragma unroll
       for (int t = 0; t < T; ++t)
@@ -368,6 +520,11 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
             sp[e * 64 + lane] = v;
           }
     }
+    };
+    if (pfk)
+      k_body(std::true_type{});
+    else
+      k_body(std::false_type{});
   }  // k
   if (bad) atomicOr(a.err, ERR_SINGULAR);
   if (nonfinite) atomicOr(a.err, ERR_NONFINITE);

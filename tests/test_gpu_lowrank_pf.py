@@ -71,15 +71,18 @@ def test_pf_temperatures(beta, nw):
 
 @pytest.mark.parametrize("nc", [1, 3, 5])
 @pytest.mark.parametrize("beta", [40.0, 100.0])
-def test_pf_packed_four_wavefronts(nc, beta):
-    """Three frequencies per tile on 64-band windows (nb = 60 and 52), with the
-    same degeneracy patterns; 100 frequencies leave a partial group of 48."""
+@pytest.mark.parametrize("nbs", [(60, 52), (44, 36), (30, 28)])
+def test_pf_packed(nc, beta, nbs):
+    """Three frequencies per tile (variant 42) on 64-band windows (four
+    wavefronts) and on 48- and 32-band windows (one wavefront), with the same
+    degeneracy patterns; 100 frequencies leave a partial group (of 48 and 12)."""
     from paper_1111_2157_amd.dyson import Context
 
     c = Context(0)
-    assert 42 in c.variants(0, 64)
-    c.set_variant(0, 64, 42)
-    for nb in (60, 52):
+    nbp = 16 * ((nbs[0] + 15) // 16)
+    assert 42 in c.variants(0, nbp)
+    c.set_variant(0, nbp, 42)
+    for nb in nbs:
         wl, lat = crafted(nc=nc, nb=nb, nw=100, beta=beta, seed=11 + nc)
         print("partial fractions, packed, nc", nc, "nb", nb, "beta", beta, flush=True)
         mats, gl, sc = gpu_density(c, wl, 0.15, lat=lat)
