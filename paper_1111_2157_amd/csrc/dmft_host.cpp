@@ -1392,7 +1392,8 @@ extern "C" {
 // Tiles the batched plan times: the default tile of every iterate and the same
 // with the k-tile halved and quartered (more, smaller items balance the class
 // kernels' last round better, at the price of more G_loc partials), then the
-// frequency tile halved.
+// frequency tile halved, and the k-tile quartered with the frequency tile
+// doubled.
 std::vector<std::vector<Tile>> batched_tile_candidates(const std::vector<Tile>& base) {
   std::vector<std::vector<Tile>> out;
   for (int f : {1, 2, 4}) {
@@ -1410,6 +1411,17 @@ std::vector<std::vector<Tile>> batched_tile_candidates(const std::vector<Tile>& 
   for (auto& t : c) {
     const int wt = std::max(4, t.wt / 2);
     changed |= wt != t.wt;
+    t.wt = wt;
+  }
+  if (changed) out.push_back(c);
+  // the quarter k-tile with twice the frequency tile: as many items as the
+  // half k-tile, and half the frequency-tile partials of the running sum
+  c = base;
+  changed = false;
+  for (auto& t : c) {
+    const int kt = std::max(1, t.kt / 4), wt = 2 * t.wt;
+    changed |= kt != t.kt;
+    t.kt = kt;
     t.wt = wt;
   }
   if (changed) out.push_back(c);
