@@ -288,18 +288,18 @@ __device__ __forceinline__ double2 lower_rows8(double2 s) {
 // so a frequency adds two rank-nc products instead of the nb x nb update
 // (D S^dag)(R S D), and the nb x nb products are formed once per k-point.  The
 // subtraction loses about |d| / |E_v - E_v'| digits, so the diagonal and pairs
-// closer than delta = pi / (8 beta) (an eighth of the first Matsubara
+// closer than delta = pi / (16 beta) (a sixteenth of the first Matsubara
 // frequency) are summed directly per column: sum_n d_v'^2 (R_n S)[.][v'] and,
 // for at most one close partner v, sum_n d_v d_v' (R_n S)[.][v'], contracted
 // with S^dag at the end of the k-point.  A k-point on which a column has more
-// than one close partner takes the direct running sum.  (Relative errors on
-// the test and benchmark inputs are near 1e-13.)
+// than one close partner takes the direct running sum.  (Normwise relative
+// errors on the test and benchmark inputs are below 1e-12.)
 //
 // Close partners of the columns v' = 16 c + c16 of this lane; returns whether
 // the form applies (the same answer in every lane of the wavefront).
 template <int T>
 __device__ __forceinline__ bool lr_pf_pairs(const double* eps, int nb, int c16, double beta, int (&partner)[T]) {
-  const double delta = M_PI / (8.0 * beta);
+  const double delta = M_PI / (16.0 * beta);
   int over = 0;
 #pragma unroll
   for (int c = 0; c < T; ++c) {

@@ -569,7 +569,7 @@ struct LRP3QuadShared {
 // Close partner of the owned column vc; whether the partial-fraction form
 // applies to the k-point (every column of the work-group has at most one).
 __device__ __forceinline__ bool p3q_pairs(const double* eps, int nb, int vc, double beta, int& partner) {
-  const double delta = M_PI / (8.0 * beta);
+  const double delta = M_PI / (16.0 * beta);
   const double ec = vc < nb ? eps[vc] : 0.0;
   int cnt = 0, pv = -1;
   for (int v = 0; v < nb; ++v) {

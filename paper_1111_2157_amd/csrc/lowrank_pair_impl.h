@@ -67,8 +67,9 @@ __device__ __forceinline__ void mac3(v4d& p1, v4d& p2, v4d& p3, double ar, doubl
 // so each frequency adds two rank-nc products of nb x nc instead of the nb x nb
 // update (D S^dag)(R S D), and the nb x nb products are formed once per k.  The
 // subtraction loses about |d| / |E_v - E_v'| digits, so pairs closer than
-// delta = pi / (8 beta) (an eighth of the first Matsubara frequency; relative
-// errors near 1e-13 on the test and benchmark inputs) and the diagonal are
+// delta = pi / (16 beta) (a sixteenth of the first Matsubara frequency;
+// normwise relative errors below 1e-12 on the test and benchmark inputs, and
+// near 3e-11 on the element of a pair just outside delta at beta = 100) and the diagonal are
 // summed directly: per owned column v' the diagonal sum_n d_v'^2 (R_n S)[.][v']
 // and, for at most one close partner v, sum_n d_v d_v' (R_n S)[.][v'], each
 // contracted with S^dag at the end of the k-point.  A k-point on which some
@@ -78,7 +79,7 @@ __device__ __forceinline__ void mac3(v4d& p1, v4d& p2, v4d& p3, double ar, doubl
 // returns whether the partial-fraction form applies to the k-point (the same
 // answer in every thread of the work-group).
 __device__ __forceinline__ bool pf_pairs(const double* eps, int nb, int v0, double beta, int (&partner)[2]) {
-  const double delta = M_PI / (8.0 * beta);
+  const double delta = M_PI / (16.0 * beta);
   int over = 0;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {

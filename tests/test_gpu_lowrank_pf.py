@@ -19,11 +19,11 @@ pytestmark = pytest.mark.gpu
 
 def crafted(nc=14, nb=60, nk=8, nw=40, beta=40.0, seed=5):
     """f-shell-like lattice whose k-points carry the degeneracy patterns above;
-    delta = pi / (8 beta) is the kernel's closeness threshold."""
+    delta = pi / (16 beta) is the kernel's closeness threshold."""
     wl = synth.f_shell(nk=nk, nb=nb, nc=nc, nw=nw, beta=beta, n_narrow=12, seed=seed)
     lat = wl.lattice
     eps = lat.eps.copy().reshape(nk, nb)
-    delta = np.pi / (8.0 * beta)
+    delta = np.pi / (16.0 * beta)
     eps[0, 3] = eps[0, 7] = eps[0, nb - 20] = eps[0, 20]      # triple degeneracy: direct sum
     eps[1, 5] = eps[1, nb - 7]                                # exact pair
     eps[2, 9] = eps[2, nb - 10] + 1e-4                         # near pair
