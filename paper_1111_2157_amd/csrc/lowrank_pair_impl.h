@@ -162,56 +162,65 @@ __device__ __forceinline__ void pf_step(v4d (&s1)[4][2], v4d (&s2)[4][2], v4d (&
   }
 }
 
-// End of a k-point: W of both wavefronts through LDS, then for the owned
+// End of a k-point: W of both wavefronts and the wavefront's Y through LDS,
+// the diagonal and close-pair sums contracted first, then for the owned
 // columns and every row tile F = (W S - S^dag Y) / (E_v - E_v'), the diagonal
 // and the close pair from their direct sums, plus the D term on the diagonal;
-// stored in the running sum's partial layout.
+// stored in the running sum's partial layout.  The tiles run in a loop (not
+// unrolled) with their operands read where they are used, so that little is
+// live at once.
 template <int NC>
 __device__ __forceinline__ void pf_finish(v4d (&s1)[4][2], v4d (&s2)[4][2], v4d (&s3)[4][2],
                                           const double2 (&dsum)[2], LRPairShared& sh, const double2* P,
                                           const double* eps, int nb, int nc, int kc, const int (&partner)[2],
                                           double2* sp, int w, int q, int c16, int tid) {
   constexpr int T = 4;
-  // the frequency loop ended with a work-group barrier: the Gl/R tiles are free
+  const int lane = tid & 63;
+  // the frequency loop ended with a work-group barrier: the Gl/R and Sigma tiles are free
   double2* wl = &sh.buf[0][0];  // W[v][beta] at v * 17 + beta (64 x 17 < 8 x 16 x 17)
+  double2* yl = &sh.sg[0][0];   // Y of owned column c, register i, at ((2 w + c) 4 + i) 64 + lane
 #pragma unroll
   for (int l = 0; l < 2; ++l) {
     const v4d re = s1[l][0] - s2[l][0], im = s3[l][0] - s1[l][0] - s2[l][0];
 #pragma unroll
     for (int i = 0; i < 4; ++i) wl[(16 * (2 * w + l) + q + 4 * i) * 17 + c16] = make_double2(re[i], im[i]);
   }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) yl[((2 * w + c) * 4 + i) * 64 + lane] = make_double2(s1[2][c][i], s2[2][c][i]);
+  // the diagonal and the close pair: sum over the orbitals q + 4 i (this lane's
+  // registers, then the four lanes of the column)
+  double2 dg[2], cl[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int vc = 16 * (2 * w + c) + c16;
+    const int pv = partner[c];
+    dg[c] = cl[c] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double2 s = lr_proj_here(P, q + 4 * i, vc, nc, nb);
+      dg[c] = cadd(dg[c], cmul(make_double2(s.x, -s.y), make_double2(s3[2][c][i], s1[3][c][i])));
+      const double2 sp_ = pv >= 0 ? lr_proj_here(P, q + 4 * i, pv, nc, nb) : make_double2(0.0, 0.0);
+      cl[c] = cadd(cl[c], cmul(make_double2(sp_.x, -sp_.y), make_double2(s2[3][c][i], s3[3][c][i])));
+    }
+#pragma unroll
+    for (int off = 16; off <= 32; off <<= 1) {
+      dg[c].x += __shfl_xor(dg[c].x, off);
+      dg[c].y += __shfl_xor(dg[c].y, off);
+      cl[c].x += __shfl_xor(cl[c].x, off);
+      cl[c].y += __shfl_xor(cl[c].y, off);
+    }
+  }
   __syncthreads();
-  double2 srow[4][T];  // S[q + 4 j][16 t + c16]
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int t = 0; t < T; ++t) srow[j][t] = lr_proj(P, q + 4 * j, 16 * t + c16, nc, nb);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int b = 2 * w + c;
     const int vc = 16 * b + c16;
     const double ec = vc < nb ? eps[vc] : 0.0;
-    const v4d yr = s1[2][c], yi = s2[2][c];
-    // the diagonal and the close pair: sum over the orbitals q + 4 i (this lane's
-    // registers, then the four lanes of the column)
-    double2 dg = make_double2(0.0, 0.0), cl = make_double2(0.0, 0.0);
     const int pv = partner[c];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const double2 s = w ? srow[i][2 + c] : srow[i][c];
-      const double2 sc = make_double2(s.x, -s.y);
-      dg = cadd(dg, cmul(sc, make_double2(s3[2][c][i], s1[3][c][i])));
-      const double2 sp_ = pv >= 0 ? lr_proj(P, q + 4 * i, pv, nc, nb) : make_double2(0.0, 0.0);
-      cl = cadd(cl, cmul(make_double2(sp_.x, -sp_.y), make_double2(s2[3][c][i], s3[3][c][i])));
-    }
-#pragma unroll
-    for (int off = 16; off <= 32; off <<= 1) {
-      dg.x += __shfl_xor(dg.x, off);
-      dg.y += __shfl_xor(dg.y, off);
-      cl.x += __shfl_xor(cl.x, off);
-      cl.y += __shfl_xor(cl.y, off);
-    }
-#pragma unroll
+    const double2 dgc = make_double2(dg[c].x + dsum[c].x, dg[c].y + dsum[c].y), clc = cl[c];
+#pragma unroll 1
     for (int t = 0; t < T; ++t) {
       CAcc<true> acc;
       acc.zero();
@@ -219,31 +228,31 @@ __device__ __forceinline__ void pf_finish(v4d (&s1)[4][2], v4d (&s2)[4][2], v4d 
       for (int j = 0; j < 4; ++j) {
         if (j >= kc) break;
         const double2 wv = wl[(16 * t + c16) * 17 + q + 4 * j];  // W[16 t + c16][q + 4 j]
-        const double2 sb = w ? srow[j][2 + c] : srow[j][c];
+        const double2 sb = lr_proj_here(P, q + 4 * j, vc, nc, nb);
         acc.mac(wv.x, wv.y, sb.x, sb.y);
-        const double2 st = srow[j][t];  // - S^dag: -(S[q + 4 j][16 t + c16])^*
-        acc.mac(-st.x, st.y, yr[j], yi[j]);
+        const double2 st = lr_proj_here(P, q + 4 * j, 16 * t + c16, nc, nb);  // - S^dag: -(S[q + 4 j][16 t + c16])^*
+        const double2 yv = yl[(b * 4 + j) * 64 + lane];
+        acc.mac(-st.x, st.y, yv.x, yv.y);
       }
       const v4d fr = acc.re(), fi = acc.im();
-      const bool diag_tile = t == b;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int v = 16 * t + q + 4 * i;
-        const double ev = v < nb ? eps[v] : 0.0;
         double2 val;
-        if (diag_tile && v == vc) {
-          val = make_double2(dg.x + dsum[c].x, dg.y + dsum[c].y);
+        if (v == vc) {
+          val = dgc;
         } else if (v == pv) {
-          val = cl;
+          val = clc;
         } else {
+          const double ev = v < nb ? eps[v] : 0.0;
           const double inv = (v < nb && vc < nb) ? 1.0 / (ev - ec) : 0.0;
           val = make_double2(fr[i] * inv, fi[i] * inv);
         }
-        sp[((t * T + b) * 4 + i) * 64 + (tid & 63)] = val;
+        sp[((t * T + b) * 4 + i) * 64 + lane] = val;
       }
     }
   }
-  __syncthreads();  // W's LDS is the next k-point's X tiles
+  __syncthreads();  // W's and Y's LDS are the next k-point's X and Sigma tiles
 }
 
 // NC: columns kept in the row-layout inversions (nc <= NC).  PF: the running sum
