@@ -450,30 +450,46 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
 #pragma unroll
         for (int i = 0; i < 4; ++i) wl[(16 * t + q + 4 * i) * 17 + c16] = make_double2(re[i], im[i]);
       }
-      wave_sync();
+      // the diagonal and the close pair: S_3^dag over the packed rows of this
+      // lane (the diagonal is contracted already), then over the four lanes of
+      // the column
+      double2 dg[T], cl[T];
 #pragma unroll
       for (int c = 0; c < T; ++c) {
-        const int vc = 16 * c + c16;
-        const double ec = vc < nb ? eps[vc] : 0.0;
-        // the diagonal and the close pair: S_3^dag over the packed rows of this
-        // lane, then over the four lanes of the column
-        double2 dg = dgl[c], cl = make_double2(0.0, 0.0);
+        dg[c] = dgl[c];
+        cl[c] = make_double2(0.0, 0.0);
         const int pv = partner[c];
+        if (anyc[c]) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          if (anyc[c]) {
-            const double2 spv = (pv >= 0 && hj[i] < 3) ? lr_proj(P, aj[i], pv, nc, nb) : make_double2(0.0, 0.0);
-            cl = cadd(cl, cmul(make_double2(spv.x, -spv.y), pfc[(c * 4 + i) * 64 + lane]));
+          for (int i = 0; i < 4; ++i) {
+            const double2 spv = (pv >= 0 && hj[i] < 3) ? lr_proj_here(P, aj[i], pv, nc, nb) : make_double2(0.0, 0.0);
+            cl[c] = cadd(cl[c], cmul(make_double2(spv.x, -spv.y), pfc[(c * 4 + i) * 64 + lane]));
           }
         }
 #pragma unroll
         for (int off = 16; off <= 32; off <<= 1) {
-          dg.x += __shfl_xor(dg.x, off);
-          dg.y += __shfl_xor(dg.y, off);
-          cl.x += __shfl_xor(cl.x, off);
-          cl.y += __shfl_xor(cl.y, off);
+          dg[c].x += __shfl_xor(dg[c].x, off);
+          dg[c].y += __shfl_xor(dg[c].y, off);
+          cl[c].x += __shfl_xor(cl[c].x, off);
+          cl[c].y += __shfl_xor(cl[c].y, off);
         }
+      }
+      // Y into the close-pair slots (read), for the B operand of S_3^dag Y
+      wave_sync();
 #pragma unroll
+      for (int c = 0; c < T; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pfc[(c * 4 + i) * 64 + lane] = make_double2(yr[c][i], yi[c][i]);
+      wave_sync();
+      // the tiles in a loop, operands read where they are used (little is live
+      // at once at the end of the k-point)
+#pragma unroll
+      for (int c = 0; c < T; ++c) {
+        const int vc = 16 * c + c16;
+        const double ec = vc < nb ? eps[vc] : 0.0;
+        const int pv = partner[c];
+        const double2 dgc = make_double2(dg[c].x + dsum[c].x, dg[c].y + dsum[c].y), clc = cl[c];
+#pragma unroll 1
         for (int t = 0; t < T; ++t) {
           // W S_3 - S_3^dag Y for tile (t, c), contraction over the packed index
           CAcc<M3 && T <= 2> acc;
@@ -481,18 +497,21 @@ __device__ __forceinline__ void lr_p3_tile(const DysonArgs& a, int ktile, int wt
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const double2 wv = wl[(16 * t + c16) * 17 + q + 4 * j];
-            acc.mac(wv.x, wv.y, sk[j][c].x, sk[j][c].y);
-            acc.mac(-sk[j][t].x, sk[j][t].y, yr[c][j], yi[c][j]);
+            const double2 sb = hj[j] < 3 ? lr_proj_here(P, aj[j], vc, nc, nb) : make_double2(0.0, 0.0);
+            acc.mac(wv.x, wv.y, sb.x, sb.y);
+            const double2 st = hj[j] < 3 ? lr_proj_here(P, aj[j], 16 * t + c16, nc, nb) : make_double2(0.0, 0.0);
+            const double2 yv = pfc[(c * 4 + j) * 64 + lane];
+            acc.mac(-st.x, st.y, yv.x, yv.y);
           }
           const v4d fr = acc.re(), fi = acc.im();
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int v = 16 * t + q + 4 * i;
             double2 val;
-            if (t == c && v == vc) {
-              val = make_double2(dg.x + dsum[c].x, dg.y + dsum[c].y);
+            if (v == vc) {
+              val = dgc;
             } else if (v == pv) {
-              val = cl;
+              val = clc;
             } else {
               const double ev = v < nb ? eps[v] : 0.0;
               const double inv = (v < nb && vc < nb) ? 1.0 / (ev - ec) : 0.0;
