@@ -57,9 +57,9 @@ TRAFFIC_SOURCES = ["paper_1111_2157_amd/csrc/lowrank_impl.h", "paper_1111_2157_a
 TRAFFIC = {
     ("batched-Nk4096-Nb20..64-x8-Nw2048", "low-rank",
      ((32, 5, 4672), (32, 14, 4672), (48, 5, 5824), (48, 14, 5824), (64, 5, 5920), (64, 14, 5920))): {
-        "bytes": 244.79e9,  # FETCH 111.64 GB + WRITE 133.15 GB
+        "bytes": 243.15e9,  # FETCH 110.09 GB + WRITE 133.06 GB
         "profile": "profiles/batched_cfg4.md",
-        "sources_sha256": "1557e14fc996380c94b0ea7048f88baf3ef82cc8a83a736d1b8015a14ad6f425",
+        "sources_sha256": "f18d62a695e1c1315a88c77ca24f04fd2f37be64be16e224ebbc954a9edd2b96",
     },
 }
 
