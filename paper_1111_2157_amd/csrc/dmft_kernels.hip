@@ -78,6 +78,7 @@ __device__ double block_sum(double v, double* red) {
 // Also the per-k scalars tr N, tr(S N S^dag), sum_v E_v N_vv.
 __global__ void __launch_bounds__(256) nk_epilogue_kernel(EpilogueArgs a, double* nk_out) {
   __shared__ double2 vinf[16 * 64];  // (Sigma_inf - V_DC) S   (nc x nb)
+  __shared__ double2 ps[16 * 64];    // S of the k-point (nc x nb), read nc times per element below
   __shared__ double red[256];
   const int k = blockIdx.x;
   const int nc = a.nc;
@@ -91,13 +92,15 @@ __global__ void __launch_bounds__(256) nk_epilogue_kernel(EpilogueArgs a, double
   const double mu = a.mu_ptr ? *a.mu_ptr : a.mu;
   const double beta = a.beta;
   const bool tail = a.tail_order == 2;
+  for (int idx = threadIdx.x; idx < nc * nb; idx += blockDim.x) ps[idx] = P[idx];
+  __syncthreads();
   for (int idx = threadIdx.x; idx < nc * nb; idx += blockDim.x) {
     int al = idx / nb, c = idx % nb;
     double2 acc = make_double2(0.0, 0.0);
     for (int be = 0; be < nc; ++be) {
       double2 m = sinf ? sinf[al * nc + be] : make_double2(0.0, 0.0);
       if (al == be) m.x -= a.e_dc[al];
-      double2 p = P[be * nb + c];
+      double2 p = ps[be * nb + c];
       acc.x += m.x * p.x - m.y * p.y;
       acc.y += m.x * p.y + m.y * p.x;
     }
@@ -117,34 +120,41 @@ __global__ void __launch_bounds__(256) nk_epilogue_kernel(EpilogueArgs a, double
     return acc;
   };
   double tr = 0.0, hks = 0.0, ncor = 0.0;
+  // one thread per pair (r <= c): the two frequency sums it needs, Ssum[r][c]
+  // and Ssum[c][r], are read once for both elements
   for (int idx = threadIdx.x; idx < nb * nb; idx += blockDim.x) {
-    int r = idx / nb, c = idx % nb;
-    double2 m1 = make_double2(r == c ? eps[r] - mu : 0.0, 0.0);
-    double2 qcr = make_double2(0.0, 0.0);  // (S^dag S)[c][r]
-    for (int al = 0; al < nc; ++al) {
-      double2 pr = P[al * nb + r];
-      double2 v = vinf[al * nb + c];
-      m1.x += pr.x * v.x + pr.y * v.y;   // conj(S[al][r]) * V[al][c]
-      m1.y += pr.x * v.y - pr.y * v.x;
-      double2 pc = P[al * nb + c];
-      qcr.x += pc.x * pr.x + pc.y * pr.y;  // conj(S[al][c]) * S[al][r]
-      qcr.y += pc.x * pr.y - pc.y * pr.x;
+    const int r0 = idx / nb, c0 = idx % nb;
+    if (r0 > c0) continue;
+    const double2 s_rc = ssum(r0, c0), s_cr = r0 == c0 ? s_rc : ssum(c0, r0);
+    for (int e = 0; e < (r0 == c0 ? 1 : 2); ++e) {
+      const int r = e ? c0 : r0, c = e ? r0 : c0;
+      const double2 s1 = e ? s_cr : s_rc, s2 = e ? s_rc : s_cr;
+      double2 m1 = make_double2(r == c ? eps[r] - mu : 0.0, 0.0);
+      double2 qcr = make_double2(0.0, 0.0);  // (S^dag S)[c][r]
+      for (int al = 0; al < nc; ++al) {
+        double2 pr = ps[al * nb + r];
+        double2 v = vinf[al * nb + c];
+        m1.x += pr.x * v.x + pr.y * v.y;  // conj(S[al][r]) * V[al][c]
+        m1.y += pr.x * v.y - pr.y * v.x;
+        double2 pc = ps[al * nb + c];
+        qcr.x += pc.x * pr.x + pc.y * pr.y;  // conj(S[al][c]) * S[al][r]
+        qcr.y += pc.x * pr.y - pc.y * pr.x;
+      }
+      double2 nv;
+      nv.x = (s1.x + s2.x) / beta;
+      nv.y = (s1.y - s2.y) / beta;
+      if (r == c) nv.x += 0.5;
+      if (tail) {
+        nv.x += -0.25 * beta * m1.x + 2.0 * a.s2 * m1.x / beta;
+        nv.y += -0.25 * beta * m1.y + 2.0 * a.s2 * m1.y / beta;
+      }
+      if (nk_out) reinterpret_cast<double2*>(nk_out)[on + r * nb + c] = nv;
+      if (r == c) {
+        tr += nv.x;
+        hks += eps[r] * nv.x;
+      }
+      ncor += nv.x * qcr.x - nv.y * qcr.y;
     }
-    double2 s1 = ssum(r, c), s2 = ssum(c, r);
-    double2 nv;
-    nv.x = (s1.x + s2.x) / beta;
-    nv.y = (s1.y - s2.y) / beta;
-    if (r == c) nv.x += 0.5;
-    if (tail) {
-      nv.x += -0.25 * beta * m1.x + 2.0 * a.s2 * m1.x / beta;
-      nv.y += -0.25 * beta * m1.y + 2.0 * a.s2 * m1.y / beta;
-    }
-    if (nk_out) reinterpret_cast<double2*>(nk_out)[on + idx] = nv;
-    if (r == c) {
-      tr += nv.x;
-      hks += eps[r] * nv.x;
-    }
-    ncor += nv.x * qcr.x - nv.y * qcr.y;
   }
   tr = block_sum(tr, red);
   ncor = block_sum(ncor, red);
