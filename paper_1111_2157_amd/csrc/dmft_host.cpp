@@ -1494,13 +1494,19 @@ int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
       r = batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, &cand, lr);
       if (r) return r;
       HIPCHK(h, hipMemcpy(w + h->b_mu, mu0.data(), sizeof(double) * n_iter, hipMemcpyHostToDevice));
-      HIPCHK(h, hipEventRecord(e0, stream));
-      r = batched_pass_impl(h, (const double*)(w + h->b_mu), nullptr, nullptr, ws, ws_bytes, stream, true);
-      if (r) return r;
-      HIPCHK(h, hipEventRecord(e1, stream));
-      HIPCHK(h, hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+      // low-rank candidates run twice and keep the faster pass (their times
+      // differ by a few percent, about the spread of one pass)
+      float ms = 1e30f;
+      for (int rep = 0; rep < (lr ? 2 : 1); ++rep) {
+        HIPCHK(h, hipEventRecord(e0, stream));
+        r = batched_pass_impl(h, (const double*)(w + h->b_mu), nullptr, nullptr, ws, ws_bytes, stream, true);
+        if (r) return r;
+        HIPCHK(h, hipEventRecord(e1, stream));
+        HIPCHK(h, hipEventSynchronize(e1));
+        float t = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&t, e0, e1));
+        ms = std::min(ms, t);
+      }
       if (first < 0) first = ms;
       if (lr) best_lowrank = std::min(best_lowrank, (double)ms);
       if (ms < best) {
