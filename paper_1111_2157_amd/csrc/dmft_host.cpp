@@ -994,9 +994,21 @@ int dmft_autotune(dmft_handle h, const dmft_lattice* lat, const dmft_sigma* sig,
     int nv = dyson_variants(nbp, kind, vars, 16);
     Tile base = heuristic_tile(nk, nw);
     std::vector<Tile> tiles;
+    // frequency tiles around the default, then the k-tile halved and doubled
+    // with the frequency tile scaled the other way (the same number of items;
+    // fewer G_loc partial read-backs against fewer partials of the running sum)
     for (int f : {1, 2, 4, 8}) {
       Tile t = base;
       t.wt = std::max(4, std::min(nw, base.wt * f / 2));
+      bool dup = false;
+      for (auto& u : tiles) dup |= (u.wt == t.wt && u.kt == t.kt);
+      if (!dup) tiles.push_back(t);
+    }
+    for (int g : {-1, 1}) {
+      Tile t = base;
+      t.kt = g < 0 ? base.kt / 2 : std::min(nk, base.kt * 2);
+      t.wt = g < 0 ? std::min(nw, base.wt * 2) : std::max(4, base.wt / 2);
+      if (t.kt < 1 || t.kt == base.kt) continue;
       bool dup = false;
       for (auto& u : tiles) dup |= (u.wt == t.wt && u.kt == t.kt);
       if (!dup) tiles.push_back(t);
