@@ -1405,7 +1405,7 @@ extern "C" {
 // with the k-tile halved and quartered (more, smaller items balance the class
 // kernels' last round better, at the price of more G_loc partials), then the
 // frequency tile halved, and the k-tile quartered with the frequency tile
-// doubled.
+// rounded down and up to whole groups of 48 frequencies, or doubled.
 std::vector<std::vector<Tile>> batched_tile_candidates(const std::vector<Tile>& base) {
   std::vector<std::vector<Tile>> out;
   for (int f : {1, 2, 4}) {
@@ -1426,6 +1426,20 @@ std::vector<std::vector<Tile>> batched_tile_candidates(const std::vector<Tile>& 
     t.wt = wt;
   }
   if (changed) out.push_back(c);
+  // the quarter k-tile with the frequency tile rounded down and up to a
+  // multiple of 48 (whole groups of the four-wavefront packed kernel, and of
+  // the 12, 8 and 4 frequencies of the others)
+  for (int up : {0, 1}) {
+    c = base;
+    changed = false;
+    for (auto& t : c) {
+      const int kt = std::max(1, t.kt / 4), wt = t.wt >= 96 ? (t.wt + (up ? 47 : 0)) / 48 * 48 : t.wt;
+      changed |= kt != t.kt && wt != t.wt;
+      t.kt = kt;
+      t.wt = wt;
+    }
+    if (changed) out.push_back(c);
+  }
   // the quarter k-tile with twice the frequency tile: as many items as the
   // half k-tile, and half the frequency-tile partials of the running sum
   c = base;
