@@ -56,6 +56,13 @@ TRAFFIC_SOURCES = ["paper_1111_2157_amd/csrc/lowrank_impl.h", "paper_1111_2157_a
                    "paper_1111_2157_amd/csrc/batched_lr48.hip", "paper_1111_2157_amd/csrc/batched_lr64.hip"]
 TRAFFIC = {
     ("batched-Nk4096-Nb20..64-x8-Nw2048", "low-rank",
+     ((32, 5, 5256), (32, 14, 5256), (48, 5, 6552), (48, 14, 6552), (64, 5, 6660), (64, 14, 6660))): {
+        "bytes": 244.49e9,  # FETCH 109.96 GB + WRITE 134.52 GB
+        "profile": "profiles/batched_cfg4.md",
+        "sources_sha256": "f18d62a695e1c1315a88c77ca24f04fd2f37be64be16e224ebbc954a9edd2b96",
+    },
+    # the plan's quarter k-tile with the default frequency tile of 256
+    ("batched-Nk4096-Nb20..64-x8-Nw2048", "low-rank",
      ((32, 5, 4672), (32, 14, 4672), (48, 5, 5824), (48, 14, 5824), (64, 5, 5920), (64, 14, 5920))): {
         "bytes": 243.15e9,  # FETCH 110.09 GB + WRITE 133.06 GB
         "profile": "profiles/batched_cfg4.md",
@@ -131,6 +138,9 @@ def parse():
                          "sums, the two adjoint passes or the autotuned density pass of the d-shell "
                          "or f-shell workload, and print that record")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (use the default variants)")
+    ap.add_argument("--plan-candidate", type=int, default=-1,
+                    help="batched plan: take this tile candidate without timing the others "
+                         "(reproducible profiles; -1, the default, times every candidate)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device three times (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -517,7 +527,7 @@ def batched_flops(wl):
     return fl
 
 
-def batched_headline(ctx, steps, warmup, tune=True):
+def batched_headline(ctx, steps, warmup, tune=True, plan_candidate=-1):
     """The batched workload: plan (the autotuner picks the form and tiles),
     capture one pass into a hipGraph with kernel timing on, replay it warmup
     times, then time steps replays.  Returns the record's measurement fields."""
@@ -530,6 +540,7 @@ def batched_headline(ctx, steps, warmup, tune=True):
     lats = [Lattice.from_host(l) for l in wl.lattices]
     sigs = [SelfEnergy.from_host(s) for s in wl.sigmas]
     ctx.batched_set_form(FORM_AUTO if tune else FORM_LOWRANK)
+    ctx.batched_set_tile_candidate(plan_candidate)
     t0 = time.perf_counter()
     ctx.batched_plan(lats, sigs, 2)
     plan_s = time.perf_counter() - t0
@@ -569,11 +580,13 @@ def batched_headline(ctx, steps, warmup, tune=True):
     from paper_1111_2157_amd.dyson import FORM_LOWRANK as LR
     form = "low-rank" if ctx.batched_form() == LR else "dense"
     concurrent = ctx.batched_concurrent() == 1
+    tile_candidate = ctx.batched_tile_candidate()
     del nks, gls
     ctx._b_ws = None
     torch.cuda.empty_cache()
     return wl, {"sec": sec, "evals": evals, "flops": fl, "kernel_s": kavg, "launches": launches,
                 "classes": classes, "plan_seconds": plan_s, "form": form, "concurrent": concurrent,
+                "tile_candidate": tile_candidate,
                 "direct_pass_ms": direct_ms / max(npass, 1)}
 
 
@@ -619,7 +632,7 @@ def main():
         return
     from paper_1111_2157_amd import synth
 
-    wl, m = batched_headline(ctx, args.steps, args.warmup, not args.no_tune)
+    wl, m = batched_headline(ctx, args.steps, args.warmup, not args.no_tune, args.plan_candidate)
     achieved = m["flops"] / m["kernel_s"] / 1e12
     traffic = measured_traffic(wl.name, m["form"], m["classes"])
     rec = {
@@ -655,6 +668,7 @@ def main():
                      "flop_count": "8 (Nb^2 Nc + 2 Nb Nc^2 + 5 Nc^3) per (k, i w_n), low-rank form"},
         "batched_classes": m["classes"],
         "plan_seconds": m["plan_seconds"],
+        "plan_tile_candidate": m["tile_candidate"],
     }
     if not args.no_mu:
         rec["mu_search"] = mu_search(ctx, not args.no_tune)

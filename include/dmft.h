@@ -275,6 +275,18 @@ int dmft_batched_classes(dmft_handle h, int max, int32_t* nbp, int32_t* ncls, in
 int dmft_batched_concurrent(dmft_handle h);
 int dmft_batched_set_concurrent(dmft_handle h, int mode);
 
+/* Tile candidates of the batched plan, in the order the plan times them: the
+ * default k- and frequency tiles of every iterate, the k-tile halved, the
+ * k-tile quartered, the frequency tile halved, and the k-tile quartered with
+ * the frequency tile rounded down to a multiple of 48 (candidates equal to an
+ * earlier one are left out of the list).  dmft_batched_set_tile_candidate(h,
+ * k) makes later plans take candidate k without timing the others (for
+ * reproducible profiles; an index past the plan's list, or -1, restores the
+ * timing; DMFT_EINVAL below -1); dmft_batched_tile_candidate returns the
+ * candidate of the current plan (-1 without a plan). */
+int dmft_batched_set_tile_candidate(dmft_handle h, int index);
+int dmft_batched_tile_candidate(dmft_handle h);
+
 /* Autotuner: times every compiled kernel variant of the three kinds (density
  * pass, trace pass, fused scalar adjoint) that fits this shape on the
  * handle's GPU, with a few frequency-tile sizes, after checking that each one

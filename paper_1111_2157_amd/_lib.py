@@ -19,6 +19,7 @@ EXPORTS = [
     "dmft_batched_graph_capture", "dmft_batched_graph_launch", "dmft_autotune", "dmft_variants",
     "dmft_set_variant", "dmft_get_variant", "dmft_timing", "dmft_batched_set_form", "dmft_batched_form",
     "dmft_batched_classes", "dmft_batched_concurrent", "dmft_batched_set_concurrent",
+    "dmft_batched_tile_candidate", "dmft_batched_set_tile_candidate",
     "dmft_hybridization", "dmft_pole_workspace_size", "dmft_pole_eig", "dmft_pole_sweeps",
     "dmft_pole_density", "dmft_pole_find_mu", "dmft_pole_dos", "dmft_pole_energy", "dmft_hubbard1",
     "dmft_sigma_from_poles", "dmft_hubbard1_poles",
@@ -103,6 +104,8 @@ def load():
         "dmft_batched_classes": ([P, I, P, P, P, P], I),
         "dmft_batched_concurrent": ([P], I),
         "dmft_batched_set_concurrent": ([P, I], I),
+        "dmft_batched_tile_candidate": ([P], I),
+        "dmft_batched_set_tile_candidate": ([P, I], I),
         "density_matrix_noalloc": ([P, lp, sp, D, I, P, P, P, P, P], I),
         "dmft_hybridization": ([P, lp, sp, D, P, P, P, P, S, P], I),
         "dmft_timing": ([P, I, C.POINTER(D), C.POINTER(C.c_int64)], I),

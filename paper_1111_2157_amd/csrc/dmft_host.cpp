@@ -97,6 +97,8 @@ struct dmft_handle_s {
   std::vector<hipStream_t> b_side;
   bool b_concurrent = true;  // else the classes run one after another on the pass's stream (plan's choice)
   int b_conc_pref = -1;      // -1: the plan times both; 0 / 1: fixed
+  int b_tile_pref = -1;      // -1: the plan times every tile candidate; k >= 0: only candidate k
+  int b_tile_chosen = -1;    // candidate of the current plan's tiles (-1: the default, untimed)
   hipEvent_t b_fork = nullptr;
   std::vector<hipEvent_t> b_join;
   // kernel timing of the batched pass: one event pair around the whole Dyson
@@ -1405,7 +1407,7 @@ extern "C" {
 // with the k-tile halved and quartered (more, smaller items balance the class
 // kernels' last round better, at the price of more G_loc partials), then the
 // frequency tile halved, and the k-tile quartered with the frequency tile
-// rounded down and up to whole groups of 48 frequencies, or doubled.
+// rounded down to whole groups of 48 frequencies.
 std::vector<std::vector<Tile>> batched_tile_candidates(const std::vector<Tile>& base) {
   std::vector<std::vector<Tile>> out;
   for (int f : {1, 2, 4}) {
@@ -1426,27 +1428,14 @@ std::vector<std::vector<Tile>> batched_tile_candidates(const std::vector<Tile>& 
     t.wt = wt;
   }
   if (changed) out.push_back(c);
-  // the quarter k-tile with the frequency tile rounded down and up to a
-  // multiple of 48 (whole groups of the four-wavefront packed kernel, and of
-  // the 12, 8 and 4 frequencies of the others)
-  for (int up : {0, 1}) {
-    c = base;
-    changed = false;
-    for (auto& t : c) {
-      const int kt = std::max(1, t.kt / 4), wt = t.wt >= 96 ? (t.wt + (up ? 47 : 0)) / 48 * 48 : t.wt;
-      changed |= kt != t.kt && wt != t.wt;
-      t.kt = kt;
-      t.wt = wt;
-    }
-    if (changed) out.push_back(c);
-  }
-  // the quarter k-tile with twice the frequency tile: as many items as the
-  // half k-tile, and half the frequency-tile partials of the running sum
+  // the quarter k-tile with the frequency tile rounded down to a multiple of 48
+  // (whole groups of the four-wavefront packed kernel, and of the 12, 8 and 4
+  // frequencies of the others)
   c = base;
   changed = false;
   for (auto& t : c) {
-    const int kt = std::max(1, t.kt / 4), wt = 2 * t.wt;
-    changed |= kt != t.kt;
+    const int kt = std::max(1, t.kt / 4), wt = t.wt >= 96 ? t.wt / 48 * 48 : t.wt;
+    changed |= kt != t.kt && wt != t.wt;
     t.kt = kt;
     t.wt = wt;
   }
@@ -1488,6 +1477,7 @@ int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
     (void)hipGraphDestroy(h->graph);
     h->graph = nullptr;
   }
+  h->b_tile_chosen = -1;
   int r = batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, nullptr, false);
   if (r) return r;
   // Autotune the form of the step (dense inversion or low-rank) and the k- and
@@ -1505,10 +1495,14 @@ int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
   bool best_lr = true;
   // low-rank form first; the dense form's other tiles are timed only when its
   // first one comes within 1.5x of the best low-rank plan
+  const std::vector<std::vector<Tile>> cands = batched_tile_candidates(base_tiles);
+  int best_ci = -1;
   for (bool lr : {true, false}) {
     if (h->b_form_pref != DMFT_FORM_AUTO && lr != (h->b_form_pref == DMFT_FORM_LOWRANK)) continue;
     double first = -1.0;
-    for (const std::vector<Tile>& cand : batched_tile_candidates(base_tiles)) {
+    for (int ci = 0; ci < (int)cands.size(); ++ci) {
+      const std::vector<Tile>& cand = cands[ci];
+      if (h->b_tile_pref >= 0 && ci != h->b_tile_pref && h->b_tile_pref < (int)cands.size()) continue;
       if (!lr && first > 1.5 * best_lowrank) break;
       std::vector<Layout> Ls;
       std::vector<size_t> bs;
@@ -1539,10 +1533,12 @@ int dmft_batched_plan(dmft_handle h, int n_iter, const dmft_lattice* const* lat,
         best = ms;
         best_tiles = cand;
         best_lr = lr;
+        best_ci = ci;
       }
     }
   }
   r = batched_build(h, n_iter, lat, sig, tail_order, ws, ws_bytes, stream, &best_tiles, best_lr);
+  h->b_tile_chosen = r ? -1 : best_ci;
   if (r) return r;
   // class kernels concurrently on side streams or one after another: the
   // overlap fills each class's tail but makes the classes share the CUs, so
@@ -1664,6 +1660,18 @@ int dmft_batched_set_concurrent(dmft_handle h, int mode) {
 int dmft_batched_concurrent(dmft_handle h) {
   if (!h || h->iters.empty() || !h->b_lowrank) return -1;
   return h->b_concurrent ? 1 : 0;
+}
+
+int dmft_batched_set_tile_candidate(dmft_handle h, int index) {
+  if (!h) return DMFT_EINVAL;
+  if (index < -1) return fail(h, DMFT_EINVAL, "tile candidate %d", index);
+  h->b_tile_pref = index;
+  return DMFT_OK;
+}
+
+int dmft_batched_tile_candidate(dmft_handle h) {
+  if (!h || h->iters.empty()) return -1;
+  return h->b_tile_chosen;
 }
 
 int dmft_batched_form(dmft_handle h) {

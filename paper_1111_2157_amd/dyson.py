@@ -292,6 +292,15 @@ class Context:
         another, -1 (default) whichever the plan times faster."""
         check(self.h, self.lib.dmft_batched_set_concurrent(self.h, int(mode)))
 
+    def batched_set_tile_candidate(self, index: int) -> None:
+        """Tiles of later batched plans: candidate `index` of the plan's list
+        without timing the others, or -1 (default) the fastest of all."""
+        check(self.h, self.lib.dmft_batched_set_tile_candidate(self.h, int(index)))
+
+    def batched_tile_candidate(self) -> int:
+        """Tile candidate of the current batched plan (-1 without a plan)."""
+        return int(self.lib.dmft_batched_tile_candidate(self.h))
+
     def batched_concurrent(self) -> int:
         """1 if the class kernels of the low-rank batched plan run concurrently,
         0 if one after another, -1 without such a plan."""

@@ -143,3 +143,39 @@ def test_batched_class_launch_orders_agree():
     with pytest.raises(Exception):
         ctx.batched_set_concurrent(2)
     ctx.close()
+
+
+def test_batched_tile_candidate_choice():
+    """dmft_batched_set_tile_candidate: candidate 0 (the default tiles) is taken
+    without timing the others and reported back, and the pass matches the
+    oracle; an index past the plan's list restores the timing; an index below
+    -1 is refused."""
+    import torch
+    from paper_1111_2157_amd._lib import DmftError
+    from paper_1111_2157_amd.dyson import FORM_LOWRANK, Context, Lattice, SelfEnergy
+
+    wl = synth.batched(nk=10, nb_lo=14, nb_hi=64, nw=24, n_iter=2)
+    lats = [Lattice.from_host(l) for l in wl.lattices]
+    sigs = [SelfEnergy.from_host(s) for s in wl.sigmas]
+    ctx = Context(0)
+    ctx.batched_set_form(FORM_LOWRANK)
+    assert ctx.batched_tile_candidate() == -1
+    with pytest.raises(DmftError):
+        ctx.batched_set_tile_candidate(-2)
+    mus = [0.05, -0.15]
+    for pick in (0, 99):
+        print("tile candidate", pick, flush=True)
+        ctx.batched_set_tile_candidate(pick)
+        ctx.batched_plan(lats, sigs, 2)
+        got = ctx.batched_tile_candidate()
+        assert got == 0 if pick == 0 else got >= 0
+        mu_dev = torch.as_tensor(mus, dtype=torch.float64, device="cuda")
+        nks, gls = ctx.batched_outputs()
+        ctx.batched_pass(mu_dev, nks, gls)
+        torch.cuda.synchronize()
+        ctx.batched_sync_status()
+        for s in range(2):
+            lat, sig = wl.lattices[s], wl.sigmas[s]
+            assert_nk_parity(_split(nks[s].cpu().numpy(), lat), lat, sig, mus[s])
+            assert_gloc_parity(gls[s].cpu().numpy(), lat, sig, mus[s])
+    ctx.close()
