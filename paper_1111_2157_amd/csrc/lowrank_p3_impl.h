@@ -35,7 +35,11 @@
 // Frequencies past the tile's end repeat its last one in stages 0-2 (so every
 // inversion is of a valid matrix) and enter stage 3 with d = 0, which removes
 // them from Q and from the running sum.  64-band windows run the same steps on
-// four wavefronts (lr_p3_quad_tile, below).
+// four wavefronts (lr_p3_quad_tile, below).  Both kernels also carry the
+// partial-fraction form of the running sum (PF, on the k-points where every
+// band has at most one close partner; see p3q_pf_step below and
+// lowrank_pair_impl.h): stage 3 then forms P = S^dag R and Q = R S of each slot
+// instead of the nb x nb update.
 #pragma once
 
 #include "lowrank_impl.h"
