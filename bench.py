@@ -59,14 +59,14 @@ TRAFFIC = {
      ((32, 5, 5256), (32, 14, 5256), (48, 5, 6552), (48, 14, 6552), (64, 5, 6660), (64, 14, 6660))): {
         "bytes": 244.49e9,  # FETCH 109.96 GB + WRITE 134.52 GB
         "profile": "profiles/batched_cfg4.md",
-        "sources_sha256": "f18d62a695e1c1315a88c77ca24f04fd2f37be64be16e224ebbc954a9edd2b96",
+        "sources_sha256": "de41587efc8a209589a8d114de9e1f41446dd861fb72014a234b37fdaca0f207",
     },
     # the plan's quarter k-tile with the default frequency tile of 256
     ("batched-Nk4096-Nb20..64-x8-Nw2048", "low-rank",
      ((32, 5, 4672), (32, 14, 4672), (48, 5, 5824), (48, 14, 5824), (64, 5, 5920), (64, 14, 5920))): {
         "bytes": 243.15e9,  # FETCH 110.09 GB + WRITE 133.06 GB
         "profile": "profiles/batched_cfg4.md",
-        "sources_sha256": "f18d62a695e1c1315a88c77ca24f04fd2f37be64be16e224ebbc954a9edd2b96",
+        "sources_sha256": "de41587efc8a209589a8d114de9e1f41446dd861fb72014a234b37fdaca0f207",
     },
 }
 
